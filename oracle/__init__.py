@@ -1,0 +1,169 @@
+"""TEST INFRASTRUCTURE ONLY: ctypes front end of the CPU oracle (``apt_oracle.c``).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The GPU library never imports it, and it imports
+nothing from the GPU library.  Arrays are numpy, host memory.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libaptoracle.so")
+ANY = 255
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle: plain C, -O2, no contraction, no fast-math, OpenMP."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                               "-fPIC", "-shared", "-std=c11", "-D_DEFAULT_SOURCE",
+                               os.path.join(_HERE, "apt_oracle.c"), "-o", tmp, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+_p = ctypes.c_void_p
+_i32, _i64, _u64, _f32, _f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float, ctypes.c_double
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        sig = {
+            "orc_d2f": ([_p, _p], _f32),
+            "orc_D2": ([_p, _p], _f64),
+            "orc_edges2": ([_f32, _i32, _p], None),
+            "orc_bin_of": ([_f64, _p, _i32], _i32),
+            "orc_select_targets": ([_i64, _p, _p, _i32, _f32, _p], _i64),
+            "orc_rdf_brute": ([_p, _p, _p, _i64, _i32, _i32, _f32, _f32, _i32, _p], None),
+            "orc_rdf_grid": ([_p, _p, _p, _i64, _i32, _i32, _f32, _f32, _i32, _p], None),
+            "orc_knn_brute": ([_p, _p, _p, _i64, _i32, _i32, _f32, _i32, _f32, _p, _p, _p, _f32, _i32, _p], _i64),
+            "orc_knn_grid": ([_p, _p, _p, _i64, _i32, _i32, _f32, _i32, _f32, _p, _p, _p, _f32, _i32, _p], _i64),
+            "orc_splitmix64": ([_u64, _u64], _u64),
+            "orc_permute_labels": ([_p, _i64, _u64, _p], None),
+            "orc_smooth_fwd": ([_p, _p, _p, _i64, _i32, _i32, _f32, _f32, _i32, _f32, _f64, _p], None),
+            "orc_smooth_bwd": ([_p, _p, _p, _i64, _i32, _i32, _f32, _f32, _i32, _f32, _f64, _p, _p, _p], None),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _cloud(xyz, lab, d_bnd):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float32).reshape(-1, 3)
+    lab = np.ascontiguousarray(lab, dtype=np.uint8).reshape(-1)
+    assert lab.shape[0] == xyz.shape[0]
+    if d_bnd is not None:
+        d_bnd = np.ascontiguousarray(d_bnd, dtype=np.float32).reshape(-1)
+        assert d_bnd.shape[0] == xyz.shape[0]
+    return xyz, lab, d_bnd
+
+
+def d2f(a, b) -> float:
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    b = np.ascontiguousarray(b, dtype=np.float32)
+    return _load().orc_d2f(a.ctypes.data, b.ctypes.data)
+
+
+def D2(a, b) -> float:
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    b = np.ascontiguousarray(b, dtype=np.float32)
+    return _load().orc_D2(a.ctypes.data, b.ctypes.data)
+
+
+def edges2(r_max: float, n_bins: int) -> np.ndarray:
+    E2 = np.empty(n_bins + 1, dtype=np.float64)
+    _load().orc_edges2(r_max, n_bins, E2.ctypes.data)
+    return E2
+
+
+def bin_of(D2v: float, E2: np.ndarray) -> int:
+    E2 = np.ascontiguousarray(E2, dtype=np.float64)
+    return _load().orc_bin_of(D2v, E2.ctypes.data, len(E2) - 1)
+
+
+def select_targets(lab, d_bnd, A: int, d_srf: float) -> np.ndarray:
+    lab = np.ascontiguousarray(lab, dtype=np.uint8)
+    if d_bnd is not None:
+        d_bnd = np.ascontiguousarray(d_bnd, dtype=np.float32)
+    out = np.empty(len(lab), dtype=np.int64)
+    t = _load().orc_select_targets(len(lab), lab.ctypes.data, _ptr(d_bnd), A, d_srf, out.ctypes.data)
+    return out[:t].copy()
+
+
+def rdf(xyz, lab, d_bnd, A: int, B: int, d_srf: float, r_max: float, n_bins: int,
+        method: str = "grid") -> np.ndarray:
+    """Ordered-pair counts per bin (uint64 [n_bins])."""
+    xyz, lab, d_bnd = _cloud(xyz, lab, d_bnd)
+    hist = np.zeros(n_bins, dtype=np.uint64)
+    f = _load().orc_rdf_grid if method == "grid" else _load().orc_rdf_brute
+    f(xyz.ctypes.data, lab.ctypes.data, _ptr(d_bnd), xyz.shape[0], A, B, d_srf, r_max, n_bins,
+      hist.ctypes.data)
+    return hist
+
+
+def knn(xyz, lab, d_bnd, A: int, B: int, d_srf: float, k: int, r_knn_max: float = float("inf"),
+        kb_rmax: float = 5.0, kb_nbins: int = 5000, method: str = "grid", want_hist: bool = True):
+    """(target_id int64 [T], dist float32 [T,k], nbr_id int64 [T,k], knn_hist uint64 [kb_nbins+1] or None)."""
+    xyz, lab, d_bnd = _cloud(xyz, lab, d_bnd)
+    n = xyz.shape[0]
+    T = int((select_targets(lab, d_bnd, A, d_srf)).shape[0])
+    tid = np.empty(max(T, 1), dtype=np.int64)
+    dist = np.empty((max(T, 1), k), dtype=np.float32)
+    nid = np.empty((max(T, 1), k), dtype=np.int64)
+    hist = np.zeros(kb_nbins + 1, dtype=np.uint64) if want_hist else None
+    f = _load().orc_knn_grid if method == "grid" else _load().orc_knn_brute
+    t = f(xyz.ctypes.data, lab.ctypes.data, _ptr(d_bnd), n, A, B, d_srf, k, r_knn_max,
+          tid.ctypes.data, dist.ctypes.data, nid.ctypes.data, kb_rmax, kb_nbins, _ptr(hist))
+    assert t == T
+    return tid[:T], dist[:T], nid[:T], hist
+
+
+def splitmix64(seed: int, i: int) -> int:
+    return int(_load().orc_splitmix64(seed, i))
+
+
+def permute_labels(lab, seed: int) -> np.ndarray:
+    lab = np.ascontiguousarray(lab, dtype=np.uint8)
+    out = np.empty_like(lab)
+    _load().orc_permute_labels(lab.ctypes.data, len(lab), seed, out.ctypes.data)
+    return out
+
+
+def smooth_fwd(xyz, lab, d_bnd, A: int, B: int, d_srf: float, r_max: float, n_bins: int,
+               sigma: float, s: float = 1.0) -> np.ndarray:
+    xyz, lab, d_bnd = _cloud(xyz, lab, d_bnd)
+    h = np.zeros(n_bins, dtype=np.float64)
+    _load().orc_smooth_fwd(xyz.ctypes.data, lab.ctypes.data, _ptr(d_bnd), xyz.shape[0], A, B, d_srf,
+                           r_max, n_bins, sigma, s, h.ctypes.data)
+    return h
+
+
+def smooth_bwd(xyz, lab, d_bnd, A: int, B: int, d_srf: float, r_max: float, n_bins: int,
+               sigma: float, s: float, grad_h):
+    """(grad_xyz float64 [n,3], grad_s float)."""
+    xyz, lab, d_bnd = _cloud(xyz, lab, d_bnd)
+    gh = np.ascontiguousarray(grad_h, dtype=np.float64)
+    assert gh.shape == (n_bins,)
+    g = np.zeros((xyz.shape[0], 3), dtype=np.float64)
+    gs = np.zeros(1, dtype=np.float64)
+    _load().orc_smooth_bwd(xyz.ctypes.data, lab.ctypes.data, _ptr(d_bnd), xyz.shape[0], A, B, d_srf,
+                           r_max, n_bins, sigma, s, gh.ctypes.data, g.ctypes.data, gs.ctypes.data)
+    return g, float(gs[0])

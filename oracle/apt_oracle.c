@@ -1,0 +1,629 @@
+/*
+ * apt_oracle.c -- TEST INFRASTRUCTURE ONLY: the CPU oracle.
+ *
+ * Plain definitions of what the spatial-statistics stage of the paper
+ * computes, written for a reader to check against the paper by eye.  Build
+ * with -O2 -ffp-contract=off (no fast-math): the distance expressions below
+ * are evaluated exactly as written.  Nothing here is shared with, or called
+ * by, the GPU library.
+ *
+ * The statistics (paper, Methods: "Descriptive, two-point spatial
+ * statistics, and clustering"; Supplementary: "Customized user defined batch
+ * processing queues"):
+ *   - a target ("central") ion is an ion of species A whose distance to the
+ *     specimen edge is at least d_srf (Methods: "Ion-to-edge distancing";
+ *     caption of the table of AM case-study tasks: "at least d_srf");
+ *   - neighbours are ions of species B other than the target itself; the
+ *     edge filter applies to targets only;
+ *   - kNN: the distances to each target's k-th nearest neighbours;
+ *   - RDF: counts of target-neighbour pairs per radial bin of a rectangular
+ *     transfer function r = [0, step, r_max];
+ *   - null model: the same statistics on a random permutation of the labels
+ *     (Supplementary: "Importance of high quality random number generators").
+ * Precision (Supplementary: "Implementation details"): positions are FP32;
+ * the RDF bin of a pair is decided on the FP64 squared distance of the two
+ * stored FP32 positions, the kNN order on one fixed FP32 expression with the
+ * original index as tie-break.
+ */
+#include "apt_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---------------------------------------------------------------------- */
+/* Distances                                                               */
+/* ---------------------------------------------------------------------- */
+
+/* FP32 squared distance: dx*dx, then two fused multiply-adds (dy, dz). */
+float orc_d2f(const float* a, const float* b) {
+    float dx = b[0] - a[0];
+    float dy = b[1] - a[1];
+    float dz = b[2] - a[2];
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
+/* FP64 squared distance of the two stored positions: ((dx^2 + dy^2) + dz^2). */
+double orc_D2(const float* a, const float* b) {
+    double dx = (double)b[0] - (double)a[0];
+    double dy = (double)b[1] - (double)a[1];
+    double dz = (double)b[2] - (double)a[2];
+    return ((dx * dx) + (dy * dy)) + (dz * dz);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Rectangular transfer function: bins [e_b, e_{b+1}), e_b = b*r_max/n     */
+/* ---------------------------------------------------------------------- */
+
+void orc_edges2(float r_max, int32_t n_bins, double* E2) {
+    for (int32_t b = 0; b <= n_bins; ++b) {
+        double e = ((double)b * (double)r_max) / (double)n_bins;
+        E2[b] = e * e;
+    }
+}
+
+int32_t orc_bin_of(double D2, const double* E2, int32_t n_bins) {
+    if (!(D2 < E2[n_bins])) return n_bins;
+    /* largest b with E2[b] <= D2 (E2[0] = 0 <= D2) */
+    int32_t lo = 0, hi = n_bins; /* invariant: E2[lo] <= D2 < E2[hi] */
+    while (hi - lo > 1) {
+        int32_t mid = lo + (hi - lo) / 2;
+        if (E2[mid] <= D2) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Eligibility                                                             */
+/* ---------------------------------------------------------------------- */
+
+static int is_species(uint8_t s, int32_t want) { return want == ORC_ANY || (int32_t)s == want; }
+
+static int is_target(int64_t i, const uint8_t* lab, const float* d_bnd, int32_t A, float d_srf) {
+    if (!is_species(lab[i], A)) return 0;
+    if (d_bnd && !(d_bnd[i] >= d_srf)) return 0; /* inclusive; NaN is never eligible */
+    return 1;
+}
+
+int64_t orc_select_targets(int64_t n, const uint8_t* lab, const float* d_bnd, int32_t A,
+                           float d_srf, int64_t* out_ids) {
+    int64_t t = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (is_target(i, lab, d_bnd, A, d_srf)) {
+            if (out_ids) out_ids[t] = i;
+            ++t;
+        }
+    return t;
+}
+
+/* ---------------------------------------------------------------------- */
+/* RDF, brute force: every target against every neighbour                 */
+/* ---------------------------------------------------------------------- */
+
+void orc_rdf_brute(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n, int32_t A,
+                   int32_t B, float d_srf, float r_max, int32_t n_bins, uint64_t* hist) {
+    double* E2 = (double*)malloc(sizeof(double) * (size_t)(n_bins + 1));
+    orc_edges2(r_max, n_bins, E2);
+    memset(hist, 0, sizeof(uint64_t) * (size_t)n_bins);
+    for (int64_t i = 0; i < n; ++i) {
+        if (!is_target(i, lab, d_bnd, A, d_srf)) continue;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i || !is_species(lab[j], B)) continue;
+            int32_t b = orc_bin_of(orc_D2(xyz + 3 * i, xyz + 3 * j), E2, n_bins);
+            if (b < n_bins) hist[b]++;
+        }
+    }
+    free(E2);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Uniform grid of the neighbour ions (oracle's own, counting sort)        */
+/* ---------------------------------------------------------------------- */
+
+typedef struct {
+    double lo[3];
+    double h;
+    int64_t dim[3];
+    int64_t* start; /* [ncell + 1] */
+    int64_t* item;  /* neighbour indices, cell by cell, ascending within a cell */
+    int64_t nitem;
+} ogrid;
+
+static int64_t ocell_axis(const ogrid* g, int a, double x) {
+    double f = floor((x - g->lo[a]) / g->h);
+    if (f < 0) return 0;
+    if (f > (double)(g->dim[a] - 1)) return g->dim[a] - 1;
+    return (int64_t)f;
+}
+
+/* coords: position of ion i on axis a (pos(i, a)); h_min: smallest cell edge. */
+static void ogrid_build(ogrid* g, int64_t n, const uint8_t* lab, int32_t B,
+                        double (*pos)(const void*, int64_t, int), const void* ctx, double h_min) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int64_t nb = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (!is_species(lab[j], B)) continue;
+        ++nb;
+        for (int a = 0; a < 3; ++a) {
+            double v = pos(ctx, j, a);
+            if (v < lo[a]) lo[a] = v;
+            if (v > hi[a]) hi[a] = v;
+        }
+    }
+    if (nb == 0)
+        for (int a = 0; a < 3; ++a) { lo[a] = 0; hi[a] = 0; }
+    double h = h_min;
+    /* bounded table: at most ~8 cells per neighbour ion */
+    for (;;) {
+        double cells = 1;
+        for (int a = 0; a < 3; ++a) cells *= floor((hi[a] - lo[a]) / h) + 1;
+        if (cells <= 8.0 * (double)nb + 64.0) break;
+        h *= 1.5;
+    }
+    int64_t ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        g->lo[a] = lo[a];
+        g->dim[a] = (int64_t)floor((hi[a] - lo[a]) / h) + 1;
+        ncell *= g->dim[a];
+    }
+    g->h = h;
+    g->start = (int64_t*)calloc((size_t)ncell + 1, sizeof(int64_t));
+    g->item = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nb > 0 ? nb : 1));
+    g->nitem = nb;
+    int64_t* cellof = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t j = 0; j < n; ++j) {
+        if (!is_species(lab[j], B)) { cellof[j] = -1; continue; }
+        int64_t c[3];
+        for (int a = 0; a < 3; ++a) c[a] = ocell_axis(g, a, pos(ctx, j, a));
+        cellof[j] = (c[2] * g->dim[1] + c[1]) * g->dim[0] + c[0];
+        g->start[cellof[j] + 1]++;
+    }
+    for (int64_t q = 0; q < ncell; ++q) g->start[q + 1] += g->start[q];
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)ncell);
+    memcpy(fill, g->start, sizeof(int64_t) * (size_t)ncell);
+    for (int64_t j = 0; j < n; ++j)
+        if (cellof[j] >= 0) g->item[fill[cellof[j]]++] = j;
+    free(fill);
+    free(cellof);
+}
+
+static void ogrid_free(ogrid* g) {
+    free(g->start);
+    free(g->item);
+}
+
+static double pos_plain(const void* ctx, int64_t j, int a) { return (double)((const float*)ctx)[3 * j + a]; }
+
+/* ---------------------------------------------------------------------- */
+/* RDF on the grid: cells of edge >= r_max, the 27 surrounding cells       */
+/* ---------------------------------------------------------------------- */
+
+void orc_rdf_grid(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n, int32_t A,
+                  int32_t B, float d_srf, float r_max, int32_t n_bins, uint64_t* hist) {
+    double* E2 = (double*)malloc(sizeof(double) * (size_t)(n_bins + 1));
+    orc_edges2(r_max, n_bins, E2);
+    ogrid g;
+    ogrid_build(&g, n, lab, B, pos_plain, xyz, (double)r_max * (1.0 + 1e-6));
+    memset(hist, 0, sizeof(uint64_t) * (size_t)n_bins);
+#pragma omp parallel
+    {
+        /* one result buffer per thread, summed at the end */
+        uint64_t* loc = (uint64_t*)calloc((size_t)n_bins, sizeof(uint64_t));
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; ++i) {
+            if (!is_target(i, lab, d_bnd, A, d_srf)) continue;
+            const float* pi = xyz + 3 * i;
+            int64_t c[3];
+            for (int a = 0; a < 3; ++a) c[a] = ocell_axis(&g, a, (double)pi[a]);
+            for (int64_t z = c[2] - 1; z <= c[2] + 1; ++z) {
+                if (z < 0 || z >= g.dim[2]) continue;
+                for (int64_t y = c[1] - 1; y <= c[1] + 1; ++y) {
+                    if (y < 0 || y >= g.dim[1]) continue;
+                    for (int64_t x = c[0] - 1; x <= c[0] + 1; ++x) {
+                        if (x < 0 || x >= g.dim[0]) continue;
+                        int64_t cell = (z * g.dim[1] + y) * g.dim[0] + x;
+                        for (int64_t t = g.start[cell]; t < g.start[cell + 1]; ++t) {
+                            int64_t j = g.item[t];
+                            if (j == i) continue;
+                            int32_t b = orc_bin_of(orc_D2(pi, xyz + 3 * j), E2, n_bins);
+                            if (b < n_bins) loc[b]++;
+                        }
+                    }
+                }
+            }
+        }
+#pragma omp critical
+        for (int32_t b = 0; b < n_bins; ++b) hist[b] += loc[b];
+        free(loc);
+    }
+    ogrid_free(&g);
+    free(E2);
+}
+
+/* ---------------------------------------------------------------------- */
+/* kNN                                                                     */
+/* ---------------------------------------------------------------------- */
+
+/* Order key: FP32 squared distance bits (non-negative floats order like their
+ * bit patterns), then the neighbour's original index. */
+static uint64_t knn_key(float d2, int64_t j) {
+    uint32_t bits;
+    memcpy(&bits, &d2, sizeof bits);
+    return ((uint64_t)bits << 32) | (uint64_t)(uint32_t)j;
+}
+static float key_d2(uint64_t key) {
+    uint32_t bits = (uint32_t)(key >> 32);
+    float f;
+    memcpy(&f, &bits, sizeof f);
+    return f;
+}
+
+/* Keep the k smallest keys seen so far, ascending (insertion). */
+static void topk_insert(uint64_t* best, int32_t* cnt, int32_t k, uint64_t key) {
+    if (*cnt == k && key >= best[k - 1]) return;
+    int32_t p = *cnt < k ? (*cnt)++ : k - 1;
+    while (p > 0 && best[p - 1] > key) {
+        best[p] = best[p - 1];
+        --p;
+    }
+    best[p] = key;
+}
+
+static void knn_emit(const float* xyz, int64_t i, int64_t row, const uint64_t* best, int32_t cnt,
+                     int32_t k, int64_t* target_id, float* dist, int64_t* nbr_id, const double* KE2,
+                     int32_t kb_nbins, uint64_t* knn_hist) {
+    target_id[row] = i;
+    for (int32_t m = 0; m < k; ++m) {
+        if (m < cnt) {
+            dist[row * k + m] = sqrtf(key_d2(best[m]));
+            nbr_id[row * k + m] = (int64_t)(uint32_t)best[m];
+        } else {
+            dist[row * k + m] = INFINITY;
+            nbr_id[row * k + m] = -1;
+        }
+    }
+    if (knn_hist) {
+        int32_t b = kb_nbins;
+        if (cnt == k) b = orc_bin_of(orc_D2(xyz + 3 * i, xyz + 3 * (uint32_t)best[k - 1]), KE2, kb_nbins);
+#pragma omp atomic
+        knn_hist[b]++;
+    }
+}
+
+static double* knn_hist_setup(float kb_rmax, int32_t kb_nbins, uint64_t* knn_hist) {
+    if (!knn_hist) return NULL;
+    double* KE2 = (double*)malloc(sizeof(double) * (size_t)(kb_nbins + 1));
+    orc_edges2(kb_rmax, kb_nbins, KE2);
+    memset(knn_hist, 0, sizeof(uint64_t) * (size_t)(kb_nbins + 1));
+    return KE2;
+}
+
+int64_t orc_knn_brute(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n,
+                      int32_t A, int32_t B, float d_srf, int32_t k, float r_knn_max,
+                      int64_t* target_id, float* dist, int64_t* nbr_id, float kb_rmax,
+                      int32_t kb_nbins, uint64_t* knn_hist) {
+    double* KE2 = knn_hist_setup(kb_rmax, kb_nbins, knn_hist);
+    float rk2 = r_knn_max * r_knn_max;
+    uint64_t* best = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)k);
+    int64_t row = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!is_target(i, lab, d_bnd, A, d_srf)) continue;
+        int32_t cnt = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i || !is_species(lab[j], B)) continue;
+            float d2 = orc_d2f(xyz + 3 * i, xyz + 3 * j);
+            if (!(d2 <= rk2)) continue;
+            topk_insert(best, &cnt, k, knn_key(d2, j));
+        }
+        knn_emit(xyz, i, row, best, cnt, k, target_id, dist, nbr_id, KE2, kb_nbins, knn_hist);
+        ++row;
+    }
+    free(best);
+    free(KE2);
+    return row;
+}
+
+/* Grid kNN: examine cells in growing cubes around the target's cell; the
+ * k-th key is final once its distance is below the distance from the target
+ * to the outside of the examined cube. */
+int64_t orc_knn_grid(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n,
+                     int32_t A, int32_t B, float d_srf, int32_t k, float r_knn_max,
+                     int64_t* target_id, float* dist, int64_t* nbr_id, float kb_rmax,
+                     int32_t kb_nbins, uint64_t* knn_hist) {
+    double* KE2 = knn_hist_setup(kb_rmax, kb_nbins, knn_hist);
+    float rk2 = r_knn_max * r_knn_max;
+    int64_t T = orc_select_targets(n, lab, d_bnd, A, d_srf, NULL);
+    int64_t* tid = (int64_t*)malloc(sizeof(int64_t) * (size_t)(T > 0 ? T : 1));
+    orc_select_targets(n, lab, d_bnd, A, d_srf, tid);
+    int64_t nb = 0;
+    for (int64_t j = 0; j < n; ++j) nb += is_species(lab[j], B);
+    /* cell edge ~ the spacing that holds a few neighbours per cell */
+    double vol = 1.0;
+    {
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int64_t j = 0; j < n; ++j)
+            if (is_species(lab[j], B))
+                for (int a = 0; a < 3; ++a) {
+                    if (xyz[3 * j + a] < lo[a]) lo[a] = xyz[3 * j + a];
+                    if (xyz[3 * j + a] > hi[a]) hi[a] = xyz[3 * j + a];
+                }
+        for (int a = 0; a < 3; ++a) vol *= (nb > 0 ? hi[a] - lo[a] : 0.0) + 1e-3;
+    }
+    double h0 = cbrt(vol * (double)(k > 4 ? k : 4) / (double)(nb > 0 ? nb : 1));
+    if (h0 < 1e-3) h0 = 1e-3;
+    ogrid g;
+    ogrid_build(&g, n, lab, B, pos_plain, xyz, h0);
+#pragma omp parallel
+    {
+        uint64_t* best = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)k);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t row = 0; row < T; ++row) {
+            int64_t i = tid[row];
+            const float* pi = xyz + 3 * i;
+            int64_t c[3];
+            for (int a = 0; a < 3; ++a) c[a] = ocell_axis(&g, a, (double)pi[a]);
+            int32_t cnt = 0;
+            for (int64_t s = 0;; ++s) {
+                /* cells on the surface of the cube of half-width s */
+                for (int64_t z = c[2] - s; z <= c[2] + s; ++z) {
+                    if (z < 0 || z >= g.dim[2]) continue;
+                    for (int64_t y = c[1] - s; y <= c[1] + s; ++y) {
+                        if (y < 0 || y >= g.dim[1]) continue;
+                        for (int64_t x = c[0] - s; x <= c[0] + s; ++x) {
+                            if (x < 0 || x >= g.dim[0]) continue;
+                            int64_t ax = x - c[0], ay = y - c[1], az = z - c[2];
+                            int64_t cheb = llabs(ax);
+                            if (llabs(ay) > cheb) cheb = llabs(ay);
+                            if (llabs(az) > cheb) cheb = llabs(az);
+                            if (cheb != s) continue;
+                            int64_t cell = (z * g.dim[1] + y) * g.dim[0] + x;
+                            for (int64_t t = g.start[cell]; t < g.start[cell + 1]; ++t) {
+                                int64_t j = g.item[t];
+                                if (j == i) continue;
+                                float d2 = orc_d2f(pi, xyz + 3 * j);
+                                if (!(d2 <= rk2)) continue;
+                                topk_insert(best, &cnt, k, knn_key(d2, j));
+                            }
+                        }
+                    }
+                }
+                /* distance from the target to the outside of the examined cube;
+                 * a side that reaches the edge of the grid has nothing beyond it */
+                double cover = INFINITY;
+                int whole = 1;
+                for (int a = 0; a < 3; ++a) {
+                    if (c[a] - s > 0) {
+                        double w = (double)pi[a] - (g.lo[a] + (double)(c[a] - s) * g.h);
+                        if (w < cover) cover = w;
+                        whole = 0;
+                    }
+                    if (c[a] + s < g.dim[a] - 1) {
+                        double w = (g.lo[a] + (double)(c[a] + s + 1) * g.h) - (double)pi[a];
+                        if (w < cover) cover = w;
+                        whole = 0;
+                    }
+                }
+                if (whole) break;
+                if (cover > 0 && (double)r_knn_max < cover * (1.0 - 1e-5)) break;
+                if (cnt == k && cover > 0 && (double)key_d2(best[k - 1]) < cover * cover * (1.0 - 1e-5))
+                    break;
+            }
+            knn_emit(xyz, i, row, best, cnt, k, target_id, dist, nbr_id, KE2, kb_nbins, knn_hist);
+        }
+        free(best);
+    }
+    ogrid_free(&g);
+    free(tid);
+    free(KE2);
+    return T;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Null model: a random permutation of the labels                          */
+/* ---------------------------------------------------------------------- */
+
+/* i-th output (i = 0, 1, ...) of SplitMix64 started from state `seed`
+ * (Steele, Lea, Flood, "Fast splittable pseudorandom number generators",
+ * OOPSLA 2014): the state advances by the golden gamma, then is mixed. */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+typedef struct {
+    uint64_t key;
+    int64_t idx;
+} keyed;
+
+static int keyed_cmp(const void* a, const void* b) {
+    const keyed* x = (const keyed*)a;
+    const keyed* y = (const keyed*)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->idx < y->idx ? -1 : (x->idx > y->idx);
+}
+
+/* pi = ascending order of the keys (ties by index); out[i] = lab[pi(i)]. */
+void orc_permute_labels(const uint8_t* lab, int64_t n, uint64_t seed, uint8_t* out) {
+    keyed* a = (keyed*)malloc(sizeof(keyed) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        a[i].key = orc_splitmix64(seed, (uint64_t)i);
+        a[i].idx = i;
+    }
+    qsort(a, (size_t)n, sizeof(keyed), keyed_cmp);
+    for (int64_t i = 0; i < n; ++i) out[i] = lab[a[i].idx];
+    free(a);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Gaussian-smoothed RDF (FP64) and its adjoint                            */
+/* ---------------------------------------------------------------------- */
+/* Each pair adds to bin b the Gaussian mass (std sigma, centred on the pair
+ * distance D) that falls in [e_b, e_{b+1}); only bins meeting
+ * (D - 6 sigma, D + 6 sigma) and pairs with D < r_max + 6 sigma take part.
+ * Coordinates are (x, y, s*z); d_bnd is not rescaled. */
+
+static double Phi(double t) { return 0.5 * erfc(-t / M_SQRT2); }   /* lower tail */
+static double Qtail(double t) { return 0.5 * erfc(t / M_SQRT2); }  /* upper tail */
+static double phi(double t) { return exp(-0.5 * t * t) / sqrt(2.0 * M_PI); }
+
+static double bin_mass(double lo, double hi) {
+    /* P(lo <= Z < hi), Z standard normal, from the tail that does not cancel */
+    if (lo >= 0) return Qtail(lo) - Qtail(hi);
+    if (hi <= 0) return Phi(hi) - Phi(lo);
+    return 1.0 - Qtail(hi) - Phi(lo);
+}
+
+typedef struct {
+    const float* xyz;
+    double s;
+} scaled_ctx;
+
+static double pos_scaled(const void* ctx, int64_t j, int a) {
+    const scaled_ctx* c = (const scaled_ctx*)ctx;
+    double v = (double)c->xyz[3 * j + a];
+    return a == 2 ? c->s * v : v;
+}
+
+/* Calls visit(i, j, dX, dY, dZ, D, user) for every target i and neighbour j
+ * with D < r_max + 6 sigma in scaled coordinates (serial, ascending i). */
+typedef void (*pair_visitor)(int64_t i, int64_t j, double dX, double dY, double dZ, double D,
+                             void* user);
+
+static void smooth_pairs(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n,
+                         int32_t A, int32_t B, float d_srf, double cut, double s,
+                         pair_visitor visit, void* user) {
+    scaled_ctx ctx = {xyz, s};
+    ogrid g;
+    ogrid_build(&g, n, lab, B, pos_scaled, &ctx, cut * (1.0 + 1e-6));
+    for (int64_t i = 0; i < n; ++i) {
+        if (!is_target(i, lab, d_bnd, A, d_srf)) continue;
+        double P[3];
+        int64_t c[3];
+        for (int a = 0; a < 3; ++a) {
+            P[a] = pos_scaled(&ctx, i, a);
+            c[a] = ocell_axis(&g, a, P[a]);
+        }
+        for (int64_t z = c[2] - 1; z <= c[2] + 1; ++z) {
+            if (z < 0 || z >= g.dim[2]) continue;
+            for (int64_t y = c[1] - 1; y <= c[1] + 1; ++y) {
+                if (y < 0 || y >= g.dim[1]) continue;
+                for (int64_t x = c[0] - 1; x <= c[0] + 1; ++x) {
+                    if (x < 0 || x >= g.dim[0]) continue;
+                    int64_t cell = (z * g.dim[1] + y) * g.dim[0] + x;
+                    for (int64_t t = g.start[cell]; t < g.start[cell + 1]; ++t) {
+                        int64_t j = g.item[t];
+                        if (j == i) continue;
+                        double dX = pos_scaled(&ctx, j, 0) - P[0];
+                        double dY = pos_scaled(&ctx, j, 1) - P[1];
+                        double dZ = pos_scaled(&ctx, j, 2) - P[2];
+                        double D = sqrt(((dX * dX) + (dY * dY)) + (dZ * dZ));
+                        if (D < cut) visit(i, j, dX, dY, dZ, D, user);
+                    }
+                }
+            }
+        }
+    }
+    ogrid_free(&g);
+}
+
+typedef struct {
+    const double* e;
+    int32_t n_bins;
+    double sigma;
+    double* h;
+    const double* grad_h;
+    double* grad;
+    double grad_s;
+    double s;
+    const float* xyz;
+} smooth_state;
+
+/* window of bins [*b0, *b1] that meet (D - 6 sigma, D + 6 sigma) */
+static void window(const smooth_state* st, double D, int32_t* b0, int32_t* b1) {
+    double w = 6.0 * st->sigma;
+    *b0 = st->n_bins;
+    *b1 = -1;
+    for (int32_t b = 0; b < st->n_bins; ++b)
+        if (st->e[b + 1] > D - w && st->e[b] < D + w) {
+            if (b < *b0) *b0 = b;
+            *b1 = b;
+        }
+}
+
+static void visit_fwd(int64_t i, int64_t j, double dX, double dY, double dZ, double D, void* user) {
+    (void)i; (void)j; (void)dX; (void)dY; (void)dZ;
+    smooth_state* st = (smooth_state*)user;
+    int32_t b0, b1;
+    window(st, D, &b0, &b1);
+    for (int32_t b = b0; b <= b1; ++b)
+        st->h[b] += bin_mass((st->e[b] - D) / st->sigma, (st->e[b + 1] - D) / st->sigma);
+}
+
+static void visit_bwd(int64_t i, int64_t j, double dX, double dY, double dZ, double D, void* user) {
+    smooth_state* st = (smooth_state*)user;
+    if (D == 0.0) return;
+    int32_t b0, b1;
+    window(st, D, &b0, &b1);
+    /* g = dL/dD = sum_b dL/dh_b * dw_b/dD, dw_b/dD = -(phi(c) - phi(a)) / sigma */
+    double g = 0.0;
+    for (int32_t b = b0; b <= b1; ++b) {
+        double a = (st->e[b] - D) / st->sigma, c = (st->e[b + 1] - D) / st->sigma;
+        g += st->grad_h[b] * (-(phi(c) - phi(a)) / st->sigma);
+    }
+    /* D = |p'_j - p'_i|; dD/dp'_j = u, dD/dp'_i = -u, u = (p'_j - p'_i)/D;
+     * z' = s z, so dL/dz = s dL/dz' and dD/ds = s (z_j - z_i)^2 / D */
+    double u[3] = {dX / D, dY / D, dZ / D};
+    for (int a = 0; a < 3; ++a) {
+        double f = a == 2 ? st->s : 1.0;
+        st->grad[3 * j + a] += g * u[a] * f;
+        st->grad[3 * i + a] -= g * u[a] * f;
+    }
+    double dz = (double)st->xyz[3 * j + 2] - (double)st->xyz[3 * i + 2];
+    st->grad_s += g * st->s * dz * dz / D;
+}
+
+static double* bin_edges(float r_max, int32_t n_bins) {
+    double* e = (double*)malloc(sizeof(double) * (size_t)(n_bins + 1));
+    for (int32_t b = 0; b <= n_bins; ++b) e[b] = ((double)b * (double)r_max) / (double)n_bins;
+    return e;
+}
+
+void orc_smooth_fwd(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n,
+                    int32_t A, int32_t B, float d_srf, float r_max, int32_t n_bins, float sigma,
+                    double s, double* h) {
+    smooth_state st;
+    memset(&st, 0, sizeof st);
+    st.e = bin_edges(r_max, n_bins);
+    st.n_bins = n_bins;
+    st.sigma = (double)sigma;
+    st.h = h;
+    st.s = s;
+    st.xyz = xyz;
+    memset(h, 0, sizeof(double) * (size_t)n_bins);
+    smooth_pairs(xyz, lab, d_bnd, n, A, B, d_srf, (double)r_max + 6.0 * (double)sigma, s, visit_fwd, &st);
+    free((void*)st.e);
+}
+
+void orc_smooth_bwd(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n,
+                    int32_t A, int32_t B, float d_srf, float r_max, int32_t n_bins, float sigma,
+                    double s, const double* grad_h, double* grad_xyz, double* grad_s) {
+    smooth_state st;
+    memset(&st, 0, sizeof st);
+    st.e = bin_edges(r_max, n_bins);
+    st.n_bins = n_bins;
+    st.sigma = (double)sigma;
+    st.grad_h = grad_h;
+    st.grad = grad_xyz;
+    st.s = s;
+    st.xyz = xyz;
+    memset(grad_xyz, 0, sizeof(double) * 3 * (size_t)n);
+    smooth_pairs(xyz, lab, d_bnd, n, A, B, d_srf, (double)r_max + 6.0 * (double)sigma, s, visit_bwd, &st);
+    *grad_s = st.grad_s;
+    free((void*)st.e);
+}

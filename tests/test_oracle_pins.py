@@ -1,0 +1,449 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test fixes one part of the oracle to the mathematics or to a published
+value: brute force on tiny inputs, exact lattice sums, Poisson closed forms,
+invariants and a library routine where the method reduces to one.  The
+paper prints no kNN or RDF values for its specimens (its result figures are
+not part of the text), so parity with the paper's own outputs is unpinned.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+AL, SC, SI, ANY = 0, 1, 2, 255
+
+
+def _read_table(name):
+    rows, meta = [], {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line:
+                continue
+            if line.startswith("#"):
+                parts = line[1:].split()
+                if len(parts) == 2:
+                    try:
+                        meta[parts[0]] = float(parts[1])
+                    except ValueError:
+                        pass
+                continue
+            rows.append(line.split())
+    return rows, meta
+
+
+# --------------------------------------------------------------------------
+# random numbers
+# --------------------------------------------------------------------------
+
+def test_splitmix64_published_outputs(orc):
+    rows, _ = _read_table("splitmix64_seed0.txt")
+    for i, hx in rows:
+        assert orc.splitmix64(0, int(i)) == int(hx, 16)
+
+
+def test_permutation_is_uniform_on_four_items(orc):
+    # every one of the 24 orderings of 4 distinct labels is equally likely
+    lab = np.array([0, 1, 2, 3], dtype=np.uint8)
+    counts = {}
+    R = 24 * 400
+    for r in range(R):
+        out = orc.permute_labels(lab, 1000 + r)
+        counts[tuple(out)] = counts.get(tuple(out), 0) + 1
+    assert len(counts) == 24
+    obs = np.array(list(counts.values()), dtype=float)
+    chi2 = ((obs - R / 24) ** 2 / (R / 24)).sum()
+    assert stats.chi2.sf(chi2, 23) > 1e-4
+
+
+def test_permutation_preserves_species_and_moves_labels(orc, synth):
+    xyz, lab, d = synth.box240k().generate()
+    out = orc.permute_labels(lab, 7)
+    assert np.array_equal(np.bincount(out, minlength=3), np.bincount(lab, minlength=3))
+    # a uniform permutation keeps a label in place with probability ~ its fraction
+    same = (out == lab).mean()
+    p = (np.bincount(lab) / len(lab)) ** 2
+    assert abs(same - p.sum()) < 5 * math.sqrt(p.sum() / len(lab)) + 1e-3
+    assert not np.array_equal(out, orc.permute_labels(lab, 8))
+
+
+def test_permutation_mean_matches_exact_null_expectation(orc, synth):
+    # E_perm[H_b(A->B)] = H_b(eligible -> any) * N_A (N_B - d_AB) / (N (N-1)),
+    # eligibility on positions only (no d_bnd here)
+    xyz, lab, d = synth.Specimen(shape="box", L=(8.0, 8.0, 8.0), n=6000, seed=3, p_m_sc=0.1,
+                                 p_m_si=0.05).generate()
+    n = len(lab)
+    NA, NB = (lab == SC).sum(), (lab == AL).sum()
+    base = orc.rdf(xyz, lab, None, ANY, ANY, 0.0, 1.0, 10).astype(float)
+    expect = base * NA * NB / (n * (n - 1.0))
+    reps = np.array([orc.rdf(xyz, orc.permute_labels(lab, 100 + r), None, SC, AL, 0.0, 1.0, 10)
+                     for r in range(48)], dtype=float)
+    m, sd = reps.mean(0), reps.std(0, ddof=1)
+    z = (m - expect) / (sd / math.sqrt(len(reps)) + 1e-9)
+    assert np.all(np.abs(z) < 5.0), z
+
+
+# --------------------------------------------------------------------------
+# distances and bins
+# --------------------------------------------------------------------------
+
+def test_distances_exact_cases(orc):
+    a = np.array([1.0, 2.0, 3.0], np.float32)
+    b = np.array([4.0, 6.0, 3.0], np.float32)  # 3-4-5
+    assert orc.D2(a, b) == 25.0 and orc.d2f(a, b) == 25.0
+    c = np.array([1.0, 2.0, 15.0], np.float32)  # 0,0,12
+    assert orc.D2(a, c) == 144.0
+    # FP64 distance of the stored FP32 values, not of their decimal spelling
+    p = np.array([0.1, 0.0, 0.0], np.float32)
+    q = np.array([0.0, 0.0, 0.0], np.float32)
+    assert orc.D2(p, q) == float(np.float64(np.float32(0.1))) ** 2
+
+
+def test_edges_and_half_open_bins(orc):
+    E2 = orc.edges2(2.0, 200)
+    assert E2[0] == 0.0 and E2[200] == 4.0 and E2[50] == 0.25 and E2[100] == 1.0
+    assert orc.bin_of(0.0, E2) == 0
+    assert orc.bin_of(0.25, E2) == 50          # lower edge belongs to the bin
+    assert orc.bin_of(np.nextafter(0.25, 0), E2) == 49
+    assert orc.bin_of(4.0, E2) == 200          # r = r_max is outside
+    assert orc.bin_of(np.nextafter(4.0, 0), E2) == 199
+
+
+def _pair_cloud(d):
+    xyz = np.array([[10.0, 10.0, 10.0], [10.0 + d, 10.0, 10.0]], np.float32)
+    return xyz, np.array([SC, SC], np.uint8)
+
+
+@pytest.mark.parametrize("d,expect", [
+    (0.5, 50), (1.0, 100), (1.5, 150),                 # representable edges
+    (0.5 + 2e-6, 50), (0.5 - 2e-6, 49), (1.0 - 1e-6, 99), (1.0 + 1e-6, 100),
+    (0.25, 25), (2.0, None), (2.0 - 2e-6, 199),
+])
+def test_pairs_at_bin_edges(orc, d, expect):
+    xyz, lab = _pair_cloud(d)
+    h = orc.rdf(xyz, lab, None, SC, SC, 0.0, 2.0, 200, method="brute")
+    D = orc.D2(xyz[0], xyz[1])
+    if expect is None:
+        assert h.sum() == 0
+    else:
+        # the bin follows the FP64 distance of the stored FP32 coordinates
+        b = int(np.searchsorted(orc.edges2(2.0, 200), D, side="right") - 1)
+        assert b == expect or abs(math.sqrt(D) - d) < 1e-5
+        assert h[b] == 2 and h.sum() == 2  # ordered pairs both ways
+
+
+# --------------------------------------------------------------------------
+# brute force == grid on small inputs, including edge cases
+# --------------------------------------------------------------------------
+
+def _small_cloud(synth, n, seed, L=6.0):
+    s = synth.Specimen(shape="box", L=(L, L, L), n=n, seed=seed, p_m_sc=0.2, p_m_si=0.1)
+    return s.generate()
+
+
+@pytest.mark.parametrize("A,B", [(SC, SC), (SC, AL), (AL, SC), (SI, ANY), (ANY, SC)])
+@pytest.mark.parametrize("use_d", [False, True])
+def test_rdf_brute_equals_grid(orc, synth, A, B, use_d):
+    xyz, lab, d = _small_cloud(synth, 3000, 11)
+    d = d if use_d else None
+    hb = orc.rdf(xyz, lab, d, A, B, 0.7, 1.3, 37, method="brute")
+    hg = orc.rdf(xyz, lab, d, A, B, 0.7, 1.3, 37, method="grid")
+    assert np.array_equal(hb, hg)
+
+
+@pytest.mark.parametrize("A,B,k,rk", [(SC, SC, 10, math.inf), (SC, AL, 5, math.inf),
+                                      (SI, SC, 12, 1.0), (ANY, SI, 3, math.inf),
+                                      (SC, SI, 40, math.inf)])
+def test_knn_brute_equals_grid(orc, synth, A, B, k, rk):
+    xyz, lab, d = _small_cloud(synth, 2500, 12)
+    a = orc.knn(xyz, lab, d, A, B, 0.5, k, rk, kb_rmax=2.0, kb_nbins=50, method="brute")
+    g = orc.knn(xyz, lab, d, A, B, 0.5, k, rk, kb_rmax=2.0, kb_nbins=50, method="grid")
+    for u, v in zip(a, g):
+        assert np.array_equal(u, v)
+    tid, dist, nid, hist = a
+    with np.errstate(invalid="ignore"):
+        assert np.all((np.diff(dist, axis=1) >= 0) | np.isinf(dist[:, 1:]))  # rows ascending
+    assert hist.sum() == len(tid)
+
+
+def test_knn_fewer_than_k_and_empty_species(orc, synth):
+    xyz, lab, d = _small_cloud(synth, 400, 13)
+    lab = lab.copy()
+    lab[lab == SI] = AL
+    lab[np.flatnonzero(lab == AL)[:3]] = SI                 # exactly three Si
+    tid, dist, nid, hist = orc.knn(xyz, lab, None, SC, SI, 0.0, 5, kb_rmax=5.0, kb_nbins=10,
+                                   method="grid")
+    assert np.all(nid[:, 3:] == -1) and np.all(np.isinf(dist[:, 3:]))
+    assert np.all(nid[:, :3] >= 0)
+    assert hist[10] == len(tid)                             # no 5th neighbour anywhere
+    tid, dist, nid, hist = orc.knn(xyz, lab, None, SC, 77, 0.0, 5, kb_rmax=5.0, kb_nbins=10)
+    assert np.all(nid == -1) and len(tid) == (lab == SC).sum()
+    assert orc.rdf(xyz, lab, None, 77, SC, 0.0, 2.0, 20).sum() == 0
+
+
+def test_eligibility_inclusive_nan_and_unfiltered_neighbours(orc):
+    xyz = np.array([[0, 0, 0], [0.25, 0, 0], [0.5, 0, 0], [0.75, 0, 0]], np.float32)
+    lab = np.array([SC, SC, SC, SC], np.uint8)
+    d = np.array([1.0, np.nan, 0.999999, -5.0], np.float32)
+    assert list(orc.select_targets(lab, d, SC, 1.0)) == [0]
+    h = orc.rdf(xyz, lab, d, SC, SC, 1.0, 1.0, 10, method="brute")
+    # target 0 sees 1 (0.25), 2 (0.5), 3 (0.75) although they are not targets
+    assert h.sum() == 3 and h[2] == 1 and h[5] == 1 and h[7] == 1
+
+
+def test_self_exclusion_by_index_and_coincident_ions(orc):
+    xyz = np.array([[1, 1, 1], [1, 1, 1], [1.5, 1, 1]], np.float32)
+    lab = np.array([SC, SC, AL], np.uint8)
+    h = orc.rdf(xyz, lab, None, SC, ANY, 0.0, 1.0, 10, method="brute")
+    assert h[0] == 2 and h[5] == 2 and h.sum() == 4          # coincident pair counts at 0
+    tid, dist, nid, _ = orc.knn(xyz, lab, None, SC, ANY, 0.0, 2, method="brute")
+    assert nid.tolist() == [[1, 2], [0, 2]] and dist[0, 0] == 0.0
+
+
+# --------------------------------------------------------------------------
+# RDF invariants
+# --------------------------------------------------------------------------
+
+def test_rdf_invariants(orc, synth):
+    xyz, lab, d = _small_cloud(synth, 5000, 21, L=7.0)
+    H = {(a, b): orc.rdf(xyz, lab, None, a, b, 0.0, 1.5, 30) for a in (AL, SC, SI, ANY)
+         for b in (AL, SC, SI, ANY)}
+    for a in (AL, SC, SI):
+        for b in (AL, SC, SI):
+            assert np.array_equal(H[a, b], H[b, a])         # symmetric without a filter
+        assert np.all(H[a, a] % 2 == 0)                    # A->A counts both orders
+        assert np.array_equal(H[a, AL] + H[a, SC] + H[a, SI], H[a, ANY])
+    # sum over bins = number of ordered pairs closer than r_max (own count)
+    sc = np.flatnonzero(lab == SC)
+    P = xyz[sc].astype(np.float64)
+    D2 = ((P[:, None, :] - P[None, :, :]) ** 2).sum(-1)
+    np.fill_diagonal(D2, np.inf)
+    assert H[SC, SC].sum() == (D2 < 1.5 ** 2).sum()
+
+
+# --------------------------------------------------------------------------
+# exact lattice sums: fcc Al, a = 0.404 nm
+# --------------------------------------------------------------------------
+
+def _r3(n):
+    k = int(math.isqrt(n)) + 1
+    r = np.arange(-k, k + 1)
+    s = r[:, None, None] ** 2 + r[None, :, None] ** 2 + r[None, None, :] ** 2
+    return int((s == n).sum())
+
+
+def test_fcc_textbook_multiplicities_match_r3():
+    rows, meta = _read_table("fcc_shells.txt")
+    for m, sites in rows:
+        assert _r3(2 * int(m)) == int(sites)
+
+
+def test_rdf_fcc_lattice_exact_shells(orc):
+    rows, meta = _read_table("fcc_shells.txt")
+    a = meta["lattice_constant_nm"]
+    M = 14
+    g = np.arange(2 * M)
+    I, J, K = np.meshgrid(g, g, g, indexing="ij")
+    keep = (I + J + K) % 2 == 0
+    xyz = (np.stack([I[keep], J[keep], K[keep]], 1) * (a / 2)).astype(np.float32)
+    hi = (2 * M - 1) * a / 2
+    d = np.minimum(xyz, hi - xyz).min(1).astype(np.float32)
+    lab = np.zeros(len(xyz), np.uint8)
+    r_max, n_bins = 2.0, 200
+    h = orc.rdf(xyz, lab, d, AL, AL, r_max + 0.01, r_max, n_bins)
+    T = len(orc.select_targets(lab, d, AL, r_max + 0.01))
+    assert T > 100
+    expect = np.zeros(n_bins, np.int64)
+    for m in range(1, int((r_max / a) ** 2 * 2) + 1):
+        r = a * math.sqrt(m / 2)
+        if r >= r_max:
+            break
+        edge = round(r / 0.01) * 0.01
+        # FP32 coordinates below 6 nm move a distance by < 5e-7 nm; shell 13
+        # (1.0300019 nm) sits 1.9e-6 nm above an edge and stays in its bin
+        assert abs(r - edge) > 1e-6, "shell radius too close to a bin edge for this check"
+        expect[int(r / 0.01)] += _r3(2 * m)
+    # sites within 2 nm of an fcc Al site, by direct enumeration of the lattice
+    g2 = np.arange(-12, 13)
+    I2, J2, K2 = np.meshgrid(g2, g2, g2, indexing="ij")
+    S2 = I2 ** 2 + J2 ** 2 + K2 ** 2
+    assert expect.sum() == (((I2 + J2 + K2) % 2 == 0) & (S2 > 0) & (a / 2 * np.sqrt(S2) < r_max)).sum() == 2092
+    assert np.array_equal(h, expect * T)
+
+
+def test_knn_index_tiebreak_on_exact_lattice(orc):
+    # simple cubic lattice with exactly representable coordinates: the 6
+    # nearest sites are exactly equidistant, so the index decides
+    g = np.arange(7, dtype=np.float32) * 0.5
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    xyz = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1).astype(np.float32)
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(len(xyz))
+    xyz = xyz[perm]
+    lab = np.zeros(len(xyz), np.uint8)
+    centre = int(np.flatnonzero((xyz == 1.5).all(1))[0])
+    d = np.full(len(xyz), -1.0, np.float32)
+    d[centre] = 1.0
+    tid, dist, nid, _ = orc.knn(xyz, lab, d, AL, AL, 0.0, 4, method="grid")
+    first = np.flatnonzero(np.abs(np.linalg.norm(xyz - xyz[centre], axis=1) - 0.5) < 1e-6)
+    assert len(first) == 6
+    assert nid[0].tolist() == sorted(first.tolist())[:4]
+    assert np.all(dist[0] == 0.5)
+
+
+# --------------------------------------------------------------------------
+# Poisson closed forms
+# --------------------------------------------------------------------------
+
+def _box_G(r, L):
+    L1, L2, L3 = L
+    return (L1 * L2 * L3 * 4 * math.pi / 3 * r ** 3 - (L1 * L2 + L2 * L3 + L3 * L1) * math.pi / 2 * r ** 4
+            + (L1 + L2 + L3) * 8 / 15 * r ** 5 - r ** 6 / 6)
+
+
+@pytest.mark.parametrize("A,B", [(SC, SC), (SC, AL)])
+def test_rdf_matches_exact_box_expectation(orc, synth, A, B):
+    # i.i.d. uniform points in a box: P(|p - q| < r) = G(r) / V^2 with the box's
+    # set covariance G integrated over the ball (valid for r <= min side)
+    spec = synth.box240k(seed=4)
+    xyz, lab, _ = spec.generate()
+    L = spec.L
+    V = L[0] * L[1] * L[2]
+    NA, NB = int((lab == A).sum()), int((lab == B).sum())
+    pairs = NA * (NB - (1 if A == B else 0))
+    n_bins, r_max = 200, 2.0
+    h = orc.rdf(xyz, lab, None, A, B, 0.0, r_max, n_bins).astype(float)
+    e = np.arange(n_bins + 1) * r_max / n_bins
+    Gv = np.array([_box_G(x, L) for x in e])
+    E = pairs * np.diff(Gv) / V ** 2
+    var = (2.0 if A == B else 1.0) * E + 1e-12
+    z = (h - E) / np.sqrt(var)
+    assert np.abs(z).max() < 5.0
+    chi2 = (z ** 2).sum()
+    assert stats.chi2.sf(chi2, n_bins) > 1e-4
+    ztot = (h.sum() - E.sum()) / math.sqrt((6.0 if A == B else 3.0) * E.sum())
+    assert abs(ztot) < 5.0
+
+
+@pytest.mark.parametrize("k", [1, 10])
+def test_knn_matches_binomial_ball_law(orc, synth, k):
+    # a target >= 4 nm inside the box with N_B - 1 other uniform points:
+    # P(R_k <= r) = P(Binomial(N_B - 1, V_ball(r) / V) >= k).  Targets of one
+    # cloud share neighbours, so the spread is taken across independent seeds.
+    V = 20.0 ** 3
+    qs = np.array([0.1, 0.25, 0.5, 0.75, 0.9])
+    diffs, Ntot, means = [], 0, []
+    for seed in range(1, 9):
+        xyz, lab, _ = synth.box240k(seed=seed).generate()
+        d = np.minimum(xyz, 20.0 - xyz).min(1).astype(np.float32)
+        tid, dist, nid, _ = orc.knn(xyz, lab, d, SC, SC, 4.0, k)
+        Rk = dist[:, k - 1].astype(np.float64)
+        assert np.all(Rk < 4.0)
+        NB = int((lab == SC).sum())
+        cdf = lambda r: stats.binom.sf(k - 1, NB - 1, np.minimum(4 / 3 * math.pi * r ** 3 / V, 1.0))
+        grid = np.linspace(0.05, 4.0, 4000)
+        rq = np.interp(qs, cdf(grid), grid)            # theoretical quantiles
+        diffs.append(np.array([(Rk <= r).mean() for r in rq]) - qs)
+        Ntot += len(Rk)
+        lam = (NB - 1) / V
+        means.append(Rk.mean() - math.gamma(k + 1 / 3) / math.gamma(k) * (3 / (4 * math.pi * lam)) ** (1 / 3))
+    diffs = np.array(diffs)
+    se = np.maximum(diffs.std(0, ddof=1) / math.sqrt(len(diffs)), np.sqrt(qs * (1 - qs) / Ntot))
+    assert np.all(np.abs(diffs.mean(0) / se) < 5.0), diffs.mean(0) / se
+    means = np.array(means)
+    assert abs(means.mean()) < 5 * means.std(ddof=1) / math.sqrt(len(means)) + 1e-4
+
+
+def test_knn_kth_histogram_is_the_kth_distance(orc, synth):
+    xyz, lab, d = _small_cloud(synth, 3000, 31)
+    tid, dist, nid, hist = orc.knn(xyz, lab, d, SC, ANY, 0.5, 4, kb_rmax=1.0, kb_nbins=100)
+    own = np.zeros(101, np.int64)
+    for t, j in zip(tid, nid[:, 3]):
+        own[orc.bin_of(orc.D2(xyz[t], xyz[j]), orc.edges2(1.0, 100))] += 1
+    assert np.array_equal(hist, own)
+
+
+# --------------------------------------------------------------------------
+# smoothed RDF and its adjoint
+# --------------------------------------------------------------------------
+
+def test_smooth_single_pair_is_gaussian_bin_mass(orc):
+    xyz = np.array([[3, 3, 3], [3.73, 3.1, 2.95]], np.float32)
+    lab = np.array([SC, SC], np.uint8)
+    sig, r_max, n_bins = 0.05, 2.0, 200
+    h = orc.smooth_fwd(xyz, lab, None, SC, SC, 0.0, r_max, n_bins, sig)
+    D = math.sqrt(orc.D2(xyz[0], xyz[1]))
+    e = np.arange(n_bins + 1) * r_max / n_bins
+    sig = float(np.float32(sig))                    # the width is passed as FP32
+    lo, hi = (e[:-1] - D) / sig, (e[1:] - D) / sig
+    w = np.where(lo >= 0, stats.norm.sf(lo) - stats.norm.sf(hi), stats.norm.cdf(hi) - stats.norm.cdf(lo))
+    w[(e[1:] <= D - 6 * sig) | (e[:-1] >= D + 6 * sig)] = 0
+    np.testing.assert_allclose(h, 2 * w, rtol=1e-12, atol=1e-15)
+
+
+def test_smooth_small_sigma_recovers_exact_histogram(orc, synth):
+    xyz, lab, d = _small_cloud(synth, 3000, 41)
+    H = orc.rdf(xyz, lab, d, SC, ANY, 0.5, 1.5, 30).astype(float)
+    h = orc.smooth_fwd(xyz, lab, d, SC, ANY, 0.5, 1.5, 30, 1e-6)
+    assert np.abs(h - H).max() <= 2.0     # only pairs within ~6e-6 nm of an edge may split
+    assert abs(h.sum() - H.sum()) <= 2.0
+
+
+def _smooth_problem(synth):
+    s = synth.Specimen(shape="box", L=(5.0, 5.0, 5.0), n=1500, seed=51, p_m_sc=0.3,
+                       n_clusters=3, r_c=0.8, p_c_sc=0.6)
+    xyz, lab, d = s.generate()
+    return xyz, lab
+
+
+def _loss(orc, xyz, lab, s, target):
+    h = orc.smooth_fwd(xyz, lab, None, SC, SC, 0.0, 1.0, 50, 0.05, s)
+    return float(((h - target) ** 2).sum()), h
+
+
+def test_smooth_adjoint_matches_finite_differences(orc, synth):
+    xyz, lab = _smooth_problem(synth)
+    rng = np.random.default_rng(0)
+    target = rng.uniform(0, 20, 50)
+    s = 1.05
+    L0, h = _loss(orc, xyz, lab, s, target)
+    g, gs = orc.smooth_bwd(xyz, lab, None, SC, SC, 0.0, 1.0, 50, 0.05, s, 2 * (h - target))
+    xyz64 = xyz.astype(np.float64)
+    sc = np.flatnonzero(lab == SC)
+    for i in rng.choice(sc, 6, replace=False):
+        for a in range(3):
+            # FP32 positions: step chosen so the perturbed value is exact in FP32
+            step = np.float32(2 ** -12)
+            xp, xm = xyz.copy(), xyz.copy()
+            xp[i, a] += step
+            xm[i, a] -= step
+            hstep = (float(xp[i, a]) - float(xm[i, a])) / 2
+            fd = (_loss(orc, xp, lab, s, target)[0] - _loss(orc, xm, lab, s, target)[0]) / (2 * hstep)
+            assert abs(fd - g[i, a]) <= 2e-3 * max(abs(g[i, a]), 1e-2 * np.abs(g).max()), (i, a, fd, g[i, a])
+    hs = 1e-6
+    fds = (_loss(orc, xyz, lab, s + hs, target)[0] - _loss(orc, xyz, lab, s - hs, target)[0]) / (2 * hs)
+    assert abs(fds - gs) <= 1e-4 * abs(gs)
+
+
+def test_smooth_adjoint_invariants(orc, synth):
+    xyz, lab = _smooth_problem(synth)
+    rng = np.random.default_rng(1)
+    target = rng.uniform(0, 20, 50)
+    for s in (1.0, 1.05):
+        _, h = _loss(orc, xyz, lab, s, target)
+        g, gs = orc.smooth_bwd(xyz, lab, None, SC, SC, 0.0, 1.0, 50, 0.05, s, 2 * (h - target))
+        scale = np.abs(g).sum()
+        # translation invariance
+        assert np.abs(g.sum(0)).max() <= 1e-10 * scale
+        # rotation about z (any s) and about every axis at s = 1
+        P = xyz.astype(np.float64)
+        torque = np.cross(P, g).sum(0)
+        assert abs(torque[2]) <= 1e-9 * scale * 5
+        if s == 1.0:
+            assert np.abs(torque).max() <= 1e-9 * scale * 5
+        # dL/ds = (1/s) sum_i z_i dL/dz_i
+        assert abs(gs - (P[:, 2] * g[:, 2]).sum() / s) <= 1e-9 * (abs(gs) + scale)
