@@ -1,0 +1,156 @@
+/*
+ * apt_stat.h -- C ABI of the GPU spatial-statistics library (libaptstat.so).
+ *
+ * For every target ("central") ion of species A lying at least d_srf from
+ * the specimen surface, the library computes the k nearest neighbours of
+ * species B (distances and identities) and the radial-distribution pair
+ * counts to B ions within r_max (paper, Methods: "Descriptive, two-point
+ * spatial statistics, and clustering" and "Ion-to-edge distancing";
+ * Supplementary: "Customized user defined batch processing queues").  Two
+ * further forms sit beside it: label-randomised null replicates of many
+ * species pairs in one launch (Supplementary: "Importance of high quality
+ * random number generators"; Methods: "User-defined batch processing
+ * queues"), and a Gaussian-smoothed RDF with its adjoint (an extension: not
+ * in the paper).
+ *
+ * Conventions shared by every entry point
+ *  - All data pointers are DEVICE pointers unless stated otherwise; the caller
+ *    owns every input, output and workspace buffer.  The library never
+ *    allocates device memory inside a call.
+ *  - Calls are asynchronous on `stream` (a hipStream_t passed as void*,
+ *    NULL = the null stream) and return as soon as the work is enqueued.
+ *  - Outputs are overwritten, never accumulated.  Integer outputs are
+ *    deterministic.
+ *  - Host-detectable errors are returned immediately (before any GPU work)
+ *    as an apt_status; apt_last_error() then gives a text.  Data-dependent
+ *    errors are OR-ed into the device status word `*status` (int32, cleared
+ *    by the call): APT_STATUS_NONFINITE, APT_STATUS_CAPACITY.
+ *  - Positions: xyz[n][3] FP32 in nm, C-contiguous.  Labels: uint8, species
+ *    0..254; APT_ANY (255) as a query species means "any species".
+ *    d_bnd[n] FP32 distance to the specimen surface (nm), or NULL for no
+ *    surface filter.  n < 2^32.
+ *  - Target eligibility: lab[i] == A (or A == APT_ANY) and
+ *    (d_bnd == NULL or d_bnd[i] >= d_srf); NaN is never eligible.
+ *    Neighbours: lab[j] == B (or B == APT_ANY), j != i; neighbours are not
+ *    filtered by d_bnd.
+ *  - Distances: the RDF bin of a pair is decided on the FP64 squared distance
+ *    ((dx*dx + dy*dy) + dz*dz) of the two stored FP32 positions (differences
+ *    taken in FP64); the kNN order is the FP32 squared distance
+ *    fmaf(dz,dz,fmaf(dy,dy,dx*dx)) with the neighbour index as tie-break.
+ *  - Bins: [e_b, e_{b+1}) with e_b = b * r_max / n_bins (FP64), b < n_bins;
+ *    a pair counts iff its distance is below r_max.  Counts are of ORDERED
+ *    pairs (an A->A histogram counts each unordered pair twice).
+ *  - uint64 outputs may be backed by int64 tensors (counts < 2^63).
+ *  - A call may be issued from several host threads at once on different
+ *    streams with different workspaces; calls that share a workspace must be
+ *    ordered by the caller.
+ */
+#ifndef APT_STAT_H
+#define APT_STAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    APT_OK = 0,
+    APT_E_ARG = -1,          /* invalid argument                                   */
+    APT_E_WORKSPACE = -2,    /* workspace NULL or smaller than apt_workspace_size  */
+    APT_E_UNSUPPORTED = -3,  /* valid but outside the supported range              */
+    APT_E_HIP = -4           /* a HIP runtime call or launch failed                */
+} apt_status;
+
+#define APT_ANY 255
+#define APT_STATUS_NONFINITE 1 /* a coordinate was NaN or infinite (such ions take part in no pair) */
+#define APT_STATUS_CAPACITY 2  /* more eligible targets than the kNN row capacity */
+
+#define APT_MAX_BINS 65536     /* largest n_bins of any histogram */
+#define APT_MAX_K 256          /* largest k */
+
+typedef struct {
+    const float* xyz;     /* [n][3] FP32, device                                 */
+    const uint8_t* lab;   /* [n] species labels, device                          */
+    const float* d_bnd;   /* [n] distance to the surface (nm), device, or NULL   */
+    int64_t n;            /* number of ions, 0 <= n < 2^32                       */
+} apt_cloud;
+
+typedef struct {
+    uint8_t target;       /* species A of the central ions (or APT_ANY)          */
+    uint8_t neighbor;     /* species B of the neighbours (or APT_ANY)            */
+    uint8_t pad[2];
+    float d_srf;          /* minimum distance of a target to the surface (nm)    */
+} apt_query;
+
+typedef struct {
+    float r_max;          /* upper edge of the last bin (nm), > 0, finite         */
+    int32_t n_bins;       /* 1 <= n_bins <= APT_MAX_BINS                          */
+} apt_bins;
+
+/* Operation codes for apt_workspace_size. */
+enum {
+    APT_OP_RDF = 1,       /* apt_rdf                               */
+    APT_OP_KNN = 2,       /* apt_knn                               */
+    APT_OP_KNN_RDF = 3,   /* apt_knn_rdf                           */
+    APT_OP_PERMUTE = 4,   /* apt_permute_labels                    */
+    APT_OP_BATCHED = 5,   /* apt_rdf_batched (n_pairs, n_rep used) */
+    APT_OP_SMOOTH = 6     /* apt_rdf_smooth_fwd / _bwd             */
+};
+
+/* Bytes of device workspace an operation needs for n ions (host only, no
+ * GPU call).  Returns 0 for an unknown op or out-of-range sizes.  The
+ * workspace must be 256-byte aligned (any hipMalloc / torch allocation is). */
+size_t apt_workspace_size(int32_t op, int64_t n, int32_t n_pairs, int32_t n_rep);
+
+/* RDF of one query (paper, Methods: "Descriptive, two-point spatial
+ * statistics"; bins of a rectangular transfer function).
+ *   hist[bins.n_bins] (uint64, device): ordered-pair counts, overwritten. */
+apt_status apt_rdf(const apt_cloud* cloud, apt_query q, apt_bins bins, uint64_t* hist,
+                   int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/* kNN of one query (paper, Methods: kNN as the distribution of distances to
+ * the k-th nearest neighbour of a given type).  Rows are for the eligible
+ * targets in ascending ion index; the search radius is unbounded unless
+ * r_knn_max is finite (neighbours with FP32 squared distance above
+ * r_knn_max*r_knn_max are ignored).
+ *   capacity           rows the output arrays hold (>= 0)
+ *   target_id[cap]     int64 ion index of each row (ascending)
+ *   dist[cap][k]       FP32 distances, ascending, +inf padding
+ *   nbr_id[cap][k]     int64 neighbour indices, -1 padding
+ *   knn_bins, knn_hist optional (knn_hist may be NULL): [knn_bins.n_bins + 1]
+ *                      uint64 counts of targets per bin of their k-th
+ *                      neighbour distance; the last slot counts targets
+ *                      whose k-th neighbour is missing or >= knn_bins.r_max
+ *   n_targets[1]       int64, device: number of eligible targets.  Rows
+ *                      beyond `capacity` are dropped and APT_STATUS_CAPACITY
+ *                      is set. */
+apt_status apt_knn(const apt_cloud* cloud, apt_query q, int32_t k, float r_knn_max,
+                   int64_t capacity, int64_t* target_id, float* dist, int64_t* nbr_id,
+                   apt_bins knn_bins, uint64_t* knn_hist, int64_t* n_targets, int32_t* status,
+                   void* ws, size_t ws_bytes, void* stream);
+
+/* kNN and RDF of one query from a single neighbour enumeration (the paper's
+ * batch queue evaluates several statistics per region of interest rather
+ * than querying again: Supplementary, "Customized user defined batch
+ * processing queues").  Arguments as apt_rdf and apt_knn; rdf_hist may not
+ * be NULL. */
+apt_status apt_knn_rdf(const apt_cloud* cloud, apt_query q, apt_bins rdf_bins, uint64_t* rdf_hist,
+                       int32_t k, float r_knn_max, int64_t capacity, int64_t* target_id,
+                       float* dist, int64_t* nbr_id, apt_bins knn_bins, uint64_t* knn_hist,
+                       int64_t* n_targets, int32_t* status, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/* Number of eligible targets of a query, for sizing kNN outputs:
+ * n_targets[1] (int64, device) is overwritten.  Workspace as APT_OP_KNN. */
+apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_targets, void* ws,
+                             size_t ws_bytes, void* stream);
+
+/* Text of the last host-side error of the calling thread ("" if none). */
+const char* apt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* APT_STAT_H */

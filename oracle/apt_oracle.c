@@ -83,6 +83,10 @@ int32_t orc_bin_of(double D2, const double* E2, int32_t n_bins) {
 
 static int is_species(uint8_t s, int32_t want) { return want == ORC_ANY || (int32_t)s == want; }
 
+/* An ion with a NaN or infinite coordinate takes part in no pair, neither as
+ * target (its row stays empty) nor as neighbour. */
+static int finite3(const float* p) { return isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]); }
+
 static int is_target(int64_t i, const uint8_t* lab, const float* d_bnd, int32_t A, float d_srf) {
     if (!is_species(lab[i], A)) return 0;
     if (d_bnd && !(d_bnd[i] >= d_srf)) return 0; /* inclusive; NaN is never eligible */
@@ -110,9 +114,9 @@ void orc_rdf_brute(const float* xyz, const uint8_t* lab, const float* d_bnd, int
     orc_edges2(r_max, n_bins, E2);
     memset(hist, 0, sizeof(uint64_t) * (size_t)n_bins);
     for (int64_t i = 0; i < n; ++i) {
-        if (!is_target(i, lab, d_bnd, A, d_srf)) continue;
+        if (!is_target(i, lab, d_bnd, A, d_srf) || !finite3(xyz + 3 * i)) continue;
         for (int64_t j = 0; j < n; ++j) {
-            if (j == i || !is_species(lab[j], B)) continue;
+            if (j == i || !is_species(lab[j], B) || !finite3(xyz + 3 * j)) continue;
             int32_t b = orc_bin_of(orc_D2(xyz + 3 * i, xyz + 3 * j), E2, n_bins);
             if (b < n_bins) hist[b]++;
         }
@@ -135,18 +139,23 @@ typedef struct {
 
 static int64_t ocell_axis(const ogrid* g, int a, double x) {
     double f = floor((x - g->lo[a]) / g->h);
-    if (f < 0) return 0;
+    if (!(f >= 0)) return 0;
     if (f > (double)(g->dim[a] - 1)) return g->dim[a] - 1;
     return (int64_t)f;
 }
 
-/* coords: position of ion i on axis a (pos(i, a)); h_min: smallest cell edge. */
+static int pos_finite(double (*pos)(const void*, int64_t, int), const void* ctx, int64_t j) {
+    return isfinite(pos(ctx, j, 0)) && isfinite(pos(ctx, j, 1)) && isfinite(pos(ctx, j, 2));
+}
+
+/* coords: position of ion i on axis a (pos(i, a)); h_min: smallest cell edge.
+ * Only neighbours with finite positions enter the grid. */
 static void ogrid_build(ogrid* g, int64_t n, const uint8_t* lab, int32_t B,
                         double (*pos)(const void*, int64_t, int), const void* ctx, double h_min) {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     int64_t nb = 0;
     for (int64_t j = 0; j < n; ++j) {
-        if (!is_species(lab[j], B)) continue;
+        if (!is_species(lab[j], B) || !pos_finite(pos, ctx, j)) continue;
         ++nb;
         for (int a = 0; a < 3; ++a) {
             double v = pos(ctx, j, a);
@@ -176,7 +185,7 @@ static void ogrid_build(ogrid* g, int64_t n, const uint8_t* lab, int32_t B,
     g->nitem = nb;
     int64_t* cellof = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     for (int64_t j = 0; j < n; ++j) {
-        if (!is_species(lab[j], B)) { cellof[j] = -1; continue; }
+        if (!is_species(lab[j], B) || !pos_finite(pos, ctx, j)) { cellof[j] = -1; continue; }
         int64_t c[3];
         for (int a = 0; a < 3; ++a) c[a] = ocell_axis(g, a, pos(ctx, j, a));
         cellof[j] = (c[2] * g->dim[1] + c[1]) * g->dim[0] + c[0];
@@ -215,7 +224,7 @@ void orc_rdf_grid(const float* xyz, const uint8_t* lab, const float* d_bnd, int6
         uint64_t* loc = (uint64_t*)calloc((size_t)n_bins, sizeof(uint64_t));
 #pragma omp for schedule(dynamic, 256)
         for (int64_t i = 0; i < n; ++i) {
-            if (!is_target(i, lab, d_bnd, A, d_srf)) continue;
+            if (!is_target(i, lab, d_bnd, A, d_srf) || !finite3(xyz + 3 * i)) continue;
             const float* pi = xyz + 3 * i;
             int64_t c[3];
             for (int a = 0; a < 3; ++a) c[a] = ocell_axis(&g, a, (double)pi[a]);
@@ -313,8 +322,8 @@ int64_t orc_knn_brute(const float* xyz, const uint8_t* lab, const float* d_bnd, 
     for (int64_t i = 0; i < n; ++i) {
         if (!is_target(i, lab, d_bnd, A, d_srf)) continue;
         int32_t cnt = 0;
-        for (int64_t j = 0; j < n; ++j) {
-            if (j == i || !is_species(lab[j], B)) continue;
+        for (int64_t j = 0; j < n && finite3(xyz + 3 * i); ++j) {
+            if (j == i || !is_species(lab[j], B) || !finite3(xyz + 3 * j)) continue;
             float d2 = orc_d2f(xyz + 3 * i, xyz + 3 * j);
             if (!(d2 <= rk2)) continue;
             topk_insert(best, &cnt, k, knn_key(d2, j));
@@ -340,13 +349,13 @@ int64_t orc_knn_grid(const float* xyz, const uint8_t* lab, const float* d_bnd, i
     int64_t* tid = (int64_t*)malloc(sizeof(int64_t) * (size_t)(T > 0 ? T : 1));
     orc_select_targets(n, lab, d_bnd, A, d_srf, tid);
     int64_t nb = 0;
-    for (int64_t j = 0; j < n; ++j) nb += is_species(lab[j], B);
+    for (int64_t j = 0; j < n; ++j) nb += is_species(lab[j], B) && finite3(xyz + 3 * j);
     /* cell edge ~ the spacing that holds a few neighbours per cell */
     double vol = 1.0;
     {
         double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
         for (int64_t j = 0; j < n; ++j)
-            if (is_species(lab[j], B))
+            if (is_species(lab[j], B) && finite3(xyz + 3 * j))
                 for (int a = 0; a < 3; ++a) {
                     if (xyz[3 * j + a] < lo[a]) lo[a] = xyz[3 * j + a];
                     if (xyz[3 * j + a] > hi[a]) hi[a] = xyz[3 * j + a];
@@ -367,7 +376,7 @@ int64_t orc_knn_grid(const float* xyz, const uint8_t* lab, const float* d_bnd, i
             int64_t c[3];
             for (int a = 0; a < 3; ++a) c[a] = ocell_axis(&g, a, (double)pi[a]);
             int32_t cnt = 0;
-            for (int64_t s = 0;; ++s) {
+            for (int64_t s = 0; finite3(pi); ++s) {
                 /* cells on the surface of the cube of half-width s */
                 for (int64_t z = c[2] - s; z <= c[2] + s; ++z) {
                     if (z < 0 || z >= g.dim[2]) continue;
@@ -502,7 +511,7 @@ static void smooth_pairs(const float* xyz, const uint8_t* lab, const float* d_bn
     ogrid g;
     ogrid_build(&g, n, lab, B, pos_scaled, &ctx, cut * (1.0 + 1e-6));
     for (int64_t i = 0; i < n; ++i) {
-        if (!is_target(i, lab, d_bnd, A, d_srf)) continue;
+        if (!is_target(i, lab, d_bnd, A, d_srf) || !pos_finite(pos_scaled, &ctx, i)) continue;
         double P[3];
         int64_t c[3];
         for (int a = 0; a < 3; ++a) {

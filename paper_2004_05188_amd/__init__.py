@@ -1,0 +1,253 @@
+"""Spatial statistics of atom-probe point clouds on the MI355X (gfx950).
+
+Thin Python binding of ``libaptstat.so`` (C ABI in ``include/apt_stat.h``).
+Arguments are torch tensors on the GPU; the binding only checks dtypes and
+shapes, passes raw device pointers and the current HIP stream, and raises
+on a non-zero return code.  Every step of the computation runs in the
+library's HIP kernels; there is no CPU fallback: without the built library
+every call raises.
+
+Species are small integers (0..254); ``ANY`` (255) selects every species.
+uint64 histograms are returned in int64 tensors (counts < 2^63).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import torch
+
+from . import _build
+
+ANY = 255
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libaptstat.so")
+
+STATUS_NONFINITE = 1
+STATUS_CAPACITY = 2
+OP_RDF, OP_KNN, OP_KNN_RDF, OP_PERMUTE, OP_BATCHED, OP_SMOOTH = 1, 2, 3, 4, 5, 6
+
+
+class AptError(RuntimeError):
+    pass
+
+
+class _Cloud(ctypes.Structure):
+    _fields_ = [("xyz", ctypes.c_void_p), ("lab", ctypes.c_void_p), ("d_bnd", ctypes.c_void_p),
+                ("n", ctypes.c_int64)]
+
+
+class _Query(ctypes.Structure):
+    _fields_ = [("target", ctypes.c_uint8), ("neighbor", ctypes.c_uint8), ("pad", ctypes.c_uint8 * 2),
+                ("d_srf", ctypes.c_float)]
+
+
+class _Bins(ctypes.Structure):
+    _fields_ = [("r_max", ctypes.c_float), ("n_bins", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_lib = None
+
+_SIGS = {
+    "apt_workspace_size": ([ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32], ctypes.c_size_t),
+    "apt_last_error": ([], ctypes.c_char_p),
+    "apt_count_targets": ([ctypes.POINTER(_Cloud), _Query, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "apt_rdf": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "apt_knn": ([ctypes.POINTER(_Cloud), _Query, ctypes.c_int32, ctypes.c_float, ctypes.c_int64, _P, _P, _P,
+                 _Bins, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "apt_knn_rdf": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, ctypes.c_int32, ctypes.c_float, ctypes.c_int64,
+                     _P, _P, _P, _Bins, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+}
+
+
+def library_path() -> str:
+    return _SO
+
+
+def lib():
+    """The loaded C library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            raise AptError(f"{_SO} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        L = ctypes.CDLL(_SO)
+        for name, (args, res) in _SIGS.items():
+            if hasattr(L, name):
+                f = getattr(L, name)
+                f.argtypes = args
+                f.restype = res
+        _lib = L
+    return _lib
+
+
+def build() -> str:
+    global _lib
+    _lib = None
+    return _build.build()
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = lib().apt_last_error()
+        raise AptError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+
+def _stream(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need(t, dtype, shape=None, name="tensor"):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise AptError(f"{name} must be on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise AptError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise AptError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+class Cloud:
+    """Positions xyz (float32 [n,3]), labels lab (uint8 [n]) and optional
+    distance-to-surface d_bnd (float32 [n]), all on one GPU."""
+
+    def __init__(self, xyz: torch.Tensor, lab: torch.Tensor, d_bnd: torch.Tensor | None = None):
+        n = xyz.shape[0]
+        _need(xyz, torch.float32, (n, 3), "xyz")
+        _need(lab, torch.uint8, (n,), "lab")
+        if d_bnd is not None:
+            _need(d_bnd, torch.float32, (n,), "d_bnd")
+            if d_bnd.device != xyz.device:
+                raise AptError("d_bnd is on another device")
+        if lab.device != xyz.device:
+            raise AptError("lab is on another device")
+        self.xyz, self.lab, self.d_bnd, self.n = xyz, lab, d_bnd, n
+        self.device = xyz.device
+        self._c = _Cloud(xyz.data_ptr(), lab.data_ptr(), d_bnd.data_ptr() if d_bnd is not None else None, n)
+
+    def c(self):
+        return ctypes.byref(self._c)
+
+
+class Workspace:
+    """Device scratch for the library calls; grows on demand and is reused."""
+
+    def __init__(self, device=None):
+        self.device = torch.device(device) if device is not None else None
+        self.buf = None
+
+    def get(self, nbytes: int, device) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != torch.device(device):
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        return self.buf
+
+
+def workspace_size(op: int, n: int, n_pairs: int = 0, n_rep: int = 0) -> int:
+    s = lib().apt_workspace_size(op, n, n_pairs, n_rep)
+    if s == 0:
+        raise AptError(f"no workspace size for op {op}, n = {n}")
+    return int(s)
+
+
+def _query(target: int, neighbor: int, d_srf: float) -> _Query:
+    q = _Query()
+    q.target, q.neighbor, q.d_srf = int(target), int(neighbor), float(d_srf)
+    return q
+
+
+def _bins(r_max: float, n_bins: int) -> _Bins:
+    b = _Bins()
+    b.r_max, b.n_bins = float(r_max), int(n_bins)
+    return b
+
+
+def _ws(ws, op, cloud, n_pairs=0, n_rep=0):
+    ws = ws if ws is not None else Workspace()
+    nb = workspace_size(op, cloud.n, n_pairs, n_rep)
+    return ws.get(nb, cloud.device), nb
+
+
+def count_targets(cloud: Cloud, target: int, d_srf: float = 0.0, ws: Workspace | None = None,
+                  out: torch.Tensor | None = None) -> torch.Tensor:
+    """Eligible-target count as a device int64 tensor [1] (no host sync)."""
+    buf, nb = _ws(ws, OP_KNN, cloud)
+    out = out if out is not None else torch.empty(1, dtype=torch.int64, device=cloud.device)
+    _check(lib().apt_count_targets(cloud.c(), _query(target, ANY, d_srf), _ptr(out), _ptr(buf), nb,
+                                   _stream(cloud.xyz)), "apt_count_targets")
+    return out
+
+
+def rdf(cloud: Cloud, target: int, neighbor: int, d_srf: float, r_max: float, n_bins: int,
+        ws: Workspace | None = None, out: torch.Tensor | None = None, status: torch.Tensor | None = None):
+    """Ordered-pair counts per bin [0, r_max) / n_bins: int64 tensor [n_bins]."""
+    buf, nb = _ws(ws, OP_RDF, cloud)
+    dev = cloud.device
+    out = out if out is not None else torch.empty(n_bins, dtype=torch.int64, device=dev)
+    _need(out, torch.int64, (n_bins,), "out")
+    status = status if status is not None else torch.empty(1, dtype=torch.int32, device=dev)
+    _check(lib().apt_rdf(cloud.c(), _query(target, neighbor, d_srf), _bins(r_max, n_bins), _ptr(out),
+                         _ptr(status), _ptr(buf), nb, _stream(cloud.xyz)), "apt_rdf")
+    return out
+
+
+class KnnResult:
+    def __init__(self, target_id, dist, nbr_id, knn_hist, n_targets, status, rdf_hist=None):
+        self.target_id, self.dist, self.nbr_id = target_id, dist, nbr_id
+        self.knn_hist, self.n_targets, self.status, self.rdf_hist = knn_hist, n_targets, status, rdf_hist
+
+    def trimmed(self):
+        """(target_id, dist, nbr_id) cut to the number of targets (host sync)."""
+        t = min(int(self.n_targets.item()), self.target_id.shape[0])
+        return self.target_id[:t], self.dist[:t], self.nbr_id[:t]
+
+
+def _knn_outputs(dev, capacity, k, kb_nbins, want_hist):
+    return (torch.empty(max(capacity, 1), dtype=torch.int64, device=dev),
+            torch.empty((max(capacity, 1), k), dtype=torch.float32, device=dev),
+            torch.empty((max(capacity, 1), k), dtype=torch.int64, device=dev),
+            torch.empty(kb_nbins + 1, dtype=torch.int64, device=dev) if want_hist else None,
+            torch.empty(1, dtype=torch.int64, device=dev),
+            torch.empty(1, dtype=torch.int32, device=dev))
+
+
+def knn_rdf(cloud: Cloud, target: int, neighbor: int, d_srf: float, k: int, r_max: float = 2.0,
+            n_bins: int = 200, r_knn_max: float = math.inf, capacity: int | None = None,
+            kb_rmax: float = 5.0, kb_nbins: int = 5000, want_rdf: bool = True, want_hist: bool = True,
+            ws: Workspace | None = None, outputs=None) -> KnnResult:
+    """kNN rows (and optionally the RDF) of one query from one enumeration.
+
+    capacity: rows to allocate; None counts the eligible targets first (one
+    extra small library call and a host sync)."""
+    dev = cloud.device
+    if capacity is None:
+        capacity = int(count_targets(cloud, target, d_srf, ws=ws).item())
+    if outputs is None:
+        tid, dist, nid, kh, nt, st = _knn_outputs(dev, capacity, k, kb_nbins, want_hist)
+        rh = torch.empty(n_bins, dtype=torch.int64, device=dev) if want_rdf else None
+    else:
+        tid, dist, nid, kh, nt, st, rh = outputs
+    op = OP_KNN_RDF if want_rdf else OP_KNN
+    buf, nb = _ws(ws, op, cloud)
+    s = _stream(cloud.xyz)
+    if want_rdf:
+        _check(lib().apt_knn_rdf(cloud.c(), _query(target, neighbor, d_srf), _bins(r_max, n_bins), _ptr(rh),
+                                 int(k), float(r_knn_max), int(capacity), _ptr(tid), _ptr(dist), _ptr(nid),
+                                 _bins(kb_rmax, kb_nbins), _ptr(kh), _ptr(nt), _ptr(st), _ptr(buf), nb, s),
+               "apt_knn_rdf")
+    else:
+        _check(lib().apt_knn(cloud.c(), _query(target, neighbor, d_srf), int(k), float(r_knn_max),
+                             int(capacity), _ptr(tid), _ptr(dist), _ptr(nid), _bins(kb_rmax, kb_nbins),
+                             _ptr(kh), _ptr(nt), _ptr(st), _ptr(buf), nb, s), "apt_knn")
+    return KnnResult(tid, dist, nid, kh, nt, st, rh)
+
+
+def knn(cloud: Cloud, target: int, neighbor: int, d_srf: float, k: int, **kw) -> KnnResult:
+    return knn_rdf(cloud, target, neighbor, d_srf, k, want_rdf=False, **kw)

@@ -1,0 +1,397 @@
+// Host side of the C ABI: argument checks, workspace layout and the launch
+// sequence of each entry point.  Nothing here allocates device memory.
+#include <math.h>
+
+#include <mutex>
+#include <string>
+
+#include "apt_bin.hpp"
+#include "apt_pair.hpp"
+
+namespace apt {
+
+static thread_local std::string g_err;
+
+static apt_status fail(apt_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+// ---------------------------------------------------------------- device --
+struct DevInfo {
+    int cus = 0;
+};
+
+static DevInfo device_info() {
+    static std::mutex mu;
+    static DevInfo cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return DevInfo{256};
+    std::lock_guard<std::mutex> g(mu);
+    if (cache[dev].cus == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cache[dev].cus = cus;
+    }
+    return cache[dev];
+}
+
+// ------------------------------------------------------------ sizing --
+constexpr int kCountTile = 4096;
+
+static int count_blocks(int64_t n) {
+    int64_t g = (n + 16 * kCountTile - 1) / (16 * kCountTile);
+    if (g < 1) g = 1;
+    if (g > 1024) g = 1024;
+    return (int)g;
+}
+static int64_t count_chunk(int64_t n, int G) {
+    int64_t c = (n + G - 1) / G;
+    return (c + kCountTile - 1) / kCountTile * kCountTile;
+}
+static uint32_t cell_cap_for(int64_t n) {
+    int64_t c = n / 2;
+    if (c < 65536) c = 65536;
+    if (c > 0xFFFFFF00ll) c = 0xFFFFFF00ll;
+    return (uint32_t)c;
+}
+static int sort_passes_max(uint32_t cap) {
+    int p = 1;
+    while (p < 4 && ((cap - 1u) >> (8 * p)) != 0u) ++p;
+    return p;
+}
+constexpr int kSortBlocks = 1024;
+
+// Workspace of the plain path (rdf / knn / knn_rdf).
+struct PlainWs {
+    GridPlan* plan;
+    uint32_t* part_cnt;
+    float* part_bbox;
+    int32_t* part_nf;
+    uint32_t* part_off;
+    double* E2;
+    double* KE2;
+    uint32_t* tid;
+    uint32_t* bsel;
+    uint32_t* K[2];
+    uint32_t* V[2];
+    uint32_t* order;
+    float* bx;
+    float* by;
+    float* bz;
+    uint32_t* cell_start;
+    uint32_t* rs_counts;
+    size_t bytes;
+};
+
+static PlainWs carve_plain(void* base, int64_t n) {
+    Carve c{reinterpret_cast<char*>(base)};
+    PlainWs w;
+    const size_t N = (size_t)(n > 0 ? n : 1);
+    w.plan = c.take<GridPlan>(1);
+    w.part_cnt = c.take<uint32_t>(2 * 1024);
+    w.part_bbox = c.take<float>(6 * 1024);
+    w.part_nf = c.take<int32_t>(1024);
+    w.part_off = c.take<uint32_t>(2 * 1024);
+    w.E2 = c.take<double>(APT_MAX_BINS + 1);
+    w.KE2 = c.take<double>(APT_MAX_BINS + 1);
+    w.rs_counts = c.take<uint32_t>(256 * kSortBlocks);
+    w.tid = c.take<uint32_t>(N);
+    w.bsel = c.take<uint32_t>(N);
+    w.K[0] = c.take<uint32_t>(N);
+    w.V[0] = c.take<uint32_t>(N);
+    w.K[1] = c.take<uint32_t>(N);
+    w.V[1] = c.take<uint32_t>(N);
+    w.order = c.take<uint32_t>(N);
+    w.bx = c.take<float>(N);
+    w.by = c.take<float>(N);
+    w.bz = c.take<float>(N);
+    w.cell_start = c.take<uint32_t>((size_t)cell_cap_for(n) + 1);
+    w.bytes = c.off;
+    return w;
+}
+
+// ------------------------------------------------------------ checks --
+static apt_status check_cloud(const apt_cloud* cl) {
+    if (!cl) return fail(APT_E_ARG, "cloud is NULL");
+    if (cl->n < 0) return fail(APT_E_ARG, "cloud->n is negative");
+    if (cl->n >= (int64_t)0xFFFFFFFFll) return fail(APT_E_UNSUPPORTED, "cloud->n must be below 2^32 - 1");
+    if (cl->n > 0 && (!cl->xyz || !cl->lab)) return fail(APT_E_ARG, "cloud->xyz or cloud->lab is NULL");
+    return APT_OK;
+}
+static apt_status check_query(apt_query q) {
+    if (isnan(q.d_srf)) return fail(APT_E_ARG, "query.d_srf is NaN");
+    return APT_OK;
+}
+static apt_status check_bins(apt_bins b, const char* what) {
+    if (!(b.r_max > 0.0f) || !isfinite(b.r_max))
+        return fail(APT_E_ARG, std::string(what) + ".r_max must be finite and > 0");
+    if (b.n_bins < 1 || b.n_bins > APT_MAX_BINS)
+        return fail(APT_E_ARG, std::string(what) + ".n_bins must be in [1, 65536]");
+    return APT_OK;
+}
+static apt_status check_ws(void* ws, size_t ws_bytes, size_t need) {
+    if (!ws) return fail(APT_E_WORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(APT_E_WORKSPACE, "workspace is not 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(APT_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes, got " +
+                                         std::to_string(ws_bytes));
+    return APT_OK;
+}
+static apt_status hip_check(const char* where) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(APT_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+    return APT_OK;
+}
+
+// ------------------------------------------------------- small kernels --
+struct InitArgs {
+    int32_t* status;
+    uint64_t* h1;
+    int32_t n1;
+    uint64_t* h2;
+    int32_t n2;
+    int64_t* n_targets;
+};
+__global__ void k_init(InitArgs a) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x, st = gridDim.x * blockDim.x;
+    if (t == 0) {
+        if (a.status) *a.status = 0;
+        if (a.n_targets) *a.n_targets = 0;
+    }
+    if (a.h1)
+        for (int b = t; b < a.n1; b += st) a.h1[b] = 0;
+    if (a.h2)
+        for (int b = t; b < a.n2; b += st) a.h2[b] = 0;
+}
+
+struct FinishArgs {
+    const GridPlan* plan;
+    int64_t capacity;
+    int64_t* n_targets;
+    int32_t* status;
+};
+__global__ void k_finish(FinishArgs a) {
+    const uint32_t nT = a.plan->nT;
+    if (a.n_targets) *a.n_targets = (int64_t)nT;
+    if (a.capacity >= 0 && (int64_t)nT > a.capacity && a.status) atomicOr(a.status, APT_STATUS_CAPACITY);
+}
+
+// The binning stage shared by the plain entry points.  Leaves in the
+// workspace: plan, tid (eligible targets ascending), order (their ranks in
+// cell order), neighbour SoA in cell order and cell_start.
+static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams& pp, const PlainWs& w,
+                              int32_t* status, hipStream_t st) {
+    const int64_t n = cl->n;
+    const int G = count_blocks(n);
+    const int64_t chunk = count_chunk(n, G);
+    const int cus = device_info().cus;
+
+    CountArgs ca{cl->xyz, cl->lab, cl->d_bnd, n, chunk, q.target, q.neighbor, q.d_srf, nullptr,
+                 w.part_cnt, w.part_bbox, w.part_nf};
+    hipLaunchKernelGGL(k_count, dim3(G), dim3(kBlock), 0, st, ca);
+    PlanArgs pa{G, w.part_cnt, w.part_bbox, w.part_nf, w.part_off, pp, nullptr, w.plan, status};
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, pa);
+    const bool all_b = q.neighbor == APT_ANY;
+    CompactArgs cm{cl->lab, cl->d_bnd, n, chunk, q.target, q.neighbor, q.d_srf, w.part_off, w.tid,
+                   all_b ? nullptr : w.bsel};
+    hipLaunchKernelGGL(k_compact, dim3(G), dim3(kBlock), 0, st, cm);
+
+    const int passes = sort_passes_max(pp.cell_cap);
+    const int Gk = cus * 8;
+    auto sort = [&](int is_T) {
+        for (int p = 0; p < passes; ++p) {
+            SortArgs sa{w.plan, is_T, p, kSortBlocks, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.rs_counts};
+            hipLaunchKernelGGL(k_rs_upsweep, dim3(kSortBlocks), dim3(kBlock), 0, st, sa);
+            hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, sa);
+            hipLaunchKernelGGL(k_rs_downsweep, dim3(kSortBlocks), dim3(kBlock), 0, st, sa);
+        }
+    };
+    // targets in cell order
+    KeyArgs kt{w.plan, cl->xyz, w.tid, nullptr, 1, 1, w.K[0], w.V[0]};
+    hipLaunchKernelGGL(k_keys, dim3(Gk), dim3(kBlock), 0, st, kt);
+    sort(1);
+    OrderArgs oa{w.plan, {w.V[0], w.V[1]}, w.order};
+    hipLaunchKernelGGL(k_take_order, dim3(Gk), dim3(kBlock), 0, st, oa);
+    // neighbours in cell order
+    KeyArgs kb{w.plan, cl->xyz, all_b ? nullptr : w.bsel, nullptr, 0, 0, w.K[0], w.V[0]};
+    hipLaunchKernelGGL(k_keys, dim3(Gk), dim3(kBlock), 0, st, kb);
+    sort(0);
+    GatherArgs ga{w.plan, cl->xyz, nullptr, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.bx, w.by, w.bz, w.cell_start};
+    hipLaunchKernelGGL(k_gather, dim3(Gk), dim3(kBlock), 0, st, ga);
+    return hip_check("binning launch");
+}
+
+// The whole plain path.  rdf_hist / knn outputs may be absent.
+static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb, uint64_t* rdf_hist,
+                            int32_t k, float r_knn_max, int64_t capacity, int64_t* target_id,
+                            float* dist, int64_t* nbr_id, const apt_bins* kb, uint64_t* knn_hist,
+                            int64_t* n_targets, int32_t* status, void* ws, size_t ws_bytes,
+                            void* stream) {
+    apt_status s;
+    if ((s = check_cloud(cl)) != APT_OK) return s;
+    if ((s = check_query(q)) != APT_OK) return s;
+    if (!status) return fail(APT_E_ARG, "status is NULL");
+    const bool do_rdf = rb != nullptr, do_knn = k > 0;
+    if (do_rdf) {
+        if ((s = check_bins(*rb, "rdf_bins")) != APT_OK) return s;
+        if (!rdf_hist) return fail(APT_E_ARG, "rdf histogram output is NULL");
+    }
+    if (do_knn) {
+        if (k > APT_MAX_K) return fail(APT_E_UNSUPPORTED, "k must be in [1, 256]");
+        if (!(r_knn_max > 0.0f)) return fail(APT_E_ARG, "r_knn_max must be > 0 (or +inf)");
+        if (capacity < 0) return fail(APT_E_ARG, "capacity is negative");
+        if (capacity > 0 && (!target_id || !dist || !nbr_id)) return fail(APT_E_ARG, "kNN row output is NULL");
+        if (!n_targets) return fail(APT_E_ARG, "n_targets is NULL");
+        if (knn_hist && (s = check_bins(*kb, "knn_bins")) != APT_OK) return s;
+    }
+    PlainWs w = carve_plain(ws, cl->n);
+    if ((s = check_ws(ws, ws_bytes, w.bytes)) != APT_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+
+    InitArgs ia{status, rdf_hist, do_rdf ? rb->n_bins : 0, knn_hist, knn_hist ? kb->n_bins + 1 : 0, n_targets};
+    hipLaunchKernelGGL(k_init, dim3(64), dim3(256), 0, st, ia);
+    if (do_rdf) hipLaunchKernelGGL(k_edges, dim3(64), dim3(256), 0, st, w.E2, rb->r_max, rb->n_bins);
+    if (knn_hist) hipLaunchKernelGGL(k_edges, dim3(64), dim3(256), 0, st, w.KE2, kb->r_max, kb->n_bins);
+
+    PlanParams pp;
+    pp.h_min = do_rdf ? rb->r_max * 0.5f : 0.0f;
+    pp.occ = 4.0f;
+    pp.k = do_knn ? k : 0;
+    pp.cell_cap = cell_cap_for(cl->n);
+    if ((s = run_binning(cl, q, pp, w, status, st)) != APT_OK) return s;
+
+    PairArgs pa{};
+    pa.plan = w.plan;
+    pa.xyz = cl->xyz;
+    pa.tid = w.tid;
+    pa.order = w.order;
+    pa.bx = w.bx;
+    pa.by = w.by;
+    pa.bz = w.bz;
+    pa.vals[0] = w.V[0];
+    pa.vals[1] = w.V[1];
+    pa.cell_start = w.cell_start;
+    pa.self_possible = q.target == APT_ANY || q.neighbor == APT_ANY || q.target == q.neighbor;
+    int n_bins = 1;
+    bool in_lds = false;
+    if (do_rdf) {
+        n_bins = rb->n_bins;
+        const double rmax = (double)rb->r_max;
+        pa.n_bins = n_bins;
+        // FP32 fast path: the bin of sqrt(d2f) is off from the FP64 bin only
+        // within ~1e-4 bins of an edge (relative error of d2f, sqrt and the
+        // scaling < 7 ulp); pairs within delta of an edge (at least 1e-6 nm)
+        // are re-decided in FP64.
+        const double w_bin = rmax / n_bins;
+        double delta = fmax(1e-6, 2e-6 * rmax);
+        double delta_b = fmax(delta / w_bin, 4e-6 * n_bins);
+        if (delta_b > 0.25) delta_b = 0.25;
+        pa.delta_b = (float)delta_b;
+        pa.inv_w = (float)(n_bins / rmax);
+        pa.inv_w64 = n_bins / rmax;
+        pa.thr2 = (float)((rmax * (1.0 + 2e-5)) * (rmax * (1.0 + 2e-5)));
+        pa.r_enum = (float)(rmax * (1.0 + 4e-5));
+        pa.E2 = w.E2;
+        pa.hist = rdf_hist;
+        in_lds = (size_t)kWavesPerBlock * n_bins * 4u <= 48u * 1024u;
+        pa.hist_in_lds = in_lds ? 1 : 0;
+    }
+    if (do_knn) {
+        pa.k = k;
+        pa.rknn = r_knn_max;
+        pa.rknn2 = r_knn_max * r_knn_max;
+        pa.capacity = capacity;
+        pa.target_id = target_id;
+        pa.dist = dist;
+        pa.nbr_id = nbr_id;
+        pa.knn_hist = knn_hist;
+        if (knn_hist) {
+            pa.kb_nbins = kb->n_bins;
+            pa.kb_inv_w64 = kb->n_bins / (double)kb->r_max;
+            pa.KE2 = w.KE2;
+        }
+    }
+    const size_t lds = pair_lds_bytes(do_rdf, do_knn, n_bins, in_lds);
+    const int Gp = device_info().cus * 8;
+    if (do_rdf && do_knn)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pair<true, true>), dim3(Gp), dim3(kBlock), lds, st, pa);
+    else if (do_rdf)
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pair<true, false>), dim3(Gp), dim3(kBlock), lds, st, pa);
+    else
+        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pair<false, true>), dim3(Gp), dim3(kBlock), lds, st, pa);
+    FinishArgs fa{w.plan, do_knn ? capacity : -1, n_targets, status};
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, st, fa);
+    return hip_check("pair launch");
+}
+
+}  // namespace apt
+
+using namespace apt;
+
+extern "C" {
+
+const char* apt_last_error(void) { return g_err.c_str(); }
+
+size_t apt_workspace_size(int32_t op, int64_t n, int32_t n_pairs, int32_t n_rep) {
+    (void)n_pairs;
+    (void)n_rep;
+    if (n < 0 || n >= (int64_t)0xFFFFFFFFll) return 0;
+    switch (op) {
+        case APT_OP_RDF:
+        case APT_OP_KNN:
+        case APT_OP_KNN_RDF:
+            return carve_plain(nullptr, n).bytes;
+        default:
+            return 0;
+    }
+}
+
+apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_targets, void* ws, size_t ws_bytes,
+                             void* stream) {
+    apt_status s;
+    if ((s = check_cloud(cloud)) != APT_OK) return s;
+    if ((s = check_query(q)) != APT_OK) return s;
+    if (!n_targets) return fail(APT_E_ARG, "n_targets is NULL");
+    PlainWs w = carve_plain(ws, cloud->n);
+    if ((s = check_ws(ws, ws_bytes, w.bytes)) != APT_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    const int G = count_blocks(cloud->n);
+    CountArgs ca{cloud->xyz, cloud->lab, cloud->d_bnd, cloud->n, count_chunk(cloud->n, G), q.target, q.neighbor,
+                 q.d_srf, nullptr, w.part_cnt, w.part_bbox, w.part_nf};
+    hipLaunchKernelGGL(k_count, dim3(G), dim3(kBlock), 0, st, ca);
+    PlanParams pp{1.0f, 4.0f, 0, cell_cap_for(cloud->n)};
+    PlanArgs pa{G, w.part_cnt, w.part_bbox, w.part_nf, w.part_off, pp, nullptr, w.plan, nullptr};
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, pa);
+    FinishArgs fa{w.plan, -1, n_targets, nullptr};
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, st, fa);
+    return hip_check("count launch");
+}
+
+apt_status apt_rdf(const apt_cloud* cloud, apt_query q, apt_bins bins, uint64_t* hist, int32_t* status,
+                   void* ws, size_t ws_bytes, void* stream) {
+    return run_plain(cloud, q, &bins, hist, 0, INFINITY, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                     nullptr, status, ws, ws_bytes, stream);
+}
+
+apt_status apt_knn(const apt_cloud* cloud, apt_query q, int32_t k, float r_knn_max, int64_t capacity,
+                   int64_t* target_id, float* dist, int64_t* nbr_id, apt_bins knn_bins, uint64_t* knn_hist,
+                   int64_t* n_targets, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+    if (k < 1) return fail(APT_E_ARG, "k must be >= 1");
+    return run_plain(cloud, q, nullptr, nullptr, k, r_knn_max, capacity, target_id, dist, nbr_id, &knn_bins,
+                     knn_hist, n_targets, status, ws, ws_bytes, stream);
+}
+
+apt_status apt_knn_rdf(const apt_cloud* cloud, apt_query q, apt_bins rdf_bins, uint64_t* rdf_hist, int32_t k,
+                       float r_knn_max, int64_t capacity, int64_t* target_id, float* dist, int64_t* nbr_id,
+                       apt_bins knn_bins, uint64_t* knn_hist, int64_t* n_targets, int32_t* status, void* ws,
+                       size_t ws_bytes, void* stream) {
+    if (k < 1) return fail(APT_E_ARG, "k must be >= 1");
+    return run_plain(cloud, q, &rdf_bins, rdf_hist, k, r_knn_max, capacity, target_id, dist, nbr_id,
+                     &knn_bins, knn_hist, n_targets, status, ws, ws_bytes, stream);
+}
+
+}  // extern "C"

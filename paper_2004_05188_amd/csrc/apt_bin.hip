@@ -1,0 +1,503 @@
+// Cell binning of a point cloud on the GPU: bounding box and counts, the
+// device-side grid plan, stable compaction of targets and neighbours, an LSD
+// radix sort on uniform-grid cell ids, and the gather into coalesced SoA
+// arrays with per-cell start offsets.
+//
+// The paper splits the cloud into regions with one array per ion type
+// (Methods: "Spatial splitting"; Supplementary: "Effectiveness of the
+// spatial splitting for heterogeneous datasets") and accelerates constant-
+// time point queries with a regular binning (Supplementary: "Details on
+// efficient spatial indices").  Here the regions are the cells of one
+// uniform grid over the neighbour species, sorted so that each row of cells
+// along x is one contiguous range of memory.
+#include "apt_bin.hpp"
+
+namespace apt {
+
+// ------------------------------------------------------------------------
+// 1. counts and bounding box.  Block b owns ions [b*chunk, (b+1)*chunk),
+//    striped over threads for coalesced loads.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_count(CountArgs a) {
+    const int64_t beg = (int64_t)blockIdx.x * a.chunk;
+    int64_t end = beg + a.chunk;
+    if (end > a.n) end = a.n;
+    uint32_t nt = 0, nb = 0;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int nf = 0;
+    const double sd = a.zscale ? *a.zscale : 1.0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
+        const uint8_t l = a.lab[i];
+        const bool isT = (a.A == APT_ANY || l == a.A) && (a.d_bnd == nullptr || a.d_bnd[i] >= a.d_srf);
+        const bool isB = (a.B == APT_ANY || l == a.B);
+        nt += isT;
+        nb += isB;
+        float p[3] = {a.xyz[3 * i], a.xyz[3 * i + 1], a.xyz[3 * i + 2]};
+        if (a.zscale) p[2] = (float)((double)p[2] * sd);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (isfinite(p[c])) {
+                lo[c] = fminf(lo[c], p[c]);
+                hi[c] = fmaxf(hi[c], p[c]);
+            } else {
+                nf = 1;
+            }
+        }
+    }
+    // block reduction through LDS
+    __shared__ float s_lo[3][kWavesPerBlock], s_hi[3][kWavesPerBlock];
+    __shared__ uint32_t s_nt[kWavesPerBlock], s_nb[kWavesPerBlock];
+    __shared__ int s_nf[kWavesPerBlock];
+    nt = wave_sum(nt);
+    nb = wave_sum(nb);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            lo[c] = fminf(lo[c], __shfl_xor(lo[c], d, kWave));
+            hi[c] = fmaxf(hi[c], __shfl_xor(hi[c], d, kWave));
+        }
+    nf = __any(nf) ? 1 : 0;
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+        for (int c = 0; c < 3; ++c) { s_lo[c][w] = lo[c]; s_hi[c][w] = hi[c]; }
+        s_nt[w] = nt;
+        s_nb[w] = nb;
+        s_nf[w] = nf;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < kWavesPerBlock; ++v) {
+            for (int c = 0; c < 3; ++c) {
+                s_lo[c][0] = fminf(s_lo[c][0], s_lo[c][v]);
+                s_hi[c][0] = fmaxf(s_hi[c][0], s_hi[c][v]);
+            }
+            s_nt[0] += s_nt[v];
+            s_nb[0] += s_nb[v];
+            s_nf[0] |= s_nf[v];
+        }
+        float* pb = a.part_bbox + 6 * blockIdx.x;
+        for (int c = 0; c < 3; ++c) { pb[c] = s_lo[c][0]; pb[3 + c] = s_hi[c][0]; }
+        a.part_cnt[2 * blockIdx.x] = s_nt[0];
+        a.part_cnt[2 * blockIdx.x + 1] = s_nb[0];
+        a.part_nf[blockIdx.x] = s_nf[0];
+    }
+}
+
+// ------------------------------------------------------------------------
+// 2. plan: reduce the block partials, scan the counts, choose the grid.
+// ------------------------------------------------------------------------
+__device__ uint32_t block_excl_scan_1024(uint32_t v, uint32_t* tmp, uint32_t* total) {
+    // 1024 threads = 16 wavefronts
+    const int w = threadIdx.x / kWave, l = lane_id();
+    uint32_t inc = wave_incl_scan(v);
+    if (l == kWave - 1) tmp[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        uint32_t x = l < 16 ? tmp[l] : 0u;
+        uint32_t xs = wave_incl_scan(x);
+        if (l < 16) tmp[16 + l] = xs - x;
+        if (l == 15) tmp[32] = xs;
+    }
+    __syncthreads();
+    uint32_t r = inc - v + tmp[16 + w];
+    *total = tmp[32];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
+    __shared__ uint32_t tmp[64];
+    __shared__ float s_box[6][16];
+    __shared__ int s_nf[16];
+    const int t = threadIdx.x, w = t / kWave;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int nf = 0;
+    uint32_t ct = 0, cb = 0;
+    if (t < a.G) {
+        const float* pb = a.part_bbox + 6 * t;
+        for (int c = 0; c < 3; ++c) { lo[c] = pb[c]; hi[c] = pb[3 + c]; }
+        nf = a.part_nf[t];
+        ct = a.part_cnt[2 * t];
+        cb = a.part_cnt[2 * t + 1];
+    }
+    uint32_t totT, totB;
+    uint32_t ot = block_excl_scan_1024(ct, tmp, &totT);
+    uint32_t ob = block_excl_scan_1024(cb, tmp, &totB);
+    if (t < a.G) {
+        a.part_off[2 * t] = ot;
+        a.part_off[2 * t + 1] = ob;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            lo[c] = fminf(lo[c], __shfl_xor(lo[c], d, kWave));
+            hi[c] = fmaxf(hi[c], __shfl_xor(hi[c], d, kWave));
+        }
+    nf = __any(nf) ? 1 : 0;
+    if (lane_id() == 0) {
+        for (int c = 0; c < 3; ++c) { s_box[c][w] = lo[c]; s_box[3 + c][w] = hi[c]; }
+        s_nf[w] = nf;
+    }
+    __syncthreads();
+    if (t != 0) return;
+    for (int v = 1; v < 16; ++v)
+        for (int c = 0; c < 3; ++c) {
+            s_box[c][0] = fminf(s_box[c][0], s_box[c][v]);
+            s_box[3 + c][0] = fmaxf(s_box[3 + c][0], s_box[3 + c][v]);
+            s_nf[0] |= s_nf[v];
+        }
+    GridPlan P;
+    double ext[3];
+    double amax = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        float l = s_box[c][0], h = s_box[3 + c][0];
+        if (!(l <= h)) { l = 0.0f; h = 0.0f; }    // no finite position at all
+        P.lo[c] = l;
+        P.hi[c] = h;
+        ext[c] = (double)h - (double)l;          // exact-ish, never overflows in FP64
+        amax = fmax(amax, fmax(fabs((double)l), fabs((double)h)));
+    }
+    const PlanParams& pp = a.pp;
+    // cell edge: at least h_min, and large enough to hold ~occ neighbours
+    double vol = 1.0;
+    for (int c = 0; c < 3; ++c) vol *= fmax(ext[c], 1e-3);
+    const double rho = (double)(totB > 0 ? totB : 1) / vol;
+    const double emax = fmax(ext[0], fmax(ext[1], ext[2]));
+    double h = fmax((double)pp.h_min, cbrt((double)pp.occ / rho));
+    if (totB == 0 || !(h > 0.0)) h = emax + 1.0;
+    if (h < 1e-6 * (emax + 1.0)) h = 1e-6 * (emax + 1.0);
+    if (h > 3.0e38) h = 3.0e38;
+    for (;;) {
+        // the cell count with the FP32 edge actually used
+        const double hf = (double)(float)h;
+        double cells = 1.0;
+        for (int c = 0; c < 3; ++c) cells *= floor(ext[c] / hf) + 1.0;
+        if (cells <= (double)pp.cell_cap || h >= 3.0e38) break;
+        h = fmin(h * 1.25, 3.0e38);               // finite ext: terminates
+    }
+    P.h = (float)h;
+    P.inv_h = (float)(1.0 / (double)P.h);
+    uint64_t ncell = 1;
+    for (int c = 0; c < 3; ++c) {
+        P.dim[c] = (int32_t)(floor(ext[c] / (double)P.h) + 1.0);
+        ncell *= (uint64_t)P.dim[c];
+    }
+    P.n_cells = (uint32_t)ncell;
+    P.nT = totT;
+    P.nB = totB;
+    uint32_t passes = 1;
+    while (passes < 4 && ((P.n_cells - 1u) >> (8u * passes)) != 0u) ++passes;
+    P.passes = passes;
+    // (x - lo) * inv_h in FP32 misplaces a point by at most ~3 ulps of the
+    // extent; cull with a margin well above that
+    P.eps = (float)fmin(fmax(1e-5, 8.0 * 5.9604645e-8 * (emax + amax)), 3.0e38);
+    const double hd = (double)P.h;
+    const double diag = sqrt((ext[0] + hd) * (ext[0] + hd) + (ext[1] + hd) * (ext[1] + hd) +
+                             (ext[2] + hd) * (ext[2] + hd));
+    P.r_all = (float)fmin(diag + 2.0 * hd, 3.0e38);
+    if (pp.k > 0) {
+        double r = 1.15 * cbrt(3.0 * ((double)pp.k + 0.5) / (4.0 * M_PI * rho));
+        P.rk0 = (float)fmin(r, (double)P.r_all);
+    } else {
+        P.rk0 = 0.0f;
+    }
+    P.zscale = a.zscale ? (float)*a.zscale : 1.0f;
+    P.nonfinite = s_nf[0];
+    P.pad[0] = P.pad[1] = 0;
+    *a.plan = P;
+    if (s_nf[0] && a.status) atomicOr(a.status, APT_STATUS_NONFINITE);
+}
+
+// ------------------------------------------------------------------------
+// 3. stable compaction of target and neighbour indices
+// ------------------------------------------------------------------------
+constexpr int kCompactItems = 16;
+constexpr int kCompactTile = kBlock * kCompactItems;
+
+__global__ __launch_bounds__(kBlock) void k_compact(CompactArgs a) {
+    __shared__ uint32_t s_cnt[2][kCompactItems][kWavesPerBlock];
+    __shared__ uint32_t s_base[2][kCompactItems][kWavesPerBlock];
+    __shared__ uint32_t s_run[2];
+    const int w = threadIdx.x / kWave;
+    const int64_t beg = (int64_t)blockIdx.x * a.chunk;
+    int64_t end = beg + a.chunk;
+    if (end > a.n) end = a.n;
+    if (threadIdx.x == 0) {
+        s_run[0] = a.part_off[2 * blockIdx.x];
+        s_run[1] = a.part_off[2 * blockIdx.x + 1];
+    }
+    __syncthreads();
+    for (int64_t tile = beg; tile < end; tile += kCompactTile) {
+        uint64_t mt[kCompactItems], mb[kCompactItems];
+#pragma unroll
+        for (int it = 0; it < kCompactItems; ++it) {
+            const int64_t i = tile + (int64_t)it * kBlock + threadIdx.x;
+            bool isT = false, isB = false;
+            if (i < end) {
+                const uint8_t l = a.lab[i];
+                isT = (a.A == APT_ANY || l == a.A) && (a.d_bnd == nullptr || a.d_bnd[i] >= a.d_srf);
+                isB = a.bsel != nullptr && (a.B == APT_ANY || l == a.B);
+            }
+            mt[it] = __ballot(isT);
+            mb[it] = __ballot(isB);
+            if (lane_id() == 0) {
+                s_cnt[0][it][w] = __popcll(mt[it]);
+                s_cnt[1][it][w] = __popcll(mb[it]);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < kWave) {
+            // exclusive scan over (item, wave) in index order, for both lists
+            const int l = lane_id();
+            for (int q = 0; q < 2; ++q) {
+                uint32_t x = s_cnt[q][l / kWavesPerBlock][l % kWavesPerBlock];
+                uint32_t xs = wave_incl_scan(x);
+                s_base[q][l / kWavesPerBlock][l % kWavesPerBlock] = xs - x + s_run[q];
+                uint32_t tot = readlane(xs, kWave - 1);
+                wave_sync();
+                if (l == 0) s_run[q] += tot;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kCompactItems; ++it) {
+            const int64_t i = tile + (int64_t)it * kBlock + threadIdx.x;
+            const uint64_t bit = 1ull << lane_id();
+            if (mt[it] & bit) a.tid[s_base[0][it][w] + __popcll(mt[it] & lanemask_lt())] = (uint32_t)i;
+            if (mb[it] & bit) a.bsel[s_base[1][it][w] + __popcll(mb[it] & lanemask_lt())] = (uint32_t)i;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------
+// 4. cell keys
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_keys(KeyArgs a) {
+    const GridPlan P = *a.plan;
+    const uint32_t n = a.count_is_T ? P.nT : P.nB;
+    const double sd = a.zscale ? *a.zscale : 1.0;
+    for (uint32_t j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock) {
+        const uint32_t id = a.src ? a.src[j] : j;
+        float x = a.xyz[3 * (size_t)id], y = a.xyz[3 * (size_t)id + 1], z = a.xyz[3 * (size_t)id + 2];
+        if (a.zscale) z = (float)((double)z * sd);
+        a.keys[j] = cell_id(P, x, y, z);
+        a.vals[j] = a.val_is_index ? j : id;
+    }
+}
+
+// ------------------------------------------------------------------------
+// 5. LSD radix sort of (cell id, value) pairs, 8-bit digits, stable.
+//    Block b sorts its chunk tile by tile; digits of a tile are ranked
+//    inside each wavefront with ballots, then placed through LDS so that
+//    the global writes of one digit are contiguous.
+// ------------------------------------------------------------------------
+constexpr int kRsItems = 8;
+constexpr int kRsTile = kBlock * kRsItems;   // 2048
+constexpr int kRadix = 256;
+
+__device__ __forceinline__ bool rs_active(const GridPlan& P, int pass) { return (uint32_t)pass < P.passes; }
+
+__device__ __forceinline__ void rs_chunk(uint32_t n, int G, uint32_t* chunk) {
+    uint32_t c = (n + (uint32_t)G - 1u) / (uint32_t)G;
+    *chunk = (c + kRsTile - 1u) / kRsTile * kRsTile;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortArgs a) {
+    const GridPlan P = *a.plan;
+    if (!rs_active(P, a.pass)) return;
+    const uint32_t n = a.count_is_T ? P.nT : P.nB;
+    const uint32_t* __restrict__ keys = a.keys[a.pass & 1];
+    __shared__ uint32_t s_h[kWavesPerBlock][kRadix];
+    for (int i = threadIdx.x; i < kWavesPerBlock * kRadix; i += kBlock) (&s_h[0][0])[i] = 0;
+    __syncthreads();
+    uint32_t chunk;
+    rs_chunk(n, gridDim.x, &chunk);
+    const uint64_t beg = (uint64_t)blockIdx.x * chunk;
+    uint64_t end = beg + chunk;
+    if (end > n) end = n;
+    const int w = threadIdx.x / kWave;
+    const uint32_t shift = 8u * (uint32_t)a.pass;
+    for (uint64_t i = beg + threadIdx.x; i < end; i += kBlock)
+        atomicAdd(&s_h[w][(keys[i] >> shift) & 0xFFu], 1u);
+    __syncthreads();
+    for (int d = threadIdx.x; d < kRadix; d += kBlock) {
+        uint32_t s = 0;
+        for (int v = 0; v < kWavesPerBlock; ++v) s += s_h[v][d];
+        a.counts[(size_t)d * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// exclusive scan of counts[256 * G] (digit-major) in one workgroup
+__global__ __launch_bounds__(1024) void k_rs_scan(SortArgs a) {
+    const GridPlan P = *a.plan;
+    if (!rs_active(P, a.pass)) return;
+    __shared__ uint32_t tmp[64];
+    const size_t total = (size_t)kRadix * a.G;
+    const size_t per = (total + 1023) / 1024;
+    const size_t b0 = threadIdx.x * per;
+    size_t b1 = b0 + per;
+    if (b1 > total) b1 = total;
+    uint32_t s = 0;
+    for (size_t i = b0; i < b1; ++i) s += a.counts[i];
+    uint32_t tot;
+    uint32_t off = block_excl_scan_1024(s, tmp, &tot);
+    for (size_t i = b0; i < b1; ++i) {
+        uint32_t c = a.counts[i];
+        a.counts[i] = off;
+        off += c;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortArgs a) {
+    const GridPlan P = *a.plan;
+    if (!rs_active(P, a.pass)) return;
+    const uint32_t n = a.count_is_T ? P.nT : P.nB;
+    const uint32_t* __restrict__ kin = a.keys[a.pass & 1];
+    const uint32_t* __restrict__ vin = a.vals[a.pass & 1];
+    uint32_t* __restrict__ kout = a.keys[(a.pass + 1) & 1];
+    uint32_t* __restrict__ vout = a.vals[(a.pass + 1) & 1];
+    const uint32_t shift = 8u * (uint32_t)a.pass;
+
+    __shared__ uint32_t s_key[kRsTile];
+    __shared__ uint32_t s_val[kRsTile];
+    __shared__ uint32_t s_wcnt[kWavesPerBlock][kRadix];
+    __shared__ uint32_t s_lstart[kRadix];
+    __shared__ uint32_t s_tot[kRadix];
+    __shared__ uint32_t s_run[kRadix];
+    __shared__ uint32_t s_tmp[16];
+
+    uint32_t chunk;
+    rs_chunk(n, gridDim.x, &chunk);
+    const uint64_t beg = (uint64_t)blockIdx.x * chunk;
+    uint64_t end = beg + chunk;
+    if (end > n) end = n;
+    const int t = threadIdx.x, w = t / kWave, l = lane_id();
+    for (int d = t; d < kRadix; d += kBlock) s_run[d] = a.counts[(size_t)d * gridDim.x + blockIdx.x];
+    __syncthreads();
+
+    for (uint64_t tile = beg; tile < end; tile += kRsTile) {
+        for (int i = t; i < kWavesPerBlock * kRadix; i += kBlock) (&s_wcnt[0][0])[i] = 0;
+        __syncthreads();
+        uint32_t key[kRsItems], val[kRsItems], pos[kRsItems];
+        bool ok[kRsItems];
+#pragma unroll
+        for (int j = 0; j < kRsItems; ++j) {
+            const uint64_t i = tile + (uint64_t)w * (kRsItems * kWave) + (uint64_t)j * kWave + l;
+            ok[j] = i < end;
+            key[j] = ok[j] ? kin[i] : 0u;
+            val[j] = ok[j] ? vin[i] : 0u;
+            const uint32_t d = (key[j] >> shift) & 0xFFu;
+            uint64_t peers = __ballot(ok[j]);
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                const uint64_t b = __ballot((d >> bit) & 1u);
+                peers &= ((d >> bit) & 1u) ? b : ~b;
+            }
+            const uint32_t before = s_wcnt[w][d];
+            wave_sync();
+            pos[j] = before + (uint32_t)__popcll(peers & lanemask_lt());
+            if (ok[j] && (peers & lanemask_lt()) == 0) s_wcnt[w][d] = before + (uint32_t)__popcll(peers);
+            wave_sync();
+        }
+        __syncthreads();
+        // per-digit totals of the tile and wave prefixes
+        uint32_t tot = 0;
+        for (int d = t; d < kRadix; d += kBlock) {
+            uint32_t acc = 0;
+            for (int v = 0; v < kWavesPerBlock; ++v) {
+                const uint32_t c = s_wcnt[v][d];
+                s_wcnt[v][d] = acc;
+                acc += c;
+            }
+            s_tot[d] = acc;
+            tot = acc;
+        }
+        // exclusive scan of the 256 digit totals (kBlock == kRadix)
+        {
+            uint32_t inc = wave_incl_scan(tot);
+            if (l == kWave - 1) s_tmp[w] = inc;
+            __syncthreads();
+            uint32_t add = 0;
+            for (int v = 0; v < w; ++v) add += s_tmp[v];
+            s_lstart[t] = inc - tot + add;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kRsItems; ++j) {
+            if (!ok[j]) continue;
+            const uint32_t d = (key[j] >> shift) & 0xFFu;
+            const uint32_t lp = s_lstart[d] + s_wcnt[w][d] + pos[j];
+            s_key[lp] = key[j];
+            s_val[lp] = val[j];
+        }
+        __syncthreads();
+        const uint32_t cnt = (uint32_t)((end - tile) < (uint64_t)kRsTile ? (end - tile) : kRsTile);
+#pragma unroll
+        for (int j = 0; j < kRsItems; ++j) {
+            const uint32_t idx = (uint32_t)(j * kBlock + t);
+            if (idx < cnt) {
+                const uint32_t k = s_key[idx];
+                const uint32_t d = (k >> shift) & 0xFFu;
+                const uint32_t g = s_run[d] + (idx - s_lstart[d]);
+                kout[g] = k;
+                vout[g] = s_val[idx];
+            }
+        }
+        __syncthreads();
+        for (int d = t; d < kRadix; d += kBlock) s_run[d] += s_tot[d];
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------
+// 6. copy of the sorted target order out of the sort buffers
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_take_order(OrderArgs a) {
+    const GridPlan P = *a.plan;
+    const uint32_t* __restrict__ v = a.vals[P.passes & 1];
+    for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < P.nT; t += gridDim.x * kBlock) a.order[t] = v[t];
+}
+
+// ------------------------------------------------------------------------
+// 7. gather into SoA and cell start offsets
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
+    const GridPlan P = *a.plan;
+    const uint32_t* __restrict__ key = a.keys[P.passes & 1];
+    const uint32_t* __restrict__ val = a.vals[P.passes & 1];
+    const uint32_t nB = P.nB, nc = P.n_cells;
+    const double sd = a.zscale ? *a.zscale : 1.0;
+    const uint32_t stride = gridDim.x * kBlock;
+    if (nB == 0) {
+        for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c <= nc; c += stride) a.cell_start[c] = 0;
+        return;
+    }
+    for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < nB; p += stride) {
+        const uint32_t id = val[p];
+        float z = a.xyz[3 * (size_t)id + 2];
+        if (a.zscale) z = (float)((double)z * sd);
+        a.bx[p] = a.xyz[3 * (size_t)id];
+        a.by[p] = a.xyz[3 * (size_t)id + 1];
+        a.bz[p] = z;
+        const uint32_t c = key[p];
+        const uint32_t cprev = p == 0 ? 0u : key[p - 1] + 1u;
+        for (uint32_t q = cprev; q <= c; ++q) a.cell_start[q] = p;
+        if (p == nB - 1)
+            for (uint32_t q = c + 1; q <= nc; ++q) a.cell_start[q] = nB;
+    }
+}
+
+// ------------------------------------------------------------------------
+// 8. squared bin edges, e_b = b * r_max / n_bins in FP64
+// ------------------------------------------------------------------------
+__global__ void k_edges(double* E2, float r_max, int n_bins) {
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b <= n_bins; b += gridDim.x * blockDim.x) {
+        const double e = __ddiv_rn(__dmul_rn((double)b, (double)r_max), (double)n_bins);
+        E2[b] = __dmul_rn(e, e);
+    }
+}
+
+}  // namespace apt

@@ -1,0 +1,95 @@
+// Kernel argument blocks of the binning stage (see apt_bin.hip).
+#pragma once
+#include "apt_internal.hpp"
+
+namespace apt {
+
+struct CountArgs {
+    const float* xyz;
+    const uint8_t* lab;
+    const float* d_bnd;
+    int64_t n;
+    int64_t chunk;
+    int32_t A, B;
+    float d_srf;
+    const double* zscale;   // NULL: unscaled
+    uint32_t* part_cnt;     // [G][2] targets, neighbours
+    float* part_bbox;       // [G][6]
+    int32_t* part_nf;       // [G]
+};
+
+struct PlanArgs {
+    int32_t G;              // number of count blocks (<= 1024)
+    const uint32_t* part_cnt;
+    const float* part_bbox;
+    const int32_t* part_nf;
+    uint32_t* part_off;     // [G][2] exclusive offsets (out)
+    PlanParams pp;
+    const double* zscale;
+    GridPlan* plan;
+    int32_t* status;
+};
+
+struct CompactArgs {
+    const uint8_t* lab;
+    const float* d_bnd;
+    int64_t n;
+    int64_t chunk;
+    int32_t A, B;
+    float d_srf;
+    const uint32_t* part_off;
+    uint32_t* tid;          // [nT]
+    uint32_t* bsel;         // [nB] or NULL (neighbours = all ions)
+};
+
+struct KeyArgs {
+    const GridPlan* plan;
+    const float* xyz;
+    const uint32_t* src;    // index list or NULL (identity)
+    const double* zscale;
+    int32_t count_is_T;     // count = plan->nT (else plan->nB)
+    int32_t val_is_index;   // value = list position (else the ion index)
+    uint32_t* keys;
+    uint32_t* vals;
+};
+
+struct SortArgs {
+    const GridPlan* plan;
+    int32_t count_is_T;
+    int32_t pass;
+    int32_t G;
+    uint32_t* keys[2];
+    uint32_t* vals[2];
+    uint32_t* counts;       // [256][G]
+};
+
+struct OrderArgs {
+    const GridPlan* plan;
+    uint32_t* vals[2];
+    uint32_t* order;
+};
+
+struct GatherArgs {
+    const GridPlan* plan;
+    const float* xyz;
+    const double* zscale;
+    uint32_t* keys[2];
+    uint32_t* vals[2];
+    float* bx;
+    float* by;
+    float* bz;
+    uint32_t* cell_start;   // [n_cells + 1]
+};
+
+__global__ void k_count(CountArgs a);
+__global__ void k_plan(PlanArgs a);
+__global__ void k_compact(CompactArgs a);
+__global__ void k_keys(KeyArgs a);
+__global__ void k_rs_upsweep(SortArgs a);
+__global__ void k_rs_scan(SortArgs a);
+__global__ void k_rs_downsweep(SortArgs a);
+__global__ void k_take_order(OrderArgs a);
+__global__ void k_gather(GatherArgs a);
+__global__ void k_edges(double* E2, float r_max, int n_bins);
+
+}  // namespace apt

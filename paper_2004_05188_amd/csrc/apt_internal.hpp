@@ -1,0 +1,126 @@
+// Internal declarations of the GPU library: the device-side plan of the
+// uniform cell grid, wavefront helpers and the exact FP64 bin decision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "apt_stat.h"
+
+namespace apt {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;                 // 4 wavefronts per workgroup
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kXcd = 8;                      // MI355X: 8 XCDs, workgroups dealt round-robin
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// Device-resident description of the cell grid of one call, written by
+// k_plan and read by every later kernel (launch grids do not depend on it).
+struct GridPlan {
+    float lo[3];        // bounding box of all finite positions
+    float hi[3];
+    float h;            // cell edge (nm)
+    float inv_h;
+    int32_t dim[3];     // cells per axis
+    uint32_t n_cells;
+    uint32_t nT;        // eligible targets
+    uint32_t nB;        // neighbour ions
+    uint32_t passes;    // active radix passes over the cell ids
+    float eps;          // culling margin covering FP32 cell-assignment error (nm)
+    float r_all;        // a radius that reaches every cell from any point of the box
+    float rk0;          // first kNN search radius
+    float zscale;       // z scale applied to positions (1 for the plain path)
+    int32_t nonfinite;
+    uint32_t pad[2];
+};
+
+// Host-chosen parameters of the plan.
+struct PlanParams {
+    float h_min;        // smallest cell edge
+    float occ;          // aimed-for neighbours per cell
+    int32_t k;          // kNN order (0: no kNN)
+    uint32_t cell_cap;  // largest number of cells the workspace holds
+};
+
+// ---------------------------------------------------------------- waves --
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <class T>
+__device__ __forceinline__ T readlane(T v, int lane) {
+    static_assert(sizeof(T) == 4, "32-bit readlane");
+    int r = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane);
+    return __builtin_bit_cast(T, r);
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t o = __shfl_up(v, d, kWave);
+        if (l >= d) v += o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// ------------------------------------------------------------- cells --
+__device__ __forceinline__ int cell_axis(const GridPlan& P, int a, float x) {
+    float f = (x - P.lo[a]) * P.inv_h;
+    if (!(f >= 0.0f)) return 0;                       // also catches NaN
+    if (f >= (float)(P.dim[a] - 1)) return P.dim[a] - 1;
+    return (int)f;
+}
+
+__device__ __forceinline__ uint32_t cell_id(const GridPlan& P, float x, float y, float z) {
+    return ((uint32_t)cell_axis(P, 2, z) * (uint32_t)P.dim[1] + (uint32_t)cell_axis(P, 1, y)) *
+               (uint32_t)P.dim[0] + (uint32_t)cell_axis(P, 0, x);
+}
+
+// ------------------------------------------------------- exact binning --
+// FP64 squared distance of two stored FP32 positions, no fused operations.
+__device__ __forceinline__ double exact_D2(float xi, float yi, float zi, float xj, float yj, float zj) {
+    double dx = __dsub_rn((double)xj, (double)xi);
+    double dy = __dsub_rn((double)yj, (double)yi);
+    double dz = __dsub_rn((double)zj, (double)zi);
+    return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
+// Largest b with E2[b] <= D2, or n_bins when D2 >= E2[n_bins].
+__device__ __forceinline__ int exact_bin(double D2, const double* __restrict__ E2, int n_bins,
+                                         double inv_w) {
+    if (!(D2 < E2[n_bins])) return n_bins;
+    int b = (int)(sqrt(D2) * inv_w);
+    if (b < 0) b = 0;
+    if (b > n_bins - 1) b = n_bins - 1;
+    while (b > 0 && D2 < E2[b]) --b;
+    while (b < n_bins - 1 && D2 >= E2[b + 1]) ++b;
+    return b;
+}
+
+// ------------------------------------------------------ workspace plan --
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Carve {
+    char* base;
+    size_t off = 0;
+    template <class T>
+    T* take(size_t count) {
+        T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+        off += align256(count * sizeof(T));
+        return p;
+    }
+};
+
+}  // namespace apt

@@ -1,0 +1,51 @@
+// Kernel argument block of the target-neighbour pair kernel (apt_pair.hip).
+#pragma once
+#include "apt_internal.hpp"
+
+namespace apt {
+
+constexpr int kKnnCap = 512;   // per-wavefront kNN candidate buffer (u64 keys)
+
+struct PairArgs {
+    const GridPlan* plan;
+    const float* xyz;            // original positions [n][3]
+    const uint32_t* tid;         // [nT] eligible targets, ascending ion index
+    const uint32_t* order;       // [nT] target ranks in cell order
+    const float* bx;             // [nB] neighbour positions in cell order
+    const float* by;
+    const float* bz;
+    uint32_t* vals[2];           // sort buffers; vals[passes & 1] = neighbour ion index
+    const uint32_t* cell_start;  // [n_cells + 1]
+    int32_t self_possible;       // a target may also be a neighbour
+    // RDF
+    int32_t n_bins;
+    float r_enum;                // enumeration radius covering every counted pair
+    float thr2;                  // FP32 squared-distance cut of the fast path
+    float inv_w;                 // n_bins / r_max (FP32)
+    float delta_b;               // near-edge band, in bins
+    double inv_w64;
+    const double* E2;            // [n_bins + 1]
+    uint64_t* hist;              // [n_bins]
+    int32_t hist_in_lds;
+    // kNN
+    int32_t k;
+    float rknn;                  // r_knn_max (may be +inf)
+    float rknn2;                 // rknn * rknn in FP32
+    int64_t capacity;
+    int64_t* target_id;
+    float* dist;
+    int64_t* nbr_id;
+    int32_t kb_nbins;
+    double kb_inv_w64;
+    const double* KE2;           // [kb_nbins + 1] or NULL
+    uint64_t* knn_hist;          // [kb_nbins + 1] or NULL
+};
+
+// grid: multiple of 8 workgroups of kBlock threads; dynamic LDS per block:
+// (hist_in_lds ? 4 * n_bins * 4 : 0) + (knn ? 4 * kKnnCap * 8 : 0) bytes
+template <bool RDF, bool KNN>
+__global__ void k_pair(PairArgs a);
+
+size_t pair_lds_bytes(bool rdf, bool knn, int n_bins, bool hist_in_lds);
+
+}  // namespace apt

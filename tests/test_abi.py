@@ -1,0 +1,113 @@
+"""Host-side checks of the C ABI: the library loads, exports everything the
+header declares, sizes workspaces, and rejects bad arguments before any GPU
+work (these calls return before the first HIP call, so they run without a
+GPU)."""
+import ctypes
+import glob
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def aptstat():
+    import paper_2004_05188_amd as aptstat
+
+    if not os.path.exists(aptstat.library_path()):
+        aptstat.build()
+    return aptstat
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(apt_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol(aptstat):
+    L = aptstat.lib()
+    names = _declared()
+    assert {"apt_rdf", "apt_knn", "apt_knn_rdf", "apt_workspace_size", "apt_last_error"} <= names
+    for name in names:
+        assert hasattr(L, name), f"{name} declared in include/ but not exported"
+
+
+def test_no_oracle_in_the_product():
+    # the GPU library neither includes nor links the oracle
+    for src in glob.glob(os.path.join(ROOT, "paper_2004_05188_amd", "**", "*"), recursive=True):
+        if src.endswith((".hip", ".hpp", ".h", ".py")):
+            text = open(src).read()
+            assert "apt_oracle" not in text and "import oracle" not in text, src
+
+
+def test_workspace_sizes(aptstat):
+    for op in (aptstat.OP_RDF, aptstat.OP_KNN, aptstat.OP_KNN_RDF):
+        a = aptstat.lib().apt_workspace_size(op, 1000, 0, 0)
+        b = aptstat.lib().apt_workspace_size(op, 10_000_000, 0, 0)
+        assert 0 < a < b
+        assert b >= 40 * 10_000_000            # SoA, sort buffers and index lists
+    assert aptstat.lib().apt_workspace_size(99, 1000, 0, 0) == 0
+    assert aptstat.lib().apt_workspace_size(1, -1, 0, 0) == 0
+    assert aptstat.lib().apt_workspace_size(1, 1 << 32, 0, 0) == 0
+
+
+def _cloud(aptstat, n=10):
+    c = aptstat._Cloud(0x1000, 0x2000, None, n)   # never dereferenced on the host
+    return ctypes.byref(c)
+
+
+def _err(aptstat):
+    return aptstat.lib().apt_last_error().decode()
+
+
+def test_argument_validation_before_gpu_work(aptstat):
+    L = aptstat.lib()
+    q = aptstat._query(1, 1, 0.0)
+    good = aptstat._bins(2.0, 200)
+    ws = ctypes.c_void_p(0x100000)
+    big = 1 << 40
+    st = ctypes.c_void_p(0x3000)
+    h = ctypes.c_void_p(0x4000)
+    # NULL cloud
+    assert L.apt_rdf(None, q, good, h, st, ws, big, None) == -1
+    assert "cloud" in _err(aptstat)
+    # bad bins
+    for bad in (aptstat._bins(0.0, 200), aptstat._bins(-1.0, 200), aptstat._bins(math.inf, 200),
+                aptstat._bins(2.0, 0), aptstat._bins(2.0, 65537)):
+        assert L.apt_rdf(_cloud(aptstat), q, bad, h, st, ws, big, None) == -1
+    # NULL output, NULL status
+    assert L.apt_rdf(_cloud(aptstat), q, good, None, st, ws, big, None) == -1
+    assert L.apt_rdf(_cloud(aptstat), q, good, h, None, ws, big, None) == -1
+    # NaN d_srf
+    assert L.apt_rdf(_cloud(aptstat), aptstat._query(1, 1, math.nan), good, h, st, ws, big, None) == -1
+    # too many ions
+    c = aptstat._Cloud(0x1000, 0x2000, None, 1 << 32)
+    assert L.apt_rdf(ctypes.byref(c), q, good, h, st, ws, big, None) == -3
+    # workspace: NULL, misaligned, too small
+    assert L.apt_rdf(_cloud(aptstat), q, good, h, st, None, big, None) == -2
+    assert L.apt_rdf(_cloud(aptstat), q, good, h, st, ctypes.c_void_p(0x100001), big, None) == -2
+    assert L.apt_rdf(_cloud(aptstat), q, good, h, st, ws, 1024, None) == -2
+    assert "workspace" in _err(aptstat)
+
+
+def test_knn_argument_validation(aptstat):
+    L = aptstat.lib()
+    q = aptstat._query(1, 1, 0.0)
+    kb = aptstat._bins(5.0, 5000)
+    p = ctypes.c_void_p(0x5000)
+    ws, big = ctypes.c_void_p(0x100000), 1 << 40
+    args = lambda k, rk, cap, tid: (_cloud(aptstat), q, k, rk, cap, tid, p, p, kb, None, p, p, ws, big, None)
+    assert L.apt_knn(*args(0, math.inf, 10, p)) == -1          # k < 1
+    assert L.apt_knn(*args(257, math.inf, 10, p)) == -3        # k too large
+    assert L.apt_knn(*args(10, 0.0, 10, p)) == -1              # r_knn_max <= 0
+    assert L.apt_knn(*args(10, math.nan, 10, p)) == -1
+    assert L.apt_knn(*args(10, math.inf, -1, p)) == -1         # capacity < 0
+    assert L.apt_knn(*args(10, math.inf, 10, None)) == -1      # NULL rows

@@ -1,0 +1,276 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Histograms, kNN identities and target rows must be bit-exact; kNN distances
+agree within 1e-6 relative (they are the FP32 square roots of identical FP32
+squared distances).  Inputs are seeded synthetic clouds from aptsynth plus
+hand-made edge cases.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+AL, SC, SI, ANY = 0, 1, 2, 255
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+
+    import paper_2004_05188_amd as aptstat
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    aptstat.lib()
+    return aptstat, torch, aptstat.Workspace()
+
+
+def _to_dev(torch, xyz, lab, d):
+    dev = torch.device("cuda:0")
+    return (torch.from_numpy(np.ascontiguousarray(xyz, np.float32)).to(dev),
+            torch.from_numpy(np.ascontiguousarray(lab, np.uint8)).to(dev),
+            None if d is None else torch.from_numpy(np.ascontiguousarray(d, np.float32)).to(dev))
+
+
+def run_gpu(gpu, xyz, lab, d, A, B, d_srf, k=10, r_max=2.0, n_bins=200, r_knn_max=math.inf,
+            kb_rmax=5.0, kb_nbins=5000, capacity=None, want_rdf=True, k_on=True):
+    aptstat, torch, ws = gpu
+    cloud = aptstat.Cloud(*_to_dev(torch, xyz, lab, d))
+    out = {}
+    if k_on:
+        r = aptstat.knn_rdf(cloud, A, B, d_srf, k, r_max=r_max, n_bins=n_bins, r_knn_max=r_knn_max,
+                            capacity=capacity, kb_rmax=kb_rmax, kb_nbins=kb_nbins, want_rdf=want_rdf, ws=ws)
+        torch.cuda.synchronize()
+        nt = int(r.n_targets.item())
+        cap = r.target_id.shape[0] if capacity is None else capacity
+        t = min(nt, cap)
+        out.update(n_targets=nt, tid=r.target_id[:t].cpu().numpy(), dist=r.dist[:t].cpu().numpy(),
+                   nid=r.nbr_id[:t].cpu().numpy(), khist=r.knn_hist.cpu().numpy().astype(np.uint64),
+                   status=int(r.status.item()))
+        if want_rdf:
+            out["rdf"] = r.rdf_hist.cpu().numpy().astype(np.uint64)
+    else:
+        status = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+        h = aptstat.rdf(cloud, A, B, d_srf, r_max, n_bins, ws=ws, status=status)
+        torch.cuda.synchronize()
+        out.update(rdf=h.cpu().numpy().astype(np.uint64), status=int(status.item()))
+    return out
+
+
+def check_against_oracle(orc, g, xyz, lab, d, A, B, d_srf, k=10, r_max=2.0, n_bins=200,
+                         r_knn_max=math.inf, kb_rmax=5.0, kb_nbins=5000, want_rdf=True, k_on=True):
+    if want_rdf:
+        ref = orc.rdf(xyz, lab, d, A, B, d_srf, r_max, n_bins)
+        assert np.array_equal(g["rdf"], ref), f"RDF differs in {np.count_nonzero(g['rdf'] != ref)} bins"
+    if k_on:
+        tid, dist, nid, kh = orc.knn(xyz, lab, d, A, B, d_srf, k, r_knn_max, kb_rmax, kb_nbins)
+        assert g["n_targets"] == len(tid)
+        assert np.array_equal(g["tid"], tid[: len(g["tid"])])
+        assert np.array_equal(g["nid"], nid[: len(g["nid"])]), "kNN identities differ"
+        gd, od = g["dist"], dist[: len(g["dist"])]
+        assert np.array_equal(np.isinf(gd), np.isinf(od))
+        fin = np.isfinite(od)
+        assert np.all(np.abs(gd[fin] - od[fin]) <= 1e-6 * np.abs(od[fin])), "kNN distances differ"
+        assert np.array_equal(g["khist"], kh), "k-th distance histogram differs"
+
+
+# ---------------------------------------------------------------------------
+# synthetic workloads
+# ---------------------------------------------------------------------------
+
+def test_box240k_sc_sc_knn10_rdf(gpu, orc, synth):
+    _say("case box240k Sc->Sc k=10 rdf 2nm/200")
+    xyz, lab, _ = synth.box240k().generate()
+    g = run_gpu(gpu, xyz, lab, None, SC, SC, 0.0)
+    assert g["status"] == 0
+    check_against_oracle(orc, g, xyz, lab, None, SC, SC, 0.0)
+
+
+@pytest.fixture(scope="module")
+def small_needle(synth):
+    spec = synth.clustered_needle(40.0, 12.0, 8.0, noise=0.2, seed=5)
+    return spec.generate()
+
+
+@pytest.mark.parametrize("A,B,k,d_srf,r_knn_max", [
+    (SC, SC, 10, 1.0, math.inf), (SC, AL, 10, 1.0, math.inf), (SI, SC, 10, 1.0, math.inf),
+    (AL, SC, 10, 1.0, math.inf), (SC, ANY, 1, 2.0, math.inf), (ANY, SI, 3, 0.5, math.inf),
+    (SC, SI, 37, 1.0, math.inf), (SC, SC, 10, 1.0, 1.3), (SI, AL, 64, 0.0, math.inf),
+])
+def test_needle_queries(gpu, orc, small_needle, A, B, k, d_srf, r_knn_max):
+    _say(f"case needle A={A} B={B} k={k} d_srf={d_srf} rknn={r_knn_max}")
+    xyz, lab, d = small_needle
+    g = run_gpu(gpu, xyz, lab, d, A, B, d_srf, k=k, r_knn_max=r_knn_max)
+    check_against_oracle(orc, g, xyz, lab, d, A, B, d_srf, k=k, r_knn_max=r_knn_max)
+
+
+def test_rdf_only_and_knn_only_entry_points(gpu, orc, small_needle):
+    _say("case needle apt_rdf and apt_knn alone")
+    xyz, lab, d = small_needle
+    g = run_gpu(gpu, xyz, lab, d, SC, AL, 1.0, k_on=False)
+    check_against_oracle(orc, g, xyz, lab, d, SC, AL, 1.0, k_on=False)
+    g = run_gpu(gpu, xyz, lab, d, SC, SC, 1.0, want_rdf=False)
+    check_against_oracle(orc, g, xyz, lab, d, SC, SC, 1.0, want_rdf=False)
+
+
+def test_large_bin_count_uses_global_histogram(gpu, orc, small_needle):
+    _say("case needle rdf 5000 bins")
+    xyz, lab, d = small_needle
+    g = run_gpu(gpu, xyz, lab, d, SC, ANY, 1.0, k_on=False, r_max=2.5, n_bins=5000)
+    check_against_oracle(orc, g, xyz, lab, d, SC, ANY, 1.0, r_max=2.5, n_bins=5000, k_on=False)
+
+
+def test_deterministic_repeat(gpu, small_needle):
+    _say("case needle repeat determinism")
+    xyz, lab, d = small_needle
+    a = run_gpu(gpu, xyz, lab, d, SC, ANY, 1.0)
+    b = run_gpu(gpu, xyz, lab, d, SC, ANY, 1.0)
+    for key in ("rdf", "tid", "nid", "dist", "khist"):
+        assert np.array_equal(a[key], b[key])
+
+
+# ---------------------------------------------------------------------------
+# hand-made edge cases
+# ---------------------------------------------------------------------------
+
+def test_pairs_on_and_near_bin_edges(gpu, orc):
+    _say("case bin edges")
+    base = np.array([10.0, 10.0, 10.0])
+    offs = [0.5, 1.0, 1.5, 0.25, 2.0, 0.5 + 1e-6, 0.5 - 1e-6, 1.0 + 3e-7, 1.0 - 3e-7, 2.0 - 1e-6,
+            2.0 + 1e-6, 1.03, 0.01, 0.0, 1.9999999]
+    pts = [base]
+    for m, o in enumerate(offs):
+        u = np.array([math.cos(0.3 * m), math.sin(0.3 * m), 0.0])
+        pts.append(base + o * u)
+    xyz = np.array(pts, np.float32)
+    lab = np.full(len(xyz), SC, np.uint8)
+    for A, B in ((SC, SC), (SC, ANY)):
+        g = run_gpu(gpu, xyz, lab, None, A, B, 0.0, k=5)
+        check_against_oracle(orc, g, xyz, lab, None, A, B, 0.0, k=5)
+
+
+def test_coincident_ions_and_self_exclusion(gpu, orc):
+    _say("case coincident")
+    xyz = np.array([[1, 1, 1], [1, 1, 1], [1, 1, 1], [1.5, 1, 1], [3, 3, 3]], np.float32)
+    lab = np.array([SC, SC, AL, AL, SC], np.uint8)
+    for A, B in ((SC, ANY), (SC, SC), (ANY, ANY), (AL, SC)):
+        g = run_gpu(gpu, xyz, lab, None, A, B, 0.0, k=3, r_max=1.0, n_bins=10)
+        check_against_oracle(orc, g, xyz, lab, None, A, B, 0.0, k=3, r_max=1.0, n_bins=10)
+
+
+def test_fewer_than_k_empty_species_and_no_targets(gpu, orc, synth):
+    _say("case fewer than k / empty species")
+    s = synth.Specimen(shape="box", L=(6.0, 6.0, 6.0), n=500, seed=13, p_m_sc=0.2)
+    xyz, lab, d = s.generate()
+    lab = lab.copy()
+    lab[np.flatnonzero(lab == AL)[:3]] = SI                      # three Si only
+    for A, B, k in ((SC, SI, 5), (SC, 77, 4), (77, SC, 4), (SI, SI, 5)):
+        g = run_gpu(gpu, xyz, lab, d, A, B, 0.0, k=k)
+        check_against_oracle(orc, g, xyz, lab, d, A, B, 0.0, k=k)
+
+
+def test_surface_filter_inclusive_and_nan(gpu, orc, synth):
+    _say("case d_bnd filter")
+    s = synth.Specimen(shape="box", L=(8.0, 8.0, 8.0), n=3000, seed=17, p_m_sc=0.3)
+    xyz, lab, d = s.generate()
+    d = d.copy()
+    d[::7] = 1.25                    # exactly d_srf: eligible
+    d[3::11] = np.nan                # never eligible
+    g = run_gpu(gpu, xyz, lab, d, SC, ANY, 1.25)
+    check_against_oracle(orc, g, xyz, lab, d, SC, ANY, 1.25)
+
+
+def test_nonfinite_positions_flagged(gpu, orc, synth):
+    _say("case NaN/inf positions")
+    s = synth.Specimen(shape="box", L=(8.0, 8.0, 8.0), n=3000, seed=19, p_m_sc=0.3)
+    xyz, lab, d = s.generate()
+    xyz = xyz.copy()
+    xyz[5, 0] = np.nan
+    xyz[np.flatnonzero(lab == SC)[3], 2] = np.inf
+    g = run_gpu(gpu, xyz, lab, None, SC, ANY, 0.0, k=4)
+    assert g["status"] & 1
+    check_against_oracle(orc, g, xyz, lab, None, SC, ANY, 0.0, k=4)
+
+
+def test_capacity_smaller_than_targets(gpu, orc, synth):
+    _say("case capacity")
+    s = synth.Specimen(shape="box", L=(8.0, 8.0, 8.0), n=3000, seed=23, p_m_sc=0.3)
+    xyz, lab, d = s.generate()
+    g = run_gpu(gpu, xyz, lab, None, SC, SC, 0.0, k=4, capacity=50)
+    assert g["status"] & 2
+    assert len(g["tid"]) == 50
+    check_against_oracle(orc, g, xyz, lab, None, SC, SC, 0.0, k=4)
+
+
+def test_empty_and_single_ion_clouds(gpu, orc):
+    _say("case n=0 and n=1")
+    for n in (0, 1):
+        xyz = np.zeros((n, 3), np.float32) + 3.0
+        lab = np.full(n, SC, np.uint8)
+        g = run_gpu(gpu, xyz, lab, None, SC, SC, 0.0, k=2, capacity=max(n, 1))
+        assert g["n_targets"] == n
+        assert g["rdf"].sum() == 0
+        if n:
+            assert np.all(g["nid"] == -1)
+
+
+def test_fcc_lattice_ties_and_near_edge_shell(gpu, orc):
+    _say("case fcc lattice")
+    a, M = 0.404, 12
+    r = np.arange(2 * M)
+    I, J, K = np.meshgrid(r, r, r, indexing="ij")
+    keep = (I + J + K) % 2 == 0
+    xyz = (np.stack([I[keep], J[keep], K[keep]], 1) * (a / 2)).astype(np.float32)
+    rng = np.random.default_rng(3)
+    xyz = xyz[rng.permutation(len(xyz))]
+    hi = (2 * M - 1) * a / 2
+    d = np.minimum(xyz, hi - xyz).min(1).astype(np.float32)
+    lab = np.zeros(len(xyz), np.uint8)
+    g = run_gpu(gpu, xyz, lab, d, AL, AL, 2.01, k=14)
+    check_against_oracle(orc, g, xyz, lab, d, AL, AL, 2.01, k=14)
+
+
+def test_exact_lattice_index_tiebreak(gpu, orc):
+    _say("case simple cubic ties")
+    gl = np.arange(9, dtype=np.float32) * 0.5
+    X, Y, Z = np.meshgrid(gl, gl, gl, indexing="ij")
+    xyz = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1).astype(np.float32)
+    xyz = xyz[np.random.default_rng(4).permutation(len(xyz))]
+    lab = np.zeros(len(xyz), np.uint8)
+    g = run_gpu(gpu, xyz, lab, None, AL, AL, 0.0, k=9, r_max=1.5, n_bins=6)
+    check_against_oracle(orc, g, xyz, lab, None, AL, AL, 0.0, k=9, r_max=1.5, n_bins=6)
+
+
+def test_flat_cloud_and_far_outlier(gpu, orc, synth):
+    _say("case flat cloud with outlier")
+    s = synth.Specimen(shape="box", L=(30.0, 30.0, 0.001), n=5000, seed=29, p_m_sc=0.2)
+    xyz, lab, d = s.generate()
+    xyz = xyz.copy()
+    xyz[0] = (1e4, -1e4, 5e3)
+    g = run_gpu(gpu, xyz, lab, None, SC, ANY, 0.0, k=6)
+    check_against_oracle(orc, g, xyz, lab, None, SC, ANY, 0.0, k=6)
+
+
+# ---------------------------------------------------------------------------
+# full-size needle: 7 696 902 ions, the three queries of the workload
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def needle7m(synth):
+    return synth.frustum7m().generate()
+
+
+@pytest.mark.parametrize("A,B", [(SC, SC), (SC, AL), (SI, SC)])
+def test_frustum7m_queries(gpu, orc, needle7m, A, B):
+    _say(f"case frustum7m A={A} B={B} k=10 d_srf=1")
+    xyz, lab, d = needle7m
+    g = run_gpu(gpu, xyz, lab, d, A, B, 1.0, k=10)
+    assert g["status"] == 0
+    check_against_oracle(orc, g, xyz, lab, d, A, B, 1.0, k=10)

@@ -195,6 +195,26 @@ def test_eligibility_inclusive_nan_and_unfiltered_neighbours(orc):
     assert h.sum() == 3 and h[2] == 1 and h[5] == 1 and h[7] == 1
 
 
+def test_nonfinite_positions_take_part_in_no_pair(orc, synth):
+    xyz, lab, d = _small_cloud(synth, 800, 14)
+    xyz = xyz.copy()
+    sc = np.flatnonzero(lab == SC)
+    xyz[sc[0], 0] = np.nan          # a target with no neighbours
+    xyz[sc[1], 2] = np.inf          # a neighbour at infinity
+    xyz[3, 1] = -np.inf
+    for method in ("brute", "grid"):
+        tid, dist, nid, hist = orc.knn(xyz, lab, None, SC, SC, 0.0, 400, method=method)
+        assert sc[1] not in nid and 3 not in nid
+        row0 = list(tid).index(sc[0])
+        assert np.all(nid[row0] == -1)
+    a = orc.knn(xyz, lab, None, SC, ANY, 0.0, 7, method="brute")
+    b = orc.knn(xyz, lab, None, SC, ANY, 0.0, 7, method="grid")
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+    assert np.array_equal(orc.rdf(xyz, lab, None, SC, ANY, 0.0, 2.0, 40, method="brute"),
+                          orc.rdf(xyz, lab, None, SC, ANY, 0.0, 2.0, 40, method="grid"))
+
+
 def test_self_exclusion_by_index_and_coincident_ions(orc):
     xyz = np.array([[1, 1, 1], [1, 1, 1], [1.5, 1, 1]], np.float32)
     lab = np.array([SC, SC, AL], np.uint8)
