@@ -1,0 +1,197 @@
+"""Benchmark: target ions/s of kNN (k = 10) + RDF (r < 2 nm) on one MI355X.
+
+A step is one pass of the whole plain path over the workload: for each
+query of the workload, one apt_knn_rdf call (bounding box, target and
+neighbour selection, cell binning by radix sort, pair enumeration with
+RDF histogram and exact kNN rows plus the k-th distance histogram).
+Inputs are generated on the host (seeded, synthetic), copied to HBM once,
+and are resident when the timed region starts.
+
+Prints one JSON line (rank 0).  --gpus above 1 is refused: this build
+measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "target ions/s for kNN(k=10)+RDF(r≤2nm); batched vs looped replicates/s"
+AL, SC, SI, ANY = 0, 1, 2, 255
+NAMES = {AL: "Al", SC: "Sc", SI: "Si", ANY: "any"}
+
+# workload -> (generator, queries (A, B), d_srf, use the surface filter)
+WORKLOADS = {
+    "frustum7m": ("frustum7m", [(SC, SC), (SC, AL), (SI, SC)], 1.0, True),
+    "box240k": ("box240k", [(SC, SC)], 0.0, False),
+    "frustum2g": ("frustum2g", [(SC, ANY)], 2.0, True),
+}
+K, R_MAX, N_BINS, KB_RMAX, KB_NBINS = 10, 2.0, 200, 5.0, 5000
+# HBM bytes per k_pair launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
+# scaled by a plain-copy calibration; valid only for the kernel source they
+# were taken on (profiles/k_pair_frustum7m_hbm_counters.md)
+PAIR_TRAFFIC = {"frustum7m": (132.3e6, "7b8a66b9d70b7c12")}
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk (packed FMA)
+FLOP_PER_PAIR = 8                 # 3 sub, 1 mul, 2 fma per pair distance
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(spec_name, queries, d_srf, use_d, seconds_budget=25.0):
+    """The oracle (grid kNN + grid RDF, OpenMP) on a bounded sample of the workload."""
+    import numpy as np
+
+    import aptsynth
+    import oracle
+
+    spec = aptsynth.WORKLOADS[spec_name]()
+    n = spec.n
+    # the whole cloud when it fits the time budget (frustum7m: a few seconds)
+    m = min(n, 8_000_000)
+    xyz, lab, d = spec.generate(0, m)
+    d = d if use_d else None
+    targets = 0
+    t0 = time.perf_counter()
+    for A, B in queries:
+        oracle.rdf(xyz, lab, d, A, B, d_srf, R_MAX, N_BINS)
+        tid, _, _, _ = oracle.knn(xyz, lab, d, A, B, d_srf, K, kb_rmax=KB_RMAX, kb_nbins=KB_NBINS)
+        targets += len(tid)
+        if time.perf_counter() - t0 > seconds_budget:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": targets / dt, "unit": "target ions/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"first {m} of {n} ions of the workload, queries "
+                      f"{', '.join(NAMES[a] + '->' + NAMES[b] for a, b in queries)}, grid oracle "
+                      f"(RDF + kNN k={K} + k-th histogram), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="frustum7m", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (scale of the HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
+              f"(the multi-GPU sharding is described in DESIGN.md but not run)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import aptsynth
+    import paper_2004_05188_amd as aptstat
+
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4, "copy_calibration_bytes_written":
+                          b.numel() * 4, "launches": 5}), flush=True)
+        return
+
+    gen_name, queries, d_srf, use_d = WORKLOADS[args.workload]
+    spec = aptsynth.WORKLOADS[gen_name]()
+    dev = torch.device("cuda:0")
+    log(f"[bench] generating {args.workload}: {spec.n} ions")
+    t = time.perf_counter()
+    xyz, lab, d = spec.generate()
+    log(f"[bench] generated in {time.perf_counter() - t:.1f} s; copying to the GPU")
+    cloud = aptstat.Cloud(torch.from_numpy(xyz).to(dev), torch.from_numpy(lab).to(dev),
+                          torch.from_numpy(d).to(dev) if use_d else None)
+    del xyz, lab, d
+    ws = aptstat.Workspace()
+    # outputs sized once from the exact target counts (outside the timed region)
+    outs = []
+    total_targets = 0
+    for A, B in queries:
+        cap = int(aptstat.count_targets(cloud, A, d_srf, ws=ws).item())
+        total_targets += cap
+        outs.append((torch.empty(max(cap, 1), dtype=torch.int64, device=dev),
+                     torch.empty((max(cap, 1), K), dtype=torch.float32, device=dev),
+                     torch.empty((max(cap, 1), K), dtype=torch.int64, device=dev),
+                     torch.empty(KB_NBINS + 1, dtype=torch.int64, device=dev),
+                     torch.empty(1, dtype=torch.int64, device=dev),
+                     torch.empty(1, dtype=torch.int32, device=dev),
+                     torch.empty(N_BINS, dtype=torch.int64, device=dev), cap))
+
+    def step():
+        for (A, B), o in zip(queries, outs):
+            aptstat.knn_rdf(cloud, A, B, d_srf, K, r_max=R_MAX, n_bins=N_BINS, capacity=o[7],
+                            kb_rmax=KB_RMAX, kb_nbins=KB_NBINS, ws=ws, outputs=o[:7])
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # in-range pairs per step (the algorithmic unit of the pair kernel)
+    pairs = sum(int(o[6].sum().item()) for o in outs)
+    status = [int(o[5].item()) for o in outs]
+    aptstat.trace_read("pair")
+    aptstat.trace_read("binning")
+    aptstat.trace_enable(True)
+    log(f"[bench] timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    aptstat.trace_enable(False)
+    pair_ms, pair_n = aptstat.trace_read("pair")
+    bin_ms, bin_n = aptstat.trace_read("binning")
+
+    ms_per_step = 1e3 * dt / args.steps
+    value = total_targets * args.steps / dt
+    # roofline of the pair kernel: algorithmic FLOPs of the in-range pairs of
+    # one launch over its average duration
+    flop_per_launch = FLOP_PER_PAIR * pairs / len(queries)
+    pair_avg_s = (pair_ms / max(pair_n, 1)) / 1e3
+    achieved = flop_per_launch / pair_avg_s / 1e12
+    traffic = None
+    if args.workload in PAIR_TRAFFIC:
+        import hashlib
+
+        csrc = os.path.join(ROOT, "paper_2004_05188_amd", "csrc")
+        blob = b"".join(open(os.path.join(csrc, f), "rb").read()
+                        for f in ("apt_pair.hip", "apt_pair.hpp", "apt_internal.hpp"))
+        sha = hashlib.sha256(blob).hexdigest()[:16]
+        if sha == PAIR_TRAFFIC[args.workload][1]:
+            traffic = PAIR_TRAFFIC[args.workload][0]
+    line = {
+        "metric": METRIC, "value": value, "unit": "target ions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "ions": spec.n,
+                   "queries": [f"{NAMES[a]}->{NAMES[b]}" for a, b in queries], "k": K, "r_max_nm": R_MAX,
+                   "n_bins": N_BINS, "d_srf_nm": d_srf if use_d else None,
+                   "knn_hist": [0.0, KB_RMAX / KB_NBINS, KB_RMAX], "targets_per_step": total_targets},
+        "roofline": {"bound": "alu", "kernel": "k_pair", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+                     "pairs_per_launch": pairs / len(queries), "avg_launch_ms": pair_ms / max(pair_n, 1)},
+        "stages_ms_per_step": {"binning": bin_ms / args.steps, "pair": pair_ms / args.steps},
+        "in_range_pairs_per_step": pairs, "pair_evals_per_s": pairs * args.steps / (pair_ms / 1e3),
+        "status": status,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on the host")
+        line["cpu_baseline"] = cpu_baseline(gen_name, queries, d_srf, use_d)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -147,6 +147,14 @@ apt_status apt_knn_rdf(const apt_cloud* cloud, apt_query q, apt_bins rdf_bins, u
 apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_targets, void* ws,
                              size_t ws_bytes, void* stream);
 
+/* Tracing: while enabled (on != 0), every call records HIP events on its
+ * stream around its stages; apt_trace_read waits for the recorded events,
+ * returns the summed time (ms) and number of launches of one stage
+ * ("binning" = bounding box to sorted SoA, "pair" = the pair kernel) and
+ * forgets that stage's records.  Host only; off by default. */
+apt_status apt_trace_enable(int32_t on);
+apt_status apt_trace_read(const char* stage, double* ms_total, int64_t* launches);
+
 /* Text of the last host-side error of the calling thread ("" if none). */
 const char* apt_last_error(void);
 

@@ -40,6 +40,7 @@ def _load():
             build()
         L = ctypes.CDLL(_SO)
         sig = {
+            "orc_threads": ([], _i32),
             "orc_d2f": ([_p, _p], _f32),
             "orc_D2": ([_p, _p], _f64),
             "orc_edges2": ([_f32, _i32, _p], None),
@@ -74,6 +75,10 @@ def _cloud(xyz, lab, d_bnd):
         d_bnd = np.ascontiguousarray(d_bnd, dtype=np.float32).reshape(-1)
         assert d_bnd.shape[0] == xyz.shape[0]
     return xyz, lab, d_bnd
+
+
+def threads() -> int:
+    return int(_load().orc_threads())
 
 
 def d2f(a, b) -> float:

@@ -35,6 +35,15 @@
 #include <omp.h>
 #endif
 
+/* Threads the OpenMP loops of the oracle use. */
+int32_t orc_threads(void) {
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* ---------------------------------------------------------------------- */
 /* Distances                                                               */
 /* ---------------------------------------------------------------------- */

@@ -18,6 +18,9 @@ extern "C" {
 
 #define ORC_ANY 255
 
+/* Number of OpenMP threads the oracle's loops use. */
+int32_t orc_threads(void);
+
 /* Canonical distances between two stored FP32 positions. */
 float orc_d2f(const float* a, const float* b);   /* FP32, fixed evaluation order */
 double orc_D2(const float* a, const float* b);   /* FP64, no fused operations   */

@@ -53,6 +53,9 @@ _lib = None
 _SIGS = {
     "apt_workspace_size": ([ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32], ctypes.c_size_t),
     "apt_last_error": ([], ctypes.c_char_p),
+    "apt_trace_enable": ([ctypes.c_int32], ctypes.c_int),
+    "apt_trace_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+                       ctypes.c_int),
     "apt_count_targets": ([ctypes.POINTER(_Cloud), _Query, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_rdf": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_knn": ([ctypes.POINTER(_Cloud), _Query, ctypes.c_int32, ctypes.c_float, ctypes.c_int64, _P, _P, _P,
@@ -148,6 +151,18 @@ class Workspace:
         if self.buf is None or self.buf.numel() < nbytes or self.buf.device != torch.device(device):
             self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
         return self.buf
+
+
+def trace_enable(on: bool = True):
+    """Record HIP events around the stages of every following call."""
+    _check(lib().apt_trace_enable(1 if on else 0), "apt_trace_enable")
+
+
+def trace_read(stage: str):
+    """(total ms, launches) of one stage ("binning" or "pair") since the last read."""
+    ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
+    _check(lib().apt_trace_read(stage.encode(), ctypes.byref(ms), ctypes.byref(n)), "apt_trace_read")
+    return ms.value, n.value
 
 
 def workspace_size(op: int, n: int, n_pairs: int = 0, n_rep: int = 0) -> int:

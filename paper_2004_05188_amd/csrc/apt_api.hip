@@ -2,8 +2,10 @@
 // sequence of each entry point.  Nothing here allocates device memory.
 #include <math.h>
 
+#include <atomic>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "apt_bin.hpp"
 #include "apt_pair.hpp"
@@ -37,13 +39,40 @@ static DevInfo device_info() {
     return cache[dev];
 }
 
+// ------------------------------------------------------------ tracing --
+struct TraceRec {
+    std::string stage;
+    hipEvent_t a, b;
+};
+static std::mutex g_trace_mu;
+static std::vector<TraceRec> g_trace;
+static std::atomic<int> g_trace_on{0};
+
+struct TraceSpan {
+    hipEvent_t a = nullptr, b = nullptr;
+    const char* stage;
+    hipStream_t st;
+    TraceSpan(const char* s, hipStream_t stream) : stage(s), st(stream) {
+        if (!g_trace_on.load()) return;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+        (void)hipEventRecord(a, st);
+    }
+    ~TraceSpan() {
+        if (!a) return;
+        (void)hipEventRecord(b, st);
+        std::lock_guard<std::mutex> g(g_trace_mu);
+        g_trace.push_back(TraceRec{stage, a, b});
+    }
+};
+
 // ------------------------------------------------------------ sizing --
 constexpr int kCountTile = 4096;
 
+constexpr int kMaxCountBlocks = 2048;
 static int count_blocks(int64_t n) {
-    int64_t g = (n + 16 * kCountTile - 1) / (16 * kCountTile);
+    int64_t g = (n + kCountTile - 1) / kCountTile;
     if (g < 1) g = 1;
-    if (g > 1024) g = 1024;
+    if (g > kMaxCountBlocks) g = kMaxCountBlocks;
     return (int)g;
 }
 static int64_t count_chunk(int64_t n, int G) {
@@ -82,6 +111,7 @@ struct PlainWs {
     float* bz;
     uint32_t* cell_start;
     uint32_t* rs_counts;
+    uint32_t* rs_totals;
     size_t bytes;
 };
 
@@ -90,13 +120,14 @@ static PlainWs carve_plain(void* base, int64_t n) {
     PlainWs w;
     const size_t N = (size_t)(n > 0 ? n : 1);
     w.plan = c.take<GridPlan>(1);
-    w.part_cnt = c.take<uint32_t>(2 * 1024);
-    w.part_bbox = c.take<float>(6 * 1024);
-    w.part_nf = c.take<int32_t>(1024);
-    w.part_off = c.take<uint32_t>(2 * 1024);
+    w.part_cnt = c.take<uint32_t>(2 * kMaxCountBlocks);
+    w.part_bbox = c.take<float>(6 * kMaxCountBlocks);
+    w.part_nf = c.take<int32_t>(kMaxCountBlocks);
+    w.part_off = c.take<uint32_t>(2 * kMaxCountBlocks);
     w.E2 = c.take<double>(APT_MAX_BINS + 1);
     w.KE2 = c.take<double>(APT_MAX_BINS + 1);
     w.rs_counts = c.take<uint32_t>(256 * kSortBlocks);
+    w.rs_totals = c.take<uint32_t>(256);
     w.tid = c.take<uint32_t>(N);
     w.bsel = c.take<uint32_t>(N);
     w.K[0] = c.take<uint32_t>(N);
@@ -202,9 +233,10 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
     const int Gk = cus * 8;
     auto sort = [&](int is_T) {
         for (int p = 0; p < passes; ++p) {
-            SortArgs sa{w.plan, is_T, p, kSortBlocks, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.rs_counts};
+            SortArgs sa{w.plan, is_T, p, kSortBlocks, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.rs_counts,
+                        w.rs_totals};
             hipLaunchKernelGGL(k_rs_upsweep, dim3(kSortBlocks), dim3(kBlock), 0, st, sa);
-            hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(1024), 0, st, sa);
+            hipLaunchKernelGGL(k_rs_scan, dim3(256), dim3(kBlock), 0, st, sa);
             hipLaunchKernelGGL(k_rs_downsweep, dim3(kSortBlocks), dim3(kBlock), 0, st, sa);
         }
     };
@@ -261,7 +293,10 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     pp.occ = 4.0f;
     pp.k = do_knn ? k : 0;
     pp.cell_cap = cell_cap_for(cl->n);
-    if ((s = run_binning(cl, q, pp, w, status, st)) != APT_OK) return s;
+    {
+        TraceSpan span("binning", st);
+        if ((s = run_binning(cl, q, pp, w, status, st)) != APT_OK) return s;
+    }
 
     PairArgs pa{};
     pa.plan = w.plan;
@@ -316,12 +351,15 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     }
     const size_t lds = pair_lds_bytes(do_rdf, do_knn, n_bins, in_lds);
     const int Gp = device_info().cus * 8;
-    if (do_rdf && do_knn)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pair<true, true>), dim3(Gp), dim3(kBlock), lds, st, pa);
-    else if (do_rdf)
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pair<true, false>), dim3(Gp), dim3(kBlock), lds, st, pa);
-    else
-        hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pair<false, true>), dim3(Gp), dim3(kBlock), lds, st, pa);
+    {
+        TraceSpan span("pair", st);
+        if (do_rdf && do_knn)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pair<true, true>), dim3(Gp), dim3(kBlock), lds, st, pa);
+        else if (do_rdf)
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pair<true, false>), dim3(Gp), dim3(kBlock), lds, st, pa);
+        else
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pair<false, true>), dim3(Gp), dim3(kBlock), lds, st, pa);
+    }
     FinishArgs fa{w.plan, do_knn ? capacity : -1, n_targets, status};
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, st, fa);
     return hip_check("pair launch");
@@ -334,6 +372,35 @@ using namespace apt;
 extern "C" {
 
 const char* apt_last_error(void) { return g_err.c_str(); }
+
+apt_status apt_trace_enable(int32_t on) {
+    g_trace_on.store(on ? 1 : 0);
+    return APT_OK;
+}
+
+apt_status apt_trace_read(const char* stage, double* ms_total, int64_t* launches) {
+    if (!stage || !ms_total || !launches) return fail(APT_E_ARG, "apt_trace_read: NULL argument");
+    std::vector<TraceRec> mine;
+    {
+        std::lock_guard<std::mutex> g(g_trace_mu);
+        std::vector<TraceRec> rest;
+        for (auto& r : g_trace) (r.stage == stage ? mine : rest).push_back(r);
+        g_trace.swap(rest);
+    }
+    double tot = 0.0;
+    apt_status s = APT_OK;
+    for (auto& r : mine) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
+            s = fail(APT_E_HIP, "apt_trace_read: event wait failed");
+        tot += ms;
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    *ms_total = tot;
+    *launches = (int64_t)mine.size();
+    return s;
+}
 
 size_t apt_workspace_size(int32_t op, int64_t n, int32_t n_pairs, int32_t n_rep) {
     (void)n_pairs;

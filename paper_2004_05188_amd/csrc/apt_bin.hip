@@ -113,20 +113,26 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
     const int t = threadIdx.x, w = t / kWave;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     int nf = 0;
+    // thread t owns partials [t*per, (t+1)*per)
+    const int per = (a.G + 1023) / 1024;
+    const int b0 = t * per;
+    const int b1 = min(b0 + per, a.G);
     uint32_t ct = 0, cb = 0;
-    if (t < a.G) {
-        const float* pb = a.part_bbox + 6 * t;
-        for (int c = 0; c < 3; ++c) { lo[c] = pb[c]; hi[c] = pb[3 + c]; }
-        nf = a.part_nf[t];
-        ct = a.part_cnt[2 * t];
-        cb = a.part_cnt[2 * t + 1];
+    for (int b = b0; b < b1; ++b) {
+        const float* pb = a.part_bbox + 6 * b;
+        for (int c = 0; c < 3; ++c) { lo[c] = fminf(lo[c], pb[c]); hi[c] = fmaxf(hi[c], pb[3 + c]); }
+        nf |= a.part_nf[b];
+        ct += a.part_cnt[2 * b];
+        cb += a.part_cnt[2 * b + 1];
     }
     uint32_t totT, totB;
     uint32_t ot = block_excl_scan_1024(ct, tmp, &totT);
     uint32_t ob = block_excl_scan_1024(cb, tmp, &totB);
-    if (t < a.G) {
-        a.part_off[2 * t] = ot;
-        a.part_off[2 * t + 1] = ob;
+    for (int b = b0; b < b1; ++b) {
+        a.part_off[2 * b] = ot;
+        a.part_off[2 * b + 1] = ob;
+        ot += a.part_cnt[2 * b];
+        ob += a.part_cnt[2 * b + 1];
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c)
@@ -330,25 +336,36 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortArgs a) {
     }
 }
 
-// exclusive scan of counts[256 * G] (digit-major) in one workgroup
-__global__ __launch_bounds__(1024) void k_rs_scan(SortArgs a) {
+// Row scan of the digit counts: workgroup d turns counts[d][0..G) into
+// exclusive prefixes within the row and writes the row total to totals[d].
+// The downsweep adds the digit bases (a scan of the 256 totals).
+__global__ __launch_bounds__(kBlock) void k_rs_scan(SortArgs a) {
     const GridPlan P = *a.plan;
     if (!rs_active(P, a.pass)) return;
-    __shared__ uint32_t tmp[64];
-    const size_t total = (size_t)kRadix * a.G;
-    const size_t per = (total + 1023) / 1024;
-    const size_t b0 = threadIdx.x * per;
-    size_t b1 = b0 + per;
-    if (b1 > total) b1 = total;
-    uint32_t s = 0;
-    for (size_t i = b0; i < b1; ++i) s += a.counts[i];
-    uint32_t tot;
-    uint32_t off = block_excl_scan_1024(s, tmp, &tot);
-    for (size_t i = b0; i < b1; ++i) {
-        uint32_t c = a.counts[i];
-        a.counts[i] = off;
-        off += c;
+    __shared__ uint32_t s_w[kWavesPerBlock];
+    const int d = blockIdx.x, t = threadIdx.x, w = t / kWave, l = lane_id();
+    const int G = a.G;
+    const int per = (G + kBlock - 1) / kBlock;    // G <= 4096: at most 16 per thread
+    uint32_t v[16];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int b = t * per + q;
+        v[q] = (q < per && b < G) ? a.counts[(size_t)d * G + b] : 0u;
+        sum += v[q];
     }
+    const uint32_t inc = wave_incl_scan(sum);
+    if (l == kWave - 1) s_w[w] = inc;
+    __syncthreads();
+    uint32_t run = inc - sum;
+    for (int u = 0; u < w; ++u) run += s_w[u];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int b = t * per + q;
+        if (q < per && b < G) a.counts[(size_t)d * G + b] = run;
+        run += v[q];
+    }
+    if (t == kBlock - 1) a.totals[d] = run;
 }
 
 __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortArgs a) {
@@ -375,7 +392,16 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortArgs a) {
     uint64_t end = beg + chunk;
     if (end > n) end = n;
     const int t = threadIdx.x, w = t / kWave, l = lane_id();
-    for (int d = t; d < kRadix; d += kBlock) s_run[d] = a.counts[(size_t)d * gridDim.x + blockIdx.x];
+    {
+        // digit base = sum of the totals of the smaller digits (kBlock == kRadix)
+        const uint32_t tot_d = a.totals[t];
+        const uint32_t inc = wave_incl_scan(tot_d);
+        if (l == kWave - 1) s_tmp[w] = inc;
+        __syncthreads();
+        uint32_t base = inc - tot_d;
+        for (int v = 0; v < w; ++v) base += s_tmp[v];
+        s_run[t] = base + a.counts[(size_t)t * gridDim.x + blockIdx.x];
+    }
     __syncthreads();
 
     for (uint64_t tile = beg; tile < end; tile += kRsTile) {

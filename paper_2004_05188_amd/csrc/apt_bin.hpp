@@ -19,7 +19,7 @@ struct CountArgs {
 };
 
 struct PlanArgs {
-    int32_t G;              // number of count blocks (<= 1024)
+    int32_t G;              // number of count blocks (<= 4096)
     const uint32_t* part_cnt;
     const float* part_bbox;
     const int32_t* part_nf;
@@ -61,6 +61,7 @@ struct SortArgs {
     uint32_t* keys[2];
     uint32_t* vals[2];
     uint32_t* counts;       // [256][G]
+    uint32_t* totals;       // [256]
 };
 
 struct OrderArgs {
