@@ -142,6 +142,17 @@ apt_status apt_knn_rdf(const apt_cloud* cloud, apt_query q, apt_bins rdf_bins, u
                        int64_t* n_targets, int32_t* status, void* ws, size_t ws_bytes,
                        void* stream);
 
+/* Null model: out[i] = lab[pi(i)], pi = the ascending order of the keys
+ * key(i) = i-th output (i = 0, 1, ...) of SplitMix64 started from state
+ * `seed` (ties by index) -- a uniform random permutation of the labels
+ * (paper, Suppl.: "Importance of high quality random number generators";
+ * the paper's Mersenne-Twister stream is replaced by this counter-based
+ * definition).  lab, out: [n] uint8, device, may not alias.  Workspace:
+ * APT_OP_PERMUTE.  The same permutation defines the replicates of
+ * apt_rdf_batched (seed of replicate r = seeds[r]). */
+apt_status apt_permute_labels(const uint8_t* lab, int64_t n, uint64_t seed, uint8_t* out, int32_t* status,
+                              void* ws, size_t ws_bytes, void* stream);
+
 /* Number of eligible targets of a query, for sizing kNN outputs:
  * n_targets[1] (int64, device) is overwritten.  Workspace as APT_OP_KNN. */
 apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_targets, void* ws,

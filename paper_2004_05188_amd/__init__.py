@@ -57,6 +57,7 @@ _SIGS = {
     "apt_trace_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
                        ctypes.c_int),
     "apt_count_targets": ([ctypes.POINTER(_Cloud), _Query, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "apt_permute_labels": ([_P, ctypes.c_int64, ctypes.c_uint64, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_rdf": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_knn": ([ctypes.POINTER(_Cloud), _Query, ctypes.c_int32, ctypes.c_float, ctypes.c_int64, _P, _P, _P,
                  _Bins, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
@@ -197,6 +198,22 @@ def count_targets(cloud: Cloud, target: int, d_srf: float = 0.0, ws: Workspace |
     out = out if out is not None else torch.empty(1, dtype=torch.int64, device=cloud.device)
     _check(lib().apt_count_targets(cloud.c(), _query(target, ANY, d_srf), _ptr(out), _ptr(buf), nb,
                                    _stream(cloud.xyz)), "apt_count_targets")
+    return out
+
+
+def permute_labels(lab: torch.Tensor, seed: int, out: torch.Tensor | None = None,
+                   ws: Workspace | None = None, status: torch.Tensor | None = None) -> torch.Tensor:
+    """Labels reordered by the SplitMix64-key permutation of `seed` (uint8 [n])."""
+    n = lab.shape[0]
+    _need(lab, torch.uint8, (n,), "lab")
+    out = out if out is not None else torch.empty_like(lab)
+    _need(out, torch.uint8, (n,), "out")
+    ws = ws if ws is not None else Workspace()
+    nb = workspace_size(OP_PERMUTE, n)
+    buf = ws.get(nb, lab.device)
+    status = status if status is not None else torch.empty(1, dtype=torch.int32, device=lab.device)
+    _check(lib().apt_permute_labels(_ptr(lab), n, ctypes.c_uint64(seed & (2**64 - 1)), _ptr(out), _ptr(status),
+                                    _ptr(buf), nb, _stream(lab)), "apt_permute_labels")
     return out
 
 

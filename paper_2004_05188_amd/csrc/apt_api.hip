@@ -9,6 +9,7 @@
 
 #include "apt_bin.hpp"
 #include "apt_pair.hpp"
+#include "apt_perm.hpp"
 
 namespace apt {
 
@@ -105,10 +106,12 @@ struct PlainWs {
     uint32_t* bsel;
     uint32_t* K[2];
     uint32_t* V[2];
-    uint32_t* order;
-    float* bx;
-    float* by;
-    float* bz;
+    uint32_t* t_rank;
+    uint32_t* t_id;
+    float* tx;
+    float* ty;
+    float* tz;
+    float4* bpos;
     uint32_t* cell_start;
     uint32_t* rs_counts;
     uint32_t* rs_totals;
@@ -134,13 +137,72 @@ static PlainWs carve_plain(void* base, int64_t n) {
     w.V[0] = c.take<uint32_t>(N);
     w.K[1] = c.take<uint32_t>(N);
     w.V[1] = c.take<uint32_t>(N);
-    w.order = c.take<uint32_t>(N);
-    w.bx = c.take<float>(N);
-    w.by = c.take<float>(N);
-    w.bz = c.take<float>(N);
+    w.t_rank = c.take<uint32_t>(N);
+    w.t_id = c.take<uint32_t>(N);
+    w.tx = c.take<float>(N);
+    w.ty = c.take<float>(N);
+    w.tz = c.take<float>(N);
+    w.bpos = c.take<float4>(N);
     w.cell_start = c.take<uint32_t>((size_t)cell_cap_for(n) + 1);
     w.bytes = c.off;
     return w;
+}
+
+// Workspace of the label permutation for n ions and up to r replicates.
+struct PermWs {
+    uint32_t* count;
+    uint32_t* cursor;
+    uint32_t* part;
+    uint64_t* ekey;
+    uint32_t* eidx;
+    size_t bytes;
+};
+
+static PermWs carve_perm(void* base, int64_t n, int reps) {
+    Carve c{reinterpret_cast<char*>(base)};
+    PermWs w;
+    const size_t nb = (size_t)1 << perm_bucket_bits(n);
+    const size_t N = (size_t)(n > 0 ? n : 1);
+    w.count = c.take<uint32_t>(nb * reps);
+    w.cursor = c.take<uint32_t>(nb * reps);
+    w.part = c.take<uint32_t>(1024);
+    w.ekey = c.take<uint64_t>(N * reps);
+    w.eidx = c.take<uint32_t>(N * reps);
+    w.bytes = c.off;
+    return w;
+}
+
+// Permuted labels of `reps` replicates (seeds[r]) into out + r * out_stride.
+static void run_permute(const uint8_t* lab, int64_t n, const uint64_t* seeds, int reps, uint8_t* out,
+                        int64_t out_stride, const PermWs& w, int32_t* status, hipStream_t st) {
+    for (int r0 = 0; r0 < reps; r0 += kMaxRepPerLaunch) {
+        const int nr = reps - r0 < kMaxRepPerLaunch ? reps - r0 : kMaxRepPerLaunch;
+        PermArgs pa{};
+        pa.lab = lab;
+        pa.n = n;
+        pa.bits = perm_bucket_bits(n);
+        pa.n_rep = nr;
+        for (int r = 0; r < nr; ++r) pa.seeds[r] = seeds[r0 + r];
+        pa.count = w.count;
+        pa.cursor = w.cursor;
+        pa.ekey = w.ekey;
+        pa.eidx = w.eidx;
+        pa.out = out + (size_t)r0 * out_stride;
+        pa.out_stride = out_stride;
+        pa.status = status;
+        const int64_t nb = (int64_t)1 << pa.bits;
+        const int cus = device_info().cus;
+        int gx = (int)((n + kBlock * 4 - 1) / (kBlock * 4));
+        if (gx > cus * 8) gx = cus * 8;
+        if (gx < 1) gx = 1;
+        hipLaunchKernelGGL(k_perm_zero, dim3(cus * 4), dim3(kBlock), 0, st, pa);
+        hipLaunchKernelGGL(k_perm_count, dim3(gx, nr), dim3(kBlock), 0, st, pa);
+        device_excl_scan(w.count, nb * nr, w.part, st);
+        hipLaunchKernelGGL(k_perm_place, dim3(gx, nr), dim3(kBlock), 0, st, pa);
+        int gs = (int)((nb + kWavesPerBlock - 1) / kWavesPerBlock);
+        if (gs > cus * 8) gs = cus * 8;
+        hipLaunchKernelGGL(k_perm_sort, dim3(gs, nr), dim3(kBlock), 0, st, pa);
+    }
 }
 
 // ------------------------------------------------------------ checks --
@@ -211,7 +273,8 @@ __global__ void k_finish(FinishArgs a) {
 
 // The binning stage shared by the plain entry points.  Leaves in the
 // workspace: plan, tid (eligible targets ascending), order (their ranks in
-// cell order), neighbour SoA in cell order and cell_start.
+// cell order, with rank, index and position), neighbour SoA in cell order
+// and cell_start.
 static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams& pp, const PlainWs& w,
                               int32_t* status, hipStream_t st) {
     const int64_t n = cl->n;
@@ -244,13 +307,13 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
     KeyArgs kt{w.plan, cl->xyz, w.tid, nullptr, 1, 1, w.K[0], w.V[0]};
     hipLaunchKernelGGL(k_keys, dim3(Gk), dim3(kBlock), 0, st, kt);
     sort(1);
-    OrderArgs oa{w.plan, {w.V[0], w.V[1]}, w.order};
+    OrderArgs oa{w.plan, cl->xyz, w.tid, {w.V[0], w.V[1]}, w.t_rank, w.t_id, w.tx, w.ty, w.tz};
     hipLaunchKernelGGL(k_take_order, dim3(Gk), dim3(kBlock), 0, st, oa);
     // neighbours in cell order
     KeyArgs kb{w.plan, cl->xyz, all_b ? nullptr : w.bsel, nullptr, 0, 0, w.K[0], w.V[0]};
     hipLaunchKernelGGL(k_keys, dim3(Gk), dim3(kBlock), 0, st, kb);
     sort(0);
-    GatherArgs ga{w.plan, cl->xyz, nullptr, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.bx, w.by, w.bz, w.cell_start};
+    GatherArgs ga{w.plan, cl->xyz, nullptr, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.bpos, w.cell_start};
     hipLaunchKernelGGL(k_gather, dim3(Gk), dim3(kBlock), 0, st, ga);
     return hip_check("binning launch");
 }
@@ -301,13 +364,12 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     PairArgs pa{};
     pa.plan = w.plan;
     pa.xyz = cl->xyz;
-    pa.tid = w.tid;
-    pa.order = w.order;
-    pa.bx = w.bx;
-    pa.by = w.by;
-    pa.bz = w.bz;
-    pa.vals[0] = w.V[0];
-    pa.vals[1] = w.V[1];
+    pa.t_rank = w.t_rank;
+    pa.t_id = w.t_id;
+    pa.tx = w.tx;
+    pa.ty = w.ty;
+    pa.tz = w.tz;
+    pa.bpos = w.bpos;
     pa.cell_start = w.cell_start;
     pa.self_possible = q.target == APT_ANY || q.neighbor == APT_ANY || q.target == q.neighbor;
     int n_bins = 1;
@@ -353,12 +415,19 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     const int Gp = device_info().cus * 8;
     {
         TraceSpan span("pair", st);
-        if (do_rdf && do_knn)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pair<true, true>), dim3(Gp), dim3(kBlock), lds, st, pa);
-        else if (do_rdf)
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pair<true, false>), dim3(Gp), dim3(kBlock), lds, st, pa);
-        else
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_pair<false, true>), dim3(Gp), dim3(kBlock), lds, st, pa);
+        const bool self = pa.self_possible != 0;
+        auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(Gp), dim3(kBlock), lds, st, pa); };
+        // RDF histograms in LDS unless there are too many bins
+        if (do_rdf && !in_lds) {
+            if (do_knn) self ? go(k_pair<kRdfGlobal | kSelf, true>) : go(k_pair<kRdfGlobal, true>);
+            else self ? go(k_pair<kRdfGlobal | kSelf, false>) : go(k_pair<kRdfGlobal, false>);
+        } else if (do_rdf && do_knn) {
+            self ? go(k_pair<kRdfLds | kSelf, true>) : go(k_pair<kRdfLds, true>);
+        } else if (do_rdf) {
+            self ? go(k_pair<kRdfLds | kSelf, false>) : go(k_pair<kRdfLds, false>);
+        } else {
+            self ? go(k_pair<kSelf, true>) : go(k_pair<0, true>);
+        }
     }
     FinishArgs fa{w.plan, do_knn ? capacity : -1, n_targets, status};
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, st, fa);
@@ -411,9 +480,28 @@ size_t apt_workspace_size(int32_t op, int64_t n, int32_t n_pairs, int32_t n_rep)
         case APT_OP_KNN:
         case APT_OP_KNN_RDF:
             return carve_plain(nullptr, n).bytes;
+        case APT_OP_PERMUTE:
+            return carve_perm(nullptr, n, 1).bytes;
         default:
             return 0;
     }
+}
+
+apt_status apt_permute_labels(const uint8_t* lab, int64_t n, uint64_t seed, uint8_t* out, int32_t* status,
+                              void* ws, size_t ws_bytes, void* stream) {
+    if (n < 0) return fail(APT_E_ARG, "n is negative");
+    if (n >= (int64_t)0xFFFFFFFFll) return fail(APT_E_UNSUPPORTED, "n must be below 2^32 - 1");
+    if (n > 0 && (!lab || !out)) return fail(APT_E_ARG, "lab or out is NULL");
+    if (!status) return fail(APT_E_ARG, "status is NULL");
+    PermWs w = carve_perm(ws, n, 1);
+    apt_status s;
+    if ((s = check_ws(ws, ws_bytes, w.bytes)) != APT_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    InitArgs ia{status, nullptr, 0, nullptr, 0, nullptr};
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, ia);
+    if (n > 0) run_permute(lab, n, &seed, 1, out, n, w, status, st);
+    return hip_check("permute launch");
 }
 
 apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_targets, void* ws, size_t ws_bytes,

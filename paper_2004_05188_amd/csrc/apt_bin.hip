@@ -479,16 +479,24 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortArgs a) {
 }
 
 // ------------------------------------------------------------------------
-// 6. copy of the sorted target order out of the sort buffers
+// 6. targets in cell order as SoA: rank, ion index, position
 // ------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_take_order(OrderArgs a) {
     const GridPlan P = *a.plan;
     const uint32_t* __restrict__ v = a.vals[P.passes & 1];
-    for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < P.nT; t += gridDim.x * kBlock) a.order[t] = v[t];
+    for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < P.nT; t += gridDim.x * kBlock) {
+        const uint32_t rank = v[t];
+        const uint32_t id = a.tid[rank];
+        a.t_rank[t] = rank;
+        a.t_id[t] = id;
+        a.tx[t] = a.xyz[3 * (size_t)id];
+        a.ty[t] = a.xyz[3 * (size_t)id + 1];
+        a.tz[t] = a.xyz[3 * (size_t)id + 2];
+    }
 }
 
 // ------------------------------------------------------------------------
-// 7. gather into SoA and cell start offsets
+// 7. gather into 16-byte records (x, y, z, index) and cell start offsets
 // ------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
     const GridPlan P = *a.plan;
@@ -505,9 +513,8 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
         const uint32_t id = val[p];
         float z = a.xyz[3 * (size_t)id + 2];
         if (a.zscale) z = (float)((double)z * sd);
-        a.bx[p] = a.xyz[3 * (size_t)id];
-        a.by[p] = a.xyz[3 * (size_t)id + 1];
-        a.bz[p] = z;
+        a.bpos[p] = make_float4(a.xyz[3 * (size_t)id], a.xyz[3 * (size_t)id + 1], z,
+                                __builtin_bit_cast(float, id));
         const uint32_t c = key[p];
         const uint32_t cprev = p == 0 ? 0u : key[p - 1] + 1u;
         for (uint32_t q = cprev; q <= c; ++q) a.cell_start[q] = p;

@@ -66,8 +66,14 @@ struct SortArgs {
 
 struct OrderArgs {
     const GridPlan* plan;
-    uint32_t* vals[2];
-    uint32_t* order;
+    const float* xyz;
+    const uint32_t* tid;    // [nT] eligible targets, ascending
+    uint32_t* vals[2];      // sorted ranks
+    uint32_t* t_rank;       // [nT] outputs, cell order
+    uint32_t* t_id;
+    float* tx;
+    float* ty;
+    float* tz;
 };
 
 struct GatherArgs {
@@ -76,9 +82,7 @@ struct GatherArgs {
     const double* zscale;
     uint32_t* keys[2];
     uint32_t* vals[2];
-    float* bx;
-    float* by;
-    float* bz;
+    float4* bpos;           // [nB] (x, y, z, ion index as bits) in cell order
     uint32_t* cell_start;   // [n_cells + 1]
 };
 

@@ -9,12 +9,12 @@ constexpr int kKnnCap = 512;   // per-wavefront kNN candidate buffer (u64 keys)
 struct PairArgs {
     const GridPlan* plan;
     const float* xyz;            // original positions [n][3]
-    const uint32_t* tid;         // [nT] eligible targets, ascending ion index
-    const uint32_t* order;       // [nT] target ranks in cell order
-    const float* bx;             // [nB] neighbour positions in cell order
-    const float* by;
-    const float* bz;
-    uint32_t* vals[2];           // sort buffers; vals[passes & 1] = neighbour ion index
+    const uint32_t* t_rank;      // [nT] targets in cell order: rank in ascending ion index
+    const uint32_t* t_id;        // [nT] ... ion index
+    const float* tx;             // [nT] ... position
+    const float* ty;
+    const float* tz;
+    const float4* bpos;          // [nB] neighbours in cell order: x, y, z, ion index (bits)
     const uint32_t* cell_start;  // [n_cells + 1]
     int32_t self_possible;       // a target may also be a neighbour
     // RDF
@@ -43,7 +43,10 @@ struct PairArgs {
 
 // grid: multiple of 8 workgroups of kBlock threads; dynamic LDS per block:
 // (hist_in_lds ? 4 * n_bins * 4 : 0) + (knn ? 4 * kKnnCap * 8 : 0) bytes
-template <bool RDF, bool KNN>
+// Variant flags of k_pair: RDF into per-wavefront LDS histograms or straight
+// into the global histogram (many bins); targets may be neighbours themselves.
+constexpr int kRdfLds = 1, kRdfGlobal = 2, kSelf = 4;
+template <int FLAGS, bool KNN>
 __global__ void k_pair(PairArgs a);
 
 size_t pair_lds_bytes(bool rdf, bool knn, int n_bins, bool hist_in_lds);

@@ -274,3 +274,23 @@ def test_frustum7m_queries(gpu, orc, needle7m, A, B):
     g = run_gpu(gpu, xyz, lab, d, A, B, 1.0, k=10)
     assert g["status"] == 0
     check_against_oracle(orc, g, xyz, lab, d, A, B, 1.0, k=10)
+
+
+# ---------------------------------------------------------------------------
+# label permutation (null model)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,seed", [(0, 1), (1, 5), (31, 7), (1000, 11), (240_000, 2**64 - 1),
+                                    (7_696_902, 123457)])
+def test_permute_labels_bit_exact(gpu, orc, synth, n, seed):
+    _say(f"case permute n={n} seed={seed}")
+    aptstat, torch, ws = gpu
+    if n == 7_696_902:
+        _, lab, _ = synth.frustum7m().generate()
+    else:
+        lab = np.random.default_rng(n).integers(0, 4, n).astype(np.uint8)
+    dl = torch.from_numpy(lab).to("cuda:0")
+    status = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    out = aptstat.permute_labels(dl, seed, ws=ws, status=status).cpu().numpy()
+    assert int(status.item()) == 0
+    assert np.array_equal(out, orc.permute_labels(lab, seed))
