@@ -73,6 +73,65 @@ def cpu_baseline(spec_name, queries, d_srf, use_d, seconds_budget=25.0):
                       f"(RDF + kNN k={K} + k-th histogram), {dt:.1f} s"}
 
 
+PAIRS6 = [(AL, SC), (AL, SI), (SC, AL), (SC, SI), (SI, AL), (SI, SC)]
+
+
+def batched_vs_looped(aptstat, torch, cloud, ws, n_rep, n_loop):
+    """Replicates/s of 6 ordered species pairs x n_rep label-randomised
+    replicates in one batched call, against looped plain calls (one label
+    permutation + one kNN+RDF call per pair and replicate) on the same GPU."""
+    pairs = [(a, b, 1.0) for a, b in PAIRS6]
+    base = 1000
+    dev = cloud.device
+    seeds = [base + r + 1 for r in range(n_rep)]
+    rh = torch.empty((n_rep, len(pairs), N_BINS), dtype=torch.int64, device=dev)
+    kh = torch.empty((n_rep, len(pairs), KB_NBINS + 1), dtype=torch.int64, device=dev)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    log(f"[bench] batched: warm-up (2 replicates)")
+    aptstat.rdf_batched(cloud, pairs, seeds[:2], r_max=R_MAX, n_bins=N_BINS, k=K, kb_rmax=KB_RMAX,
+                        kb_nbins=KB_NBINS, ws=ws)
+    torch.cuda.synchronize()
+    log(f"[bench] batched: {n_rep} replicates x {len(pairs)} pairs")
+    for stage in ("pair", "binning", "permute", "partition"):
+        aptstat.trace_read(stage)
+    aptstat.trace_enable(True)
+    t0 = time.perf_counter()
+    aptstat.rdf_batched(cloud, pairs, seeds, r_max=R_MAX, n_bins=N_BINS, k=K, kb_rmax=KB_RMAX,
+                        kb_nbins=KB_NBINS, ws=ws, out=(rh, kh, st))
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    aptstat.trace_enable(False)
+    stages = {s_: aptstat.trace_read(s_)[0] for s_ in ("pair", "binning", "permute", "partition")}
+    # looped: the definition of the batched result, call by call
+    lab_r = torch.empty_like(cloud.lab)
+    outs = (torch.empty(1, dtype=torch.int64, device=dev), torch.empty((1, K), dtype=torch.float32, device=dev),
+            torch.empty((1, K), dtype=torch.int64, device=dev),
+            torch.empty(KB_NBINS + 1, dtype=torch.int64, device=dev), torch.empty(1, dtype=torch.int64, device=dev),
+            torch.empty(1, dtype=torch.int32, device=dev), torch.empty(N_BINS, dtype=torch.int64, device=dev))
+
+    def loop(reps):
+        for sd in reps:
+            aptstat.permute_labels(cloud.lab, sd, out=lab_r, ws=ws)
+            c = aptstat.Cloud(cloud.xyz, lab_r, cloud.d_bnd)
+            for a, b, d in pairs:
+                aptstat.knn_rdf(c, a, b, d, K, r_max=R_MAX, n_bins=N_BINS, capacity=0, kb_rmax=KB_RMAX,
+                                kb_nbins=KB_NBINS, ws=ws, outputs=outs)
+
+    log(f"[bench] looped: {n_loop} replicates x {len(pairs)} pairs")
+    loop(seeds[:1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loop(seeds[:n_loop])
+    torch.cuda.synchronize()
+    tl = time.perf_counter() - t0
+    return {"replicates": n_rep, "pairs": [f"{NAMES[a]}->{NAMES[b]}" for a, b, _ in pairs],
+            "batched_replicates_per_s": n_rep / tb, "batched_s": tb,
+            "batched_stage_ms": stages,
+            "looped_replicates_per_s": n_loop / tl, "looped_replicates_timed": n_loop,
+            "looped_calls_timed": n_loop * (1 + len(pairs)),
+            "speedup": (n_rep / tb) / (n_loop / tl), "status": int(st.item())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +139,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="frustum7m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-reps", type=int, default=256,
+                    help="replicates of the batched null-model measurement (0 = skip)")
+    ap.add_argument("--looped-reps", type=int, default=16,
+                    help="replicates timed for the looped baseline (its rate is replicates/s)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (scale of the HBM byte counters)")
     args = ap.parse_args()
@@ -187,6 +250,8 @@ def main():
         "in_range_pairs_per_step": pairs, "pair_evals_per_s": pairs * args.steps / (pair_ms / 1e3),
         "status": status,
     }
+    if args.batched_reps > 0 and args.workload == "frustum7m":
+        line["batched"] = batched_vs_looped(aptstat, torch, cloud, ws, args.batched_reps, args.looped_reps)
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host")
         line["cpu_baseline"] = cpu_baseline(gen_name, queries, d_srf, use_d)

@@ -153,10 +153,46 @@ apt_status apt_knn_rdf(const apt_cloud* cloud, apt_query q, apt_bins rdf_bins, u
 apt_status apt_permute_labels(const uint8_t* lab, int64_t n, uint64_t seed, uint8_t* out, int32_t* status,
                               void* ws, size_t ws_bytes, void* stream);
 
+/* Null-model replicates of several species pairs in one call (paper, Suppl.:
+ * every statistic for randomised labels; Methods: "User-defined batch
+ * processing queues").  For replicate r (0 <= r < n_rep) the labels are
+ * apt_permute_labels(lab, seeds[r]); the outputs of (r, p) are DEFINED as
+ * apt_knn_rdf's rdf_hist and knn_hist for query pairs[p] on those labels:
+ *   pairs[n_pairs]   host array; concrete species (no APT_ANY), at most 16
+ *                    pairs and 7 distinct species; each with its own d_srf
+ *   seeds[n_rep]     host array
+ *   rdf_hist         [n_rep][n_pairs][rdf_bins.n_bins] uint64 (n_bins <= 3072)
+ *   knn_hist         [n_rep][n_pairs][knn_bins.n_bins + 1] uint64, or NULL;
+ *                    k-th neighbour distance of every eligible target
+ *   tuning           reserved, pass NULL
+ * Positions are binned once; replicates run in blocks of up to 64.
+ * Workspace: apt_workspace_size(APT_OP_BATCHED, n, n_pairs, n_rep). */
+apt_status apt_rdf_batched(const apt_cloud* cloud, const apt_query* pairs, int32_t n_pairs, const uint64_t* seeds,
+                           int32_t n_rep, apt_bins rdf_bins, int32_t k, apt_bins knn_bins, uint64_t* rdf_hist,
+                           uint64_t* knn_hist, const void* tuning, int32_t* status, void* ws, size_t ws_bytes,
+                           void* stream);
+
 /* Number of eligible targets of a query, for sizing kNN outputs:
  * n_targets[1] (int64, device) is overwritten.  Workspace as APT_OP_KNN. */
 apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_targets, void* ws,
                              size_t ws_bytes, void* stream);
+
+/* Process-wide tuning of the plain entry points (host only; results do not
+ * depend on it, only speed):
+ *   tile_policy  0 automatic, 1 one target per wavefront, 2 64 targets per
+ *                wavefront with LDS-staged neighbours and a register kNN list
+ *                (used only when k <= 16 and n_bins <= 3072)
+ *   cell_occ     neighbours per grid cell aimed at (default 4)
+ *   h_min_frac   smallest cell edge as a fraction of r_max (default 0.5)
+ * apt_set_tuning(NULL) restores the defaults. */
+typedef struct {
+    int32_t tile_policy;
+    float cell_occ;
+    float h_min_frac;
+    float reserved;
+} apt_tuning;
+apt_status apt_set_tuning(const apt_tuning* t);
+apt_status apt_get_tuning(apt_tuning* t);
 
 /* Tracing: while enabled (on != 0), every call records HIP events on its
  * stream around its stages; apt_trace_read waits for the recorded events,

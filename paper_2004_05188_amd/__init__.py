@@ -43,6 +43,11 @@ class _Query(ctypes.Structure):
                 ("d_srf", ctypes.c_float)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("tile_policy", ctypes.c_int32), ("cell_occ", ctypes.c_float), ("h_min_frac", ctypes.c_float),
+                ("reserved", ctypes.c_float)]
+
+
 class _Bins(ctypes.Structure):
     _fields_ = [("r_max", ctypes.c_float), ("n_bins", ctypes.c_int32)]
 
@@ -54,10 +59,14 @@ _SIGS = {
     "apt_workspace_size": ([ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32], ctypes.c_size_t),
     "apt_last_error": ([], ctypes.c_char_p),
     "apt_trace_enable": ([ctypes.c_int32], ctypes.c_int),
+    "apt_set_tuning": ([ctypes.POINTER(_Tuning)], ctypes.c_int),
+    "apt_get_tuning": ([ctypes.POINTER(_Tuning)], ctypes.c_int),
     "apt_trace_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
                        ctypes.c_int),
     "apt_count_targets": ([ctypes.POINTER(_Cloud), _Query, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_permute_labels": ([_P, ctypes.c_int64, ctypes.c_uint64, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "apt_rdf_batched": ([ctypes.POINTER(_Cloud), _P, ctypes.c_int32, _P, ctypes.c_int32, _Bins, ctypes.c_int32,
+                         _Bins, _P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_rdf": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_knn": ([ctypes.POINTER(_Cloud), _Query, ctypes.c_int32, ctypes.c_float, ctypes.c_int64, _P, _P, _P,
                  _Bins, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
@@ -154,6 +163,18 @@ class Workspace:
         return self.buf
 
 
+def set_tuning(tile_policy: int = 0, cell_occ: float = 4.0, h_min_frac: float = 0.5):
+    """Process-wide speed knobs (results do not depend on them)."""
+    t = _Tuning(int(tile_policy), float(cell_occ), float(h_min_frac), 0.0)
+    _check(lib().apt_set_tuning(ctypes.byref(t)), "apt_set_tuning")
+
+
+def get_tuning() -> dict:
+    t = _Tuning()
+    _check(lib().apt_get_tuning(ctypes.byref(t)), "apt_get_tuning")
+    return {"tile_policy": t.tile_policy, "cell_occ": t.cell_occ, "h_min_frac": t.h_min_frac}
+
+
 def trace_enable(on: bool = True):
     """Record HIP events around the stages of every following call."""
     _check(lib().apt_trace_enable(1 if on else 0), "apt_trace_enable")
@@ -215,6 +236,32 @@ def permute_labels(lab: torch.Tensor, seed: int, out: torch.Tensor | None = None
     _check(lib().apt_permute_labels(_ptr(lab), n, ctypes.c_uint64(seed & (2**64 - 1)), _ptr(out), _ptr(status),
                                     _ptr(buf), nb, _stream(lab)), "apt_permute_labels")
     return out
+
+
+def rdf_batched(cloud: Cloud, pairs, seeds, r_max: float = 2.0, n_bins: int = 200, k: int = 10,
+                kb_rmax: float = 5.0, kb_nbins: int = 5000, want_knn: bool = True,
+                ws: Workspace | None = None, out=None):
+    """Null-model replicates: pairs = [(A, B, d_srf), ...], seeds = [seed_r, ...].
+
+    Returns (rdf int64 [n_rep, n_pairs, n_bins], knn int64 [n_rep, n_pairs, kb_nbins + 1] or None,
+    status int32 [1]); (r, p) equals knn_rdf of pair p on permute_labels(lab, seeds[r])."""
+    n_pairs, n_rep = len(pairs), len(seeds)
+    qs = (_Query * n_pairs)(*[_query(a, b, d) for a, b, d in pairs])
+    sd = (ctypes.c_uint64 * n_rep)(*[int(x) & (2**64 - 1) for x in seeds])
+    dev = cloud.device
+    if out is None:
+        rh = torch.empty((n_rep, n_pairs, n_bins), dtype=torch.int64, device=dev)
+        kh = torch.empty((n_rep, n_pairs, kb_nbins + 1), dtype=torch.int64, device=dev) if want_knn else None
+        st = torch.empty(1, dtype=torch.int32, device=dev)
+    else:
+        rh, kh, st = out
+    ws = ws if ws is not None else Workspace()
+    nb = workspace_size(OP_BATCHED, cloud.n, n_pairs, n_rep)
+    buf = ws.get(nb, dev)
+    _check(lib().apt_rdf_batched(cloud.c(), qs, n_pairs, sd, n_rep, _bins(r_max, n_bins), int(k),
+                                 _bins(kb_rmax, kb_nbins), _ptr(rh), _ptr(kh), None, _ptr(st), _ptr(buf), nb,
+                                 _stream(cloud.xyz)), "apt_rdf_batched")
+    return rh, kh, st
 
 
 def rdf(cloud: Cloud, target: int, neighbor: int, d_srf: float, r_max: float, n_bins: int,

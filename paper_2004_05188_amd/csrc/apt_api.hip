@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "apt_batched.hpp"
 #include "apt_bin.hpp"
 #include "apt_pair.hpp"
 #include "apt_perm.hpp"
@@ -38,6 +39,15 @@ static DevInfo device_info() {
         cache[dev].cus = cus;
     }
     return cache[dev];
+}
+
+// ------------------------------------------------------------- tuning --
+static std::mutex g_tune_mu;
+static apt_tuning g_tune = {0, 4.0f, 0.5f, 0.0f};
+
+static apt_tuning tuning() {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    return g_tune;
 }
 
 // ------------------------------------------------------------ tracing --
@@ -115,6 +125,8 @@ struct PlainWs {
     uint32_t* cell_start;
     uint32_t* rs_counts;
     uint32_t* rs_totals;
+    uint32_t* strag;
+    uint32_t* strag_count;
     size_t bytes;
 };
 
@@ -144,6 +156,8 @@ static PlainWs carve_plain(void* base, int64_t n) {
     w.tz = c.take<float>(N);
     w.bpos = c.take<float4>(N);
     w.cell_start = c.take<uint32_t>((size_t)cell_cap_for(n) + 1);
+    w.strag = c.take<uint32_t>(N);
+    w.strag_count = c.take<uint32_t>(64);
     w.bytes = c.off;
     return w;
 }
@@ -205,6 +219,55 @@ static void run_permute(const uint8_t* lab, int64_t n, const uint64_t* seeds, in
     }
 }
 
+// Workspace of the batched replicates: the binning of all ions, and per
+// block of R replicates their labels, permutation scratch, class segments
+// and cell offsets.
+constexpr int kMaxPartBlocks = 2048;
+static int part_blocks(int64_t n) {
+    int64_t g = (n + kPartTile - 1) / kPartTile;
+    if (g < 1) g = 1;
+    if (g > kMaxPartBlocks) g = kMaxPartBlocks;
+    return (int)g;
+}
+static int batch_reps(int64_t n, int n_rep) {
+    int64_t r = n_rep < kMaxRepPerLaunch ? n_rep : kMaxRepPerLaunch;
+    const int64_t lim = (int64_t)0xFFFFFFFEll / (n > 0 ? n : 1);
+    if (r > lim) r = lim;
+    return (int)(r < 1 ? 1 : r);
+}
+
+struct BatchWs {
+    PlainWs plain;    // plan, partials, edge tables, sort buffers, binned records
+    PermWs perm;
+    uint8_t* LR;
+    uint32_t* cnt;
+    float4* Pp;
+    uint32_t* Pcell;
+    uint32_t* CS;
+    uint64_t* items;
+    uint64_t* work;
+    size_t bytes;
+};
+
+static BatchWs carve_batched(void* base, int64_t n, int R) {
+    BatchWs w;
+    w.plain = carve_plain(base, n);
+    char* b2 = base ? reinterpret_cast<char*>(base) + w.plain.bytes : nullptr;
+    w.perm = carve_perm(b2, n, R);
+    Carve c{b2 ? b2 + w.perm.bytes : nullptr};
+    c.off = 0;
+    const size_t N = (size_t)(n > 0 ? n : 1);
+    w.LR = c.take<uint8_t>(N * R);
+    w.cnt = c.take<uint32_t>((size_t)R * kMaxClasses * kMaxPartBlocks);
+    w.Pp = c.take<float4>(N * R);
+    w.Pcell = c.take<uint32_t>(N * R);
+    w.CS = c.take<uint32_t>((size_t)R * (kMaxClasses - 1) * ((size_t)cell_cap_for(n) + 1));
+    w.items = c.take<uint64_t>((size_t)R * kMaxPairs + 1);
+    w.work = c.take<uint64_t>(8);
+    w.bytes = w.plain.bytes + w.perm.bytes + c.off;
+    return w;
+}
+
 // ------------------------------------------------------------ checks --
 static apt_status check_cloud(const apt_cloud* cl) {
     if (!cl) return fail(APT_E_ARG, "cloud is NULL");
@@ -246,12 +309,14 @@ struct InitArgs {
     uint64_t* h2;
     int32_t n2;
     int64_t* n_targets;
+    uint32_t* counter;
 };
 __global__ void k_init(InitArgs a) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x, st = gridDim.x * blockDim.x;
     if (t == 0) {
         if (a.status) *a.status = 0;
         if (a.n_targets) *a.n_targets = 0;
+        if (a.counter) *a.counter = 0;
     }
     if (a.h1)
         for (int b = t; b < a.n1; b += st) a.h1[b] = 0;
@@ -346,16 +411,22 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     (void)hipGetLastError();
 
-    InitArgs ia{status, rdf_hist, do_rdf ? rb->n_bins : 0, knn_hist, knn_hist ? kb->n_bins + 1 : 0, n_targets};
+    InitArgs ia{status, rdf_hist, do_rdf ? rb->n_bins : 0, knn_hist, knn_hist ? kb->n_bins + 1 : 0, n_targets,
+                w.strag_count};
     hipLaunchKernelGGL(k_init, dim3(64), dim3(256), 0, st, ia);
     if (do_rdf) hipLaunchKernelGGL(k_edges, dim3(64), dim3(256), 0, st, w.E2, rb->r_max, rb->n_bins);
     if (knn_hist) hipLaunchKernelGGL(k_edges, dim3(64), dim3(256), 0, st, w.KE2, kb->r_max, kb->n_bins);
 
+    const apt_tuning tu = tuning();
+    const bool rdf_lds = do_rdf && (size_t)kWavesPerBlock * rb->n_bins * 4u <= 48u * 1024u;
     PlanParams pp;
-    pp.h_min = do_rdf ? rb->r_max * 0.5f : 0.0f;
-    pp.occ = 4.0f;
+    pp.h_min = do_rdf ? rb->r_max * tu.h_min_frac : 0.0f;
+    pp.occ = tu.cell_occ;
     pp.k = do_knn ? k : 0;
     pp.cell_cap = cell_cap_for(cl->n);
+    // tiles need an LDS histogram and at most 16 kNN keys per lane
+    pp.tile_policy = ((do_rdf && !rdf_lds) || (do_knn && k > 16)) ? 1 : tu.tile_policy;
+    pp.r_enum = do_rdf ? rb->r_max : 0.0f;
     {
         TraceSpan span("binning", st);
         if ((s = run_binning(cl, q, pp, w, status, st)) != APT_OK) return s;
@@ -411,8 +482,28 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
             pa.KE2 = w.KE2;
         }
     }
+    pa.strag = w.strag;
+    pa.strag_count = w.strag_count;
     const size_t lds = pair_lds_bytes(do_rdf, do_knn, n_bins, in_lds);
     const int Gp = device_info().cus * 8;
+    if (pp.tile_policy != 1) {
+        // 64 targets per wavefront when the plan chooses it (exits otherwise)
+        TraceSpan span("tile", st);
+        const bool self = pa.self_possible != 0;
+        const size_t tl = tile_lds_bytes(do_rdf, n_bins);
+        auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(Gp), dim3(kBlock), tl, st, pa); };
+        const int km = !do_knn ? 0 : k <= 4 ? 4 : k <= 10 ? 10 : 16;
+        if (do_rdf) {
+            if (km == 0) self ? go(k_pair_tile<kRdfLds | kSelf, 0>) : go(k_pair_tile<kRdfLds, 0>);
+            else if (km == 4) self ? go(k_pair_tile<kRdfLds | kSelf, 4>) : go(k_pair_tile<kRdfLds, 4>);
+            else if (km == 10) self ? go(k_pair_tile<kRdfLds | kSelf, 10>) : go(k_pair_tile<kRdfLds, 10>);
+            else self ? go(k_pair_tile<kRdfLds | kSelf, 16>) : go(k_pair_tile<kRdfLds, 16>);
+        } else {
+            if (km == 4) self ? go(k_pair_tile<kSelf, 4>) : go(k_pair_tile<0, 4>);
+            else if (km == 10) self ? go(k_pair_tile<kSelf, 10>) : go(k_pair_tile<0, 10>);
+            else self ? go(k_pair_tile<kSelf, 16>) : go(k_pair_tile<0, 16>);
+        }
+    }
     {
         TraceSpan span("pair", st);
         const bool self = pa.self_possible != 0;
@@ -434,6 +525,160 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     return hip_check("pair launch");
 }
 
+static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32_t n_pairs, const uint64_t* seeds,
+                              int32_t n_rep, apt_bins rb, int32_t k, apt_bins kb, uint64_t* rdf_hist,
+                              uint64_t* knn_hist, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+    apt_status s;
+    if ((s = check_cloud(cl)) != APT_OK) return s;
+    if (!pairs || n_pairs < 1) return fail(APT_E_ARG, "pairs is NULL or n_pairs < 1");
+    if (n_pairs > kMaxPairs) return fail(APT_E_UNSUPPORTED, "at most 16 pairs per call");
+    if (!seeds || n_rep < 1) return fail(APT_E_ARG, "seeds is NULL or n_rep < 1");
+    if ((s = check_bins(rb, "rdf_bins")) != APT_OK) return s;
+    if (!rdf_hist) return fail(APT_E_ARG, "rdf_hist is NULL");
+    if (k < 1) return fail(APT_E_ARG, "k must be >= 1");
+    if (k > APT_MAX_K) return fail(APT_E_UNSUPPORTED, "k must be in [1, 256]");
+    if (knn_hist && (s = check_bins(kb, "knn_bins")) != APT_OK) return s;
+    if (!status) return fail(APT_E_ARG, "status is NULL");
+    if ((size_t)kWavesPerBlock * rb.n_bins * 4u > 48u * 1024u)
+        return fail(APT_E_UNSUPPORTED, "batched RDF supports at most 3072 bins");
+    // species -> class; every species of the pairs gets one class
+    uint8_t slot[256];
+    int C = 0;
+    int cls_of[256];
+    for (int q = 0; q < 256; ++q) cls_of[q] = -1;
+    for (int p = 0; p < n_pairs; ++p) {
+        if (isnan(pairs[p].d_srf)) return fail(APT_E_ARG, "pair d_srf is NaN");
+        for (int v = 0; v < 2; ++v) {
+            const int sp = v ? pairs[p].neighbor : pairs[p].target;
+            if (sp == APT_ANY) return fail(APT_E_UNSUPPORTED, "batched pairs name concrete species (not APT_ANY)");
+            if (cls_of[sp] < 0) {
+                if (C >= kMaxClasses - 1) return fail(APT_E_UNSUPPORTED, "at most 7 species over all pairs");
+                cls_of[sp] = C++;
+            }
+        }
+    }
+    const int Cn = C + 1;   // plus "other"
+    for (int q = 0; q < 256; ++q) slot[q] = (uint8_t)(cls_of[q] >= 0 ? cls_of[q] : C);
+    const int64_t n = cl->n;
+    const int R = batch_reps(n, n_rep);
+    BatchWs w = carve_batched(ws, n, R);
+    if ((s = check_ws(ws, ws_bytes, w.bytes)) != APT_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    const int cus = device_info().cus;
+
+    // zero the outputs and the status word, edge tables
+    const int64_t nh = (int64_t)n_rep * n_pairs * rb.n_bins;
+    const int64_t nk = knn_hist ? (int64_t)n_rep * n_pairs * (kb.n_bins + 1) : 0;
+    InitArgs ia{status, rdf_hist, (int32_t)nh, knn_hist, (int32_t)nk, nullptr, nullptr};
+    hipLaunchKernelGGL(k_init, dim3(cus * 4), dim3(256), 0, st, ia);
+    hipLaunchKernelGGL(k_edges, dim3(64), dim3(256), 0, st, w.plain.E2, rb.r_max, rb.n_bins);
+    if (knn_hist) hipLaunchKernelGGL(k_edges, dim3(64), dim3(256), 0, st, w.plain.KE2, kb.r_max, kb.n_bins);
+
+    // all ions binned once: records in cell order (w.plain.bpos), cell ids
+    {
+        TraceSpan span("binning", st);
+        const PlainWs& pw = w.plain;
+        const int G = count_blocks(n);
+        const int64_t chunk = count_chunk(n, G);
+        CountArgs ca{cl->xyz, cl->lab, nullptr, n, chunk, APT_ANY, APT_ANY, 0.0f, nullptr, pw.part_cnt, pw.part_bbox,
+                     pw.part_nf};
+        hipLaunchKernelGGL(k_count, dim3(G), dim3(kBlock), 0, st, ca);
+        PlanParams pp{rb.r_max * 0.5f, 4.0f, k, cell_cap_for(n), 1, rb.r_max};
+        PlanArgs pa{G, pw.part_cnt, pw.part_bbox, pw.part_nf, pw.part_off, pp, nullptr, pw.plan, status};
+        hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, pa);
+        const int Gk = cus * 8;
+        KeyArgs kk{pw.plan, cl->xyz, nullptr, nullptr, 0, 0, pw.K[0], pw.V[0]};
+        hipLaunchKernelGGL(k_keys, dim3(Gk), dim3(kBlock), 0, st, kk);
+        for (int p = 0; p < sort_passes_max(pp.cell_cap); ++p) {
+            SortArgs sa{pw.plan, 0, p, kSortBlocks, {pw.K[0], pw.K[1]}, {pw.V[0], pw.V[1]}, pw.rs_counts,
+                        pw.rs_totals};
+            hipLaunchKernelGGL(k_rs_upsweep, dim3(kSortBlocks), dim3(kBlock), 0, st, sa);
+            hipLaunchKernelGGL(k_rs_scan, dim3(256), dim3(kBlock), 0, st, sa);
+            hipLaunchKernelGGL(k_rs_downsweep, dim3(kSortBlocks), dim3(kBlock), 0, st, sa);
+        }
+        GatherArgs ga{pw.plan, cl->xyz, nullptr, {pw.K[0], pw.K[1]}, {pw.V[0], pw.V[1]}, pw.bpos, pw.cell_start};
+        hipLaunchKernelGGL(k_gather, dim3(Gk), dim3(kBlock), 0, st, ga);
+    }
+
+    const int Gp = part_blocks(n);
+    const int64_t pchunk = ((n + Gp - 1) / Gp + kPartTile - 1) / kPartTile * kPartTile;
+    const size_t lds = batched_lds_bytes(rb.n_bins);
+    const double w_bin = (double)rb.r_max / rb.n_bins;
+    double delta_b = fmax(fmax(1e-6, 2e-6 * (double)rb.r_max) / w_bin, 4e-6 * rb.n_bins);
+    if (delta_b > 0.25) delta_b = 0.25;
+    for (int r0 = 0; r0 < n_rep; r0 += R) {
+        const int nr = n_rep - r0 < R ? n_rep - r0 : R;
+        {
+            TraceSpan span("permute", st);
+            run_permute(cl->lab, n, seeds + r0, nr, w.LR, n, w.perm, status, st);
+        }
+        TraceSpan span("partition", st);
+        PartArgs pa{};
+        pa.plan = w.plain.plan;
+        pa.S = w.plain.bpos;
+        pa.keys[0] = w.plain.K[0];
+        pa.keys[1] = w.plain.K[1];
+        pa.vals[0] = w.plain.V[0];
+        pa.vals[1] = w.plain.V[1];
+        pa.LR = w.LR;
+        pa.n = n;
+        pa.chunk = pchunk;
+        pa.G = Gp;
+        pa.C = Cn;
+        for (int q = 0; q < 256; ++q) pa.slot[q] = slot[q];
+        pa.cnt = w.cnt;
+        pa.Pp = w.Pp;
+        pa.Pcell = w.Pcell;
+        pa.CS = w.CS;
+        pa.cs_stride = (int64_t)cell_cap_for(n) + 1;
+        hipLaunchKernelGGL(k_bpart_count, dim3(Gp, nr), dim3(kBlock), 0, st, pa);
+        device_excl_scan(w.cnt, (int64_t)nr * Cn * Gp, w.perm.part, st);
+        hipLaunchKernelGGL(k_bpart_scatter, dim3(Gp, nr), dim3(kBlock), 0, st, pa);
+        hipLaunchKernelGGL(k_bpart_cells, dim3(cus * 4, nr), dim3(kBlock), 0, st, pa);
+        hipLaunchKernelGGL(k_bpart_empty, dim3(64, nr * (Cn - 1)), dim3(kBlock), 0, st, pa);
+
+        BatchPairArgs ba{};
+        ba.plan = w.plain.plan;
+        ba.xyz = cl->xyz;
+        ba.d_bnd = cl->d_bnd;
+        ba.Pp = w.Pp;
+        ba.CS = w.CS;
+        ba.cs_stride = pa.cs_stride;
+        ba.cnt = w.cnt;
+        ba.G = Gp;
+        ba.C = Cn;
+        ba.R = nr;
+        ba.n_pairs = n_pairs;
+        ba.n = n;
+        ba.rep0 = r0;
+        for (int p = 0; p < n_pairs; ++p) {
+            ba.pairs[p].a = cls_of[pairs[p].target];
+            ba.pairs[p].b = cls_of[pairs[p].neighbor];
+            ba.pairs[p].d_srf = pairs[p].d_srf;
+        }
+        ba.items = w.items;
+        ba.work = w.work;
+        ba.n_bins = rb.n_bins;
+        ba.r_enum = (float)((double)rb.r_max * (1.0 + 4e-5));
+        ba.thr2 = (float)(((double)rb.r_max * (1.0 + 2e-5)) * ((double)rb.r_max * (1.0 + 2e-5)));
+        ba.inv_w = (float)(rb.n_bins / (double)rb.r_max);
+        ba.delta_b = (float)delta_b;
+        ba.inv_w64 = rb.n_bins / (double)rb.r_max;
+        ba.E2 = w.plain.E2;
+        ba.rdf_hist = rdf_hist;
+        ba.k = k;
+        ba.kb_nbins = knn_hist ? kb.n_bins : 0;
+        ba.kb_inv_w64 = knn_hist ? kb.n_bins / (double)kb.r_max : 0.0;
+        ba.KE2 = w.plain.KE2;
+        ba.knn_hist = knn_hist;
+        hipLaunchKernelGGL(k_batch_items, dim3(1), dim3(64), 0, st, ba);
+        TraceSpan span2("pair", st);
+        hipLaunchKernelGGL(k_pair_batched, dim3(cus * 8), dim3(kBlock), lds, st, ba);
+    }
+    return hip_check("batched launch");
+}
+
 }  // namespace apt
 
 using namespace apt;
@@ -441,6 +686,25 @@ using namespace apt;
 extern "C" {
 
 const char* apt_last_error(void) { return g_err.c_str(); }
+
+apt_status apt_set_tuning(const apt_tuning* t) {
+    apt_tuning v = {0, 4.0f, 0.5f, 0.0f};
+    if (t) {
+        if (t->tile_policy < 0 || t->tile_policy > 2) return fail(APT_E_ARG, "tile_policy must be 0, 1 or 2");
+        if (!(t->cell_occ > 0.0f) || !(t->h_min_frac > 0.0f) || !isfinite(t->cell_occ) || !isfinite(t->h_min_frac))
+            return fail(APT_E_ARG, "cell_occ and h_min_frac must be finite and > 0");
+        v = *t;
+    }
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune = v;
+    return APT_OK;
+}
+
+apt_status apt_get_tuning(apt_tuning* t) {
+    if (!t) return fail(APT_E_ARG, "apt_get_tuning: NULL");
+    *t = tuning();
+    return APT_OK;
+}
 
 apt_status apt_trace_enable(int32_t on) {
     g_trace_on.store(on ? 1 : 0);
@@ -482,6 +746,9 @@ size_t apt_workspace_size(int32_t op, int64_t n, int32_t n_pairs, int32_t n_rep)
             return carve_plain(nullptr, n).bytes;
         case APT_OP_PERMUTE:
             return carve_perm(nullptr, n, 1).bytes;
+        case APT_OP_BATCHED:
+            if (n_rep < 1) return 0;
+            return carve_batched(nullptr, n, batch_reps(n, n_rep)).bytes;
         default:
             return 0;
     }
@@ -498,10 +765,19 @@ apt_status apt_permute_labels(const uint8_t* lab, int64_t n, uint64_t seed, uint
     if ((s = check_ws(ws, ws_bytes, w.bytes)) != APT_OK) return s;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     (void)hipGetLastError();
-    InitArgs ia{status, nullptr, 0, nullptr, 0, nullptr};
+    InitArgs ia{status, nullptr, 0, nullptr, 0, nullptr, nullptr};
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, ia);
     if (n > 0) run_permute(lab, n, &seed, 1, out, n, w, status, st);
     return hip_check("permute launch");
+}
+
+apt_status apt_rdf_batched(const apt_cloud* cloud, const apt_query* pairs, int32_t n_pairs, const uint64_t* seeds,
+                           int32_t n_rep, apt_bins rdf_bins, int32_t k, apt_bins knn_bins, uint64_t* rdf_hist,
+                           uint64_t* knn_hist, const void* tuning, int32_t* status, void* ws, size_t ws_bytes,
+                           void* stream) {
+    (void)tuning;
+    return run_batched(cloud, pairs, n_pairs, seeds, n_rep, rdf_bins, k, knn_bins, rdf_hist, knn_hist, status, ws,
+                       ws_bytes, stream);
 }
 
 apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_targets, void* ws, size_t ws_bytes,
@@ -518,7 +794,7 @@ apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_tar
     CountArgs ca{cloud->xyz, cloud->lab, cloud->d_bnd, cloud->n, count_chunk(cloud->n, G), q.target, q.neighbor,
                  q.d_srf, nullptr, w.part_cnt, w.part_bbox, w.part_nf};
     hipLaunchKernelGGL(k_count, dim3(G), dim3(kBlock), 0, st, ca);
-    PlanParams pp{1.0f, 4.0f, 0, cell_cap_for(cloud->n)};
+    PlanParams pp{1.0f, 4.0f, 0, cell_cap_for(cloud->n), 1, 0.0f};
     PlanArgs pa{G, w.part_cnt, w.part_bbox, w.part_nf, w.part_off, pp, nullptr, w.plan, nullptr};
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, pa);
     FinishArgs fa{w.plan, -1, n_targets, nullptr};

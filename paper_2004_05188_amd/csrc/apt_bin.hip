@@ -211,7 +211,12 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
     }
     P.zscale = a.zscale ? (float)*a.zscale : 1.0f;
     P.nonfinite = s_nf[0];
-    P.pad[0] = P.pad[1] = 0;
+    // 64 consecutive targets (cell order) per wavefront when the targets are at
+    // least as dense as the neighbours; their kNN is certified within rk_tile
+    P.rk_tile = pp.k > 0 ? (float)fmin(1.6 / 1.15 * (double)P.rk0, (double)P.r_all) : 0.0f;
+    if (pp.tile_policy == 1) P.tile_mode = 0;
+    else if (pp.tile_policy == 2) P.tile_mode = pp.k <= 16 ? 1 : 0;
+    else P.tile_mode = (pp.k <= 16 && totT >= totB && totT >= 4096) ? 1 : 0;
     *a.plan = P;
     if (s_nf[0] && a.status) atomicOr(a.status, APT_STATUS_NONFINITE);
 }

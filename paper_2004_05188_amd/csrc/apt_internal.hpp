@@ -32,7 +32,8 @@ struct GridPlan {
     float rk0;          // first kNN search radius
     float zscale;       // z scale applied to positions (1 for the plain path)
     int32_t nonfinite;
-    uint32_t pad[2];
+    int32_t tile_mode;  // 1: 64 targets per wavefront (dense targets), 0: one target per wavefront
+    float rk_tile;      // kNN radius certified by the tile pass
 };
 
 // Host-chosen parameters of the plan.
@@ -41,6 +42,8 @@ struct PlanParams {
     float occ;          // aimed-for neighbours per cell
     int32_t k;          // kNN order (0: no kNN)
     uint32_t cell_cap;  // largest number of cells the workspace holds
+    int32_t tile_policy;  // 0: automatic, 1: one target per wavefront, 2: 64 targets per wavefront
+    float r_enum;       // RDF enumeration radius (0: no RDF)
 };
 
 // ---------------------------------------------------------------- waves --

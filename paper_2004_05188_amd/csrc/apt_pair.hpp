@@ -39,6 +39,9 @@ struct PairArgs {
     double kb_inv_w64;
     const double* KE2;           // [kb_nbins + 1] or NULL
     uint64_t* knn_hist;          // [kb_nbins + 1] or NULL
+    // tile mode: targets left for the one-per-wavefront pass
+    uint32_t* strag;             // [nT] target slots (cell order)
+    uint32_t* strag_count;       // [1], zeroed before the tile pass
 };
 
 // grid: multiple of 8 workgroups of kBlock threads; dynamic LDS per block:
@@ -50,5 +53,11 @@ template <int FLAGS, bool KNN>
 __global__ void k_pair(PairArgs a);
 
 size_t pair_lds_bytes(bool rdf, bool knn, int n_bins, bool hist_in_lds);
+
+// 64 targets per wavefront (apt_pair.hip); KMAX >= k kNN keys per lane, 0 for
+// RDF only.  Exits at once unless the plan chose tile mode.
+template <int FLAGS, int KMAX>
+__global__ void k_pair_tile(PairArgs a);
+size_t tile_lds_bytes(bool rdf, int n_bins);
 
 }  // namespace apt

@@ -1,0 +1,354 @@
+// Device-side building blocks of the target-neighbour pair loop, shared by
+// the plain kernel (apt_pair.hip) and the batched-replicate kernel
+// (apt_batched.hip): the stencil enumeration, the exact kNN key sort and
+// the per-target work (RDF counts and k nearest neighbours of one target).
+#pragma once
+#include "apt_pair.hpp"
+
+namespace apt {
+
+__device__ __forceinline__ uint32_t f2u(float f) { return __builtin_bit_cast(uint32_t, f); }
+__device__ __forceinline__ float u2f(uint32_t u) { return __builtin_bit_cast(float, u); }
+
+// Ascending bitonic sort of buf[0..c) (padded to a power of two >= 64 with
+// all-ones keys) by one wavefront; c <= kKnnCap.
+__device__ inline void wave_sort_keys(uint64_t* buf, int c) {
+    const int l = lane_id();
+    int N = kWave;
+    while (N < c) N <<= 1;
+    for (int i = c + l; i < N; i += kWave) buf[i] = ~0ull;
+    wave_sync();
+    for (int size = 2; size <= N; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int p = l; p < (N >> 1); p += kWave) {
+                const int i = ((p & ~(stride - 1)) << 1) | (p & (stride - 1));
+                const int j = i + stride;
+                const bool asc = (i & size) == 0;
+                const uint64_t x = buf[i], y = buf[j];
+                if ((x > y) == asc) {
+                    buf[i] = y;
+                    buf[j] = x;
+                }
+            }
+            wave_sync();
+        }
+    }
+}
+
+// Visit the neighbours in the cell rows that a sphere of radius R around
+// (px, py, pz) meets.  f(idx, x, y, z) is called by all 64 lanes per step,
+// idx == kNone on lanes without a candidate.  kUnroll batches of 64
+// candidates are located and their positions loaded before any is visited,
+// so that several memory round trips overlap.
+constexpr int kUnroll = 4;
+
+template <class F>
+__device__ __forceinline__ void enumerate_box(const GridPlan& P, const uint32_t* __restrict__ cell_start,
+                                              const float4* __restrict__ bpos, float x0, float y0, float z0,
+                                              float x1, float y1, float z1, float R, F&& f) {
+    // neighbours within R of the box [x0,x1] x [y0,y1] x [z0,z1]
+    const int l = lane_id();
+    const float Re = R + P.eps;
+    const float R2 = Re * Re;
+    const int cy0 = cell_axis(P, 1, y0 - Re), cy1 = cell_axis(P, 1, y1 + Re);
+    const int cz0 = cell_axis(P, 2, z0 - Re), cz1 = cell_axis(P, 2, z1 + Re);
+    const int ny = cy1 - cy0 + 1;
+    const int nrows = ny * (cz1 - cz0 + 1);
+    for (int rb = 0; rb < nrows; rb += kWave) {
+        const int r = rb + l;
+        uint32_t st = 0, len = 0;
+        if (r < nrows) {
+            const int cz = cz0 + r / ny, cy = cy0 + r % ny;
+            const float ya = P.lo[1] + (float)cy * P.h - P.eps, yb = P.lo[1] + (float)(cy + 1) * P.h + P.eps;
+            const float za = P.lo[2] + (float)cz * P.h - P.eps, zb = P.lo[2] + (float)(cz + 1) * P.h + P.eps;
+            const float dy = fmaxf(0.0f, fmaxf(ya - y1, y0 - yb));
+            const float dz = fmaxf(0.0f, fmaxf(za - z1, z0 - zb));
+            const float d2 = dy * dy + dz * dz;
+            if (d2 <= R2) {
+                const float ex = sqrtf(R2 - d2) + P.eps;
+                const int cx0 = cell_axis(P, 0, x0 - ex), cx1 = cell_axis(P, 0, x1 + ex);
+                const uint32_t base = ((uint32_t)cz * (uint32_t)P.dim[1] + (uint32_t)cy) * (uint32_t)P.dim[0];
+                st = cell_start[base + (uint32_t)cx0];
+                len = cell_start[base + (uint32_t)cx1 + 1u] - st;
+            }
+        }
+        const uint32_t inc = wave_incl_scan(len);
+        const uint32_t tot = readlane(inc, kWave - 1);
+        const uint32_t off = inc - len;
+        for (uint32_t b0 = 0; b0 < tot; b0 += kWave * kUnroll) {
+            uint32_t idx[kUnroll];
+            float4 c[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t b = b0 + (uint32_t)(kWave * u);
+                const uint32_t v = b + (uint32_t)l;
+                idx[u] = kNone;
+                if (b < tot) {
+                    const int r0 = __popcll(__ballot(inc <= b));   // first row ending after b
+                    const uint32_t e0 = readlane(inc, r0);
+                    if (e0 >= b + kWave) {
+                        // the whole step lies in row r0
+                        idx[u] = readlane(st, r0) + (v - (e0 - readlane(len, r0)));
+                    } else {
+                        for (int rr = r0; rr < kWave; ++rr) {
+                            const uint32_t o = readlane(off, rr);
+                            if (o >= b + kWave || o >= tot) break;
+                            const uint32_t s0 = readlane(st, rr), ln = readlane(len, rr);
+                            if (v >= o && v < o + ln) idx[u] = s0 + (v - o);
+                        }
+                    }
+                }
+            }
+            // lanes without a candidate read record 0 (always present when tot > 0)
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) c[u] = bpos[idx[u] == kNone ? 0u : idx[u]];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                if (b0 + (uint32_t)(kWave * u) < tot) f(idx[u] != kNone, c[u]);
+        }
+    }
+}
+
+
+template <class F>
+__device__ __forceinline__ void enumerate(const GridPlan& P, const uint32_t* __restrict__ cell_start,
+                                          const float4* __restrict__ bpos, float px, float py, float pz,
+                                          float R, F&& f) {
+    enumerate_box(P, cell_start, bpos, px, py, pz, px, py, pz, R, f);
+}
+
+// Everything one target needs besides its position and index.
+struct PairTask {
+    const float4* bpos;          // neighbour records, cell order
+    const uint32_t* cell_start;  // [n_cells + 1] into bpos
+    // RDF
+    int n_bins;
+    float r_enum, thr2, inv_w, lo_b, hi_b;
+    double inv_w64;
+    const double* E2;
+    uint32_t* hist_l;            // per-wavefront LDS histogram (LDS variant)
+    uint64_t* hist_g;            // global histogram (global variant)
+    // kNN
+    int k;
+    float rk0, rknn, rknn2;
+    uint64_t* kbuf;              // per-wavefront LDS key buffer [kKnnCap]
+};
+
+// RDF counts and kNN keys of one target.  Leaves the sorted keys in kbuf and
+// returns how many of the k nearest were found; adds this lane's RDF counts
+// to `hits`.
+template <int FLAGS, bool KNN>
+__device__ __forceinline__ int run_target(const GridPlan& P, const PairTask& T, float px, float py, float pz,
+                                          uint32_t i, uint32_t& hits, bool rdf_on = true) {
+    constexpr bool RDF_T = (FLAGS & (kRdfLds | kRdfGlobal)) != 0;
+    const bool RDF = RDF_T && rdf_on;
+    constexpr bool LDS_HIST = (FLAGS & kRdfLds) != 0;
+    constexpr bool SELF = (FLAGS & kSelf) != 0;
+    const int l = lane_id();
+    const bool finite = isfinite(px) && isfinite(py) && isfinite(pz);
+    auto dist2 = [&](float4 c) {
+        const float dx = c.x - px, dy = c.y - py, dz = c.z - pz;
+        return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    };
+    auto cid = [](float4 c) { return __builtin_bit_cast(uint32_t, c.w); };
+
+    // ---- RDF of one candidate: FP32 bin, FP64 re-decision near an edge
+    auto rdf_one = [&](bool valid, float4 c, float d2) {
+        bool ok = valid && d2 < T.thr2;
+        if (SELF) ok = ok && !(d2 == 0.0f && cid(c) == i);     // the target itself
+        const float t = __builtin_amdgcn_sqrtf(d2) * T.inv_w;
+        int b = (int)t;
+        const float fr = t - (float)b;
+        if (ok) {
+            if (__builtin_expect(fr < T.lo_b || fr > T.hi_b, 0))
+                b = exact_bin(exact_D2(px, py, pz, c.x, c.y, c.z), T.E2, T.n_bins, T.inv_w64);
+            if (b < T.n_bins) {
+                if (LDS_HIST) atomicAdd(&T.hist_l[b], 1u);
+                else atomicAdd((unsigned long long*)&T.hist_g[b], 1ull);
+                ++hits;
+            }
+        }
+    };
+
+    // ---- kNN: keys of candidates in (rk2_prev, rk2] into the LDS buffer
+    int cnt = 0;                        // keys in kbuf
+    uint64_t thr_key = ~0ull;           // keys must be below this once the buffer was cut
+    float rk = KNN ? fminf(T.rk0, T.rknn) : 0.0f;
+    float rk2 = (KNN && rk >= T.rknn) ? T.rknn2 : rk * rk;
+    float rk2_prev = -1.0f;
+    auto knn_one = [&](bool valid, float4 c, float d2) {
+        const uint32_t j = cid(c);
+        bool q = valid && d2 <= rk2 && d2 > rk2_prev;
+        if (SELF) q = q && j != i;
+        const uint64_t key = ((uint64_t)f2u(d2) << 32) | (uint64_t)j;
+        q = q && key < thr_key;
+        uint64_t m = __ballot(q);
+        if (m) {
+            int nn = __popcll(m);
+            if (cnt + nn > kKnnCap) {
+                // keep the k smallest keys, raise the bar to the k-th
+                wave_sort_keys(T.kbuf, cnt);
+                cnt = T.k;
+                thr_key = T.kbuf[T.k - 1];
+                q = q && key < thr_key;
+                m = __ballot(q);
+                nn = __popcll(m);
+            }
+            if (q) T.kbuf[cnt + __popcll(m & lanemask_lt())] = key;
+            cnt += nn;
+            wave_sync();
+        }
+    };
+
+    if (finite) {
+        if (RDF && (!KNN || rk * 1.000001f < T.r_enum)) {
+            enumerate(P, T.cell_start, T.bpos, px, py, pz, T.r_enum,
+                      [&](bool v, float4 c) { rdf_one(v, c, dist2(c)); });
+            if (KNN)
+                enumerate(P, T.cell_start, T.bpos, px, py, pz, rk * 1.000001f,
+                          [&](bool v, float4 c) { knn_one(v, c, dist2(c)); });
+        } else if (RDF) {
+            // the first kNN radius covers r_max: one enumeration for both
+            enumerate(P, T.cell_start, T.bpos, px, py, pz, rk * 1.000001f, [&](bool v, float4 c) {
+                const float d2 = dist2(c);
+                rdf_one(v, c, d2);
+                knn_one(v, c, d2);
+            });
+        } else if (KNN) {
+            enumerate(P, T.cell_start, T.bpos, px, py, pz, rk * 1.000001f,
+                      [&](bool v, float4 c) { knn_one(v, c, dist2(c)); });
+        }
+        if (KNN) {
+            // grow the radius until k keys are certain (or everything was seen)
+            while (cnt < T.k && rk < T.rknn && rk < P.r_all) {
+                float g = cbrtf((float)(T.k + 1) / (float)(cnt + 1)) * 1.1f;
+                g = fminf(fmaxf(g, 1.25f), 4.0f);
+                rk2_prev = rk2;
+                rk = fminf(rk * g, fminf(T.rknn, P.r_all));
+                rk2 = rk >= T.rknn ? T.rknn2 : rk * rk;
+                enumerate(P, T.cell_start, T.bpos, px, py, pz, rk * 1.000001f,
+                          [&](bool v, float4 c) { knn_one(v, c, dist2(c)); });
+            }
+        }
+    }
+    if (!KNN) return 0;
+    wave_sort_keys(T.kbuf, cnt);
+    (void)l;
+    return cnt < T.k ? cnt : T.k;
+}
+
+// ---------------------------------------------------------------- tiles --
+// 64 targets per wavefront, one per lane: the neighbour records within R of
+// the targets' bounding box are staged through LDS in chunks, and every lane
+// scans them for its own target, keeping its KMAX smallest kNN keys (FP32
+// squared distance, index) in registers.  Used when targets are dense, so
+// that the 64 targets of a tile are close together.
+constexpr int kStage = 512;   // records per staging chunk (16 B each)
+
+template <int KMAX>
+struct TopK {
+    uint64_t key[KMAX > 0 ? KMAX : 1];
+};
+
+// Returns this lane's number of kNN keys with d2 <= Rk^2 (0 when KMAX == 0).
+template <int FLAGS, int KMAX>
+__device__ __forceinline__ void run_tile(const GridPlan& P, const PairTask& T, bool valid, float px, float py,
+                                         float pz, uint32_t i, float Rk, float4* stage, TopK<KMAX>& top,
+                                         uint32_t& hits) {
+    constexpr bool RDF = (FLAGS & (kRdfLds | kRdfGlobal)) != 0;
+    constexpr bool LDS_HIST = (FLAGS & kRdfLds) != 0;
+    constexpr bool SELF = (FLAGS & kSelf) != 0;
+    const int l = lane_id();
+#pragma unroll
+    for (int m = 0; m < (KMAX > 0 ? KMAX : 1); ++m) top.key[m] = ~0ull;
+    const bool fin = valid && isfinite(px) && isfinite(py) && isfinite(pz);
+    float x0 = fin ? px : INFINITY, y0 = fin ? py : INFINITY, z0 = fin ? pz : INFINITY;
+    float x1 = fin ? px : -INFINITY, y1 = fin ? py : -INFINITY, z1 = fin ? pz : -INFINITY;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        x0 = fminf(x0, __shfl_xor(x0, d, kWave));
+        y0 = fminf(y0, __shfl_xor(y0, d, kWave));
+        z0 = fminf(z0, __shfl_xor(z0, d, kWave));
+        x1 = fmaxf(x1, __shfl_xor(x1, d, kWave));
+        y1 = fmaxf(y1, __shfl_xor(y1, d, kWave));
+        z1 = fmaxf(z1, __shfl_xor(z1, d, kWave));
+    }
+    if (!__any(fin)) return;
+    const float rk2 = Rk * Rk;
+    float R = 0.0f;
+    if (RDF) R = T.r_enum;
+    if (KMAX > 0) R = fmaxf(R, Rk * 1.000001f);
+
+    auto scan = [&](int m) {
+        wave_sync();
+        for (int j = 0; j < m; ++j) {
+            const float4 c = stage[j];
+            const float dx = c.x - px, dy = c.y - py, dz = c.z - pz;
+            const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            const uint32_t cj = __builtin_bit_cast(uint32_t, c.w);
+            const bool me = fin && (!SELF || cj != i);
+            if (RDF && me && d2 < T.thr2) {
+                const float t = __builtin_amdgcn_sqrtf(d2) * T.inv_w;
+                int b = (int)t;
+                const float fr = t - (float)b;
+                if (__builtin_expect(fr < T.lo_b || fr > T.hi_b, 0))
+                    b = exact_bin(exact_D2(px, py, pz, c.x, c.y, c.z), T.E2, T.n_bins, T.inv_w64);
+                if (b < T.n_bins) {
+                    if (LDS_HIST) atomicAdd(&T.hist_l[b], 1u);
+                    else atomicAdd((unsigned long long*)&T.hist_g[b], 1ull);
+                    ++hits;
+                }
+            }
+            if (KMAX > 0) {
+                const uint64_t key = ((uint64_t)__builtin_bit_cast(uint32_t, d2) << 32) | (uint64_t)cj;
+                if (me && d2 <= rk2 && key < top.key[KMAX - 1]) {
+                    // insert, keeping the keys ascending
+                    uint64_t x = key;
+#pragma unroll
+                    for (int q = 0; q < KMAX; ++q) {
+                        const uint64_t lo = x < top.key[q] ? x : top.key[q];
+                        const uint64_t hi = x < top.key[q] ? top.key[q] : x;
+                        top.key[q] = lo;
+                        x = hi;
+                    }
+                }
+            }
+        }
+        wave_sync();
+    };
+
+    int m = 0;   // staged records
+    enumerate_box(P, T.cell_start, T.bpos, x0, y0, z0, x1, y1, z1, R, [&](bool v, float4 c) {
+        const uint64_t bal = __ballot(v);
+        const int nn = __popcll(bal);
+        if (m + nn > kStage) {
+            scan(m);
+            m = 0;
+        }
+        if (v) stage[m + __popcll(bal & lanemask_lt())] = c;
+        m += nn;
+    });
+    if (m > 0) scan(m);
+    (void)l;
+}
+
+// Flush a per-wavefront u32 LDS histogram into a global u64 histogram.
+__device__ __forceinline__ void flush_hist(uint32_t* hist_l, uint64_t* hist_g, int n_bins) {
+    for (int b = lane_id(); b < n_bins; b += kWave) {
+        const uint32_t v = hist_l[b];
+        if (v) atomicAdd((unsigned long long*)&hist_g[b], (unsigned long long)v);
+        hist_l[b] = 0;
+    }
+    wave_sync();
+}
+
+// Bin of the k-th neighbour's FP64 distance (kb_nbins when missing).
+__device__ __forceinline__ int kth_bin(int found, int k, const uint64_t* kbuf, const float* xyz, float px,
+                                       float py, float pz, const double* KE2, int kb_nbins, double kb_inv_w64) {
+    if (found < k) return kb_nbins;
+    const uint32_t j = (uint32_t)kbuf[k - 1];
+    return exact_bin(exact_D2(px, py, pz, xyz[3 * (size_t)j], xyz[3 * (size_t)j + 1], xyz[3 * (size_t)j + 2]),
+                     KE2, kb_nbins, kb_inv_w64);
+}
+
+}  // namespace apt

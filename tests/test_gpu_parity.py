@@ -294,3 +294,135 @@ def test_permute_labels_bit_exact(gpu, orc, synth, n, seed):
     out = aptstat.permute_labels(dl, seed, ws=ws, status=status).cpu().numpy()
     assert int(status.item()) == 0
     assert np.array_equal(out, orc.permute_labels(lab, seed))
+
+
+# ---------------------------------------------------------------------------
+# batched null-model replicates
+# ---------------------------------------------------------------------------
+
+PAIRS6 = [(AL, SC), (AL, SI), (SC, AL), (SC, SI), (SI, AL), (SI, SC)]
+
+
+def _looped(gpu, cloud_args, pairs, seeds, d_srf, r_max, n_bins, k, kb_rmax, kb_nbins):
+    """The definition: plain calls on apt_permute_labels' labels."""
+    aptstat, torch, ws = gpu
+    xyz_t, lab_t, d_t = cloud_args
+    out_r, out_k = [], []
+    for sd in seeds:
+        lab_r = aptstat.permute_labels(lab_t, sd, ws=ws)
+        cloud = aptstat.Cloud(xyz_t, lab_r, d_t)
+        rr, kk = [], []
+        for A, B in pairs:
+            r = aptstat.knn_rdf(cloud, A, B, d_srf, k, r_max=r_max, n_bins=n_bins, capacity=0,
+                                kb_rmax=kb_rmax, kb_nbins=kb_nbins, ws=ws)
+            rr.append(r.rdf_hist.clone())
+            kk.append(r.knn_hist.clone())
+        out_r.append(torch.stack(rr))
+        out_k.append(torch.stack(kk))
+    return torch.stack(out_r), torch.stack(out_k)
+
+
+def test_batched_matches_oracle_on_permuted_labels(gpu, orc, small_needle):
+    _say("case batched small needle vs oracle")
+    aptstat, torch, ws = gpu
+    xyz, lab, d = small_needle
+    seeds = [101, 202, 303]
+    pairs = [(A, B, 1.0) for A, B in PAIRS6]
+    cloud = aptstat.Cloud(*_to_dev(torch, xyz, lab, d))
+    rh, kh, st = aptstat.rdf_batched(cloud, pairs, seeds, r_max=2.0, n_bins=200, k=10, kb_rmax=5.0,
+                                     kb_nbins=500, ws=ws)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    rh, kh = rh.cpu().numpy().astype(np.uint64), kh.cpu().numpy().astype(np.uint64)
+    for r, sd in enumerate(seeds):
+        lab_r = orc.permute_labels(lab, sd)
+        for p, (A, B, ds) in enumerate(pairs):
+            assert np.array_equal(rh[r, p], orc.rdf(xyz, lab_r, d, A, B, ds, 2.0, 200)), (r, p)
+            assert np.array_equal(kh[r, p], orc.knn(xyz, lab_r, d, A, B, ds, 10, kb_rmax=5.0, kb_nbins=500)[3]), (r, p)
+
+
+def test_batched_equals_looped_frustum7m(gpu, needle7m):
+    _say("case batched frustum7m vs looped plain calls")
+    aptstat, torch, ws = gpu
+    xyz, lab, d = needle7m
+    args = _to_dev(torch, xyz, lab, d)
+    seeds = [7, 8]
+    pairs = [(A, B, 1.0) for A, B in PAIRS6]
+    rh, kh, st = aptstat.rdf_batched(aptstat.Cloud(*args), pairs, seeds, ws=ws)
+    lr, lk = _looped(gpu, args, PAIRS6, seeds, 1.0, 2.0, 200, 10, 5.0, 5000)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    assert torch.equal(rh, lr) and torch.equal(kh, lk)
+
+
+def test_batched_many_replicates_cross_blocks(gpu, synth):
+    _say("case batched 70 replicates (two launches)")
+    aptstat, torch, ws = gpu
+    s = synth.Specimen(shape="box", L=(12.0, 12.0, 12.0), n=20_000, seed=31, p_m_sc=0.05, p_m_si=0.1)
+    xyz, lab, d = s.generate()
+    args = _to_dev(torch, xyz, lab, d)
+    seeds = list(range(1000, 1070))
+    pairs = [(SC, SI), (SI, SI), (AL, SC)]
+    rh, kh, st = aptstat.rdf_batched(aptstat.Cloud(*args), [(A, B, 0.5) for A, B in pairs], seeds,
+                                     r_max=1.5, n_bins=30, k=3, kb_rmax=3.0, kb_nbins=60, ws=ws)
+    lr, lk = _looped(gpu, args, pairs, seeds, 0.5, 1.5, 30, 3, 3.0, 60)
+    torch.cuda.synchronize()
+    assert torch.equal(rh, lr) and torch.equal(kh, lk)
+
+
+# ---------------------------------------------------------------------------
+# 64 targets per wavefront (tile mode) and one target per wavefront, forced
+# ---------------------------------------------------------------------------
+
+@pytest.fixture()
+def policy(gpu):
+    aptstat = gpu[0]
+    yield aptstat.set_tuning
+    aptstat.set_tuning()          # back to the defaults
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("A,B,k,d_srf,r_knn_max,rdf", [
+    (SC, SC, 10, 1.0, math.inf, True), (AL, SC, 10, 1.0, math.inf, True), (AL, SI, 4, 1.0, math.inf, True),
+    (ANY, SC, 1, 0.5, math.inf, True), (SC, ANY, 16, 1.0, math.inf, True), (AL, SC, 10, 1.0, 1.2, True),
+    (AL, AL, 3, 2.0, math.inf, True), (AL, SC, 7, 1.0, math.inf, False), (SI, SI, 12, 0.0, math.inf, True),
+])
+def test_needle_queries_forced_mode(gpu, orc, small_needle, policy, mode, A, B, k, d_srf, r_knn_max, rdf):
+    _say(f"case needle mode={mode} A={A} B={B} k={k} d_srf={d_srf} rknn={r_knn_max} rdf={rdf}")
+    policy(tile_policy=mode)
+    xyz, lab, d = small_needle
+    g = run_gpu(gpu, xyz, lab, d, A, B, d_srf, k=k, r_knn_max=r_knn_max, want_rdf=rdf)
+    check_against_oracle(orc, g, xyz, lab, d, A, B, d_srf, k=k, r_knn_max=r_knn_max, want_rdf=rdf)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_rdf_only_forced_mode(gpu, orc, small_needle, policy, mode):
+    _say(f"case needle rdf-only mode={mode}")
+    policy(tile_policy=mode)
+    xyz, lab, d = small_needle
+    g = run_gpu(gpu, xyz, lab, d, AL, SC, 1.0, k_on=False)
+    check_against_oracle(orc, g, xyz, lab, d, AL, SC, 1.0, k_on=False)
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_edge_cases_forced_mode(gpu, orc, synth, policy, mode):
+    _say(f"case edge cases mode={mode}")
+    policy(tile_policy=mode)
+    xyz = np.array([[1, 1, 1], [1, 1, 1], [1, 1, 1], [1.5, 1, 1], [3, 3, 3], [np.nan, 0, 0]], np.float32)
+    lab = np.array([SC, SC, AL, AL, SC, SC], np.uint8)
+    for A, B in ((SC, ANY), (SC, SC), (ANY, ANY), (AL, SC)):
+        g = run_gpu(gpu, xyz, lab, None, A, B, 0.0, k=3, r_max=1.0, n_bins=10)
+        check_against_oracle(orc, g, xyz, lab, None, A, B, 0.0, k=3, r_max=1.0, n_bins=10)
+    s = synth.Specimen(shape="box", L=(8.0, 8.0, 8.0), n=3000, seed=23, p_m_sc=0.3)
+    xyz, lab, d = s.generate()
+    g = run_gpu(gpu, xyz, lab, None, AL, SC, 0.0, k=4, capacity=50)
+    check_against_oracle(orc, g, xyz, lab, None, AL, SC, 0.0, k=4)
+
+
+@pytest.mark.parametrize("A,B", [(AL, SC), (AL, SI)])
+def test_frustum7m_dense_targets(gpu, orc, needle7m, A, B):
+    _say(f"case frustum7m dense targets A={A} B={B} (automatic mode)")
+    xyz, lab, d = needle7m
+    g = run_gpu(gpu, xyz, lab, d, A, B, 1.0, k=10)
+    assert g["status"] == 0
+    check_against_oracle(orc, g, xyz, lab, d, A, B, 1.0, k=10)
