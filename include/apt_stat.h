@@ -172,6 +172,40 @@ apt_status apt_rdf_batched(const apt_cloud* cloud, const apt_query* pairs, int32
                            uint64_t* knn_hist, const void* tuning, int32_t* status, void* ws, size_t ws_bytes,
                            void* stream);
 
+/* Gaussian-smoothed RDF, an extension (not in the paper) of the RDF's
+ * rectangular transfer function (paper, Methods: "Descriptive, two-point
+ * spatial statistics") that is differentiable in the positions and in a
+ * scale factor s of the z axis (the reconstruction parameter to fit).
+ * Positions are taken as (x, y, s*z); d_bnd is not rescaled.  Every ordered
+ * pair (eligible target i of species A, neighbour j != i of species B) at
+ * FP64 distance D < r_max + 6 sigma adds to each bin b whose interval meets
+ * (D - 6 sigma, D + 6 sigma) the Gaussian mass
+ *   w_b(D) = Phi((e_{b+1} - D) / sigma) - Phi((e_b - D) / sigma),
+ * with e_b = b * r_max / n_bins and Phi the standard normal distribution
+ * function (evaluated from the tail that does not cancel).
+ *   sigma        > 0, at most (1021 bin widths) / 12
+ *   z_scale      device double [1] (s), or NULL for s = 1
+ *   h            [bins.n_bins] FP64, device, overwritten
+ * bins.n_bins <= 4096.  Arithmetic after an FP32 culling test is FP64; the
+ * result is reproducible bit for bit.  Ions with a non-finite (scaled)
+ * position take part in no pair and set APT_STATUS_NONFINITE.
+ * Workspace: APT_OP_SMOOTH. */
+apt_status apt_rdf_smooth_fwd(const apt_cloud* cloud, apt_query q, apt_bins bins, float sigma, const double* z_scale,
+                              double* h, int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of apt_rdf_smooth_fwd: given grad_h = dL/dh [bins.n_bins] (FP64,
+ * device), writes
+ *   grad_xyz     [n][3] FP32, device, overwritten: dL/d(x, y, z) of every
+ *                ion (0 for ions in no pair); accumulated in FP64
+ *   grad_z_scale device double [1], dL/ds, or NULL to skip
+ * with g = sum_b grad_h[b] dw_b/dD for each pair; a pair at D = 0 adds
+ * nothing.  Pair lists are recomputed, not stored; each ion gathers its own
+ * gradient over its pairs in both roles (no atomics), so the result is
+ * reproducible bit for bit.  Arguments otherwise as the forward. */
+apt_status apt_rdf_smooth_bwd(const apt_cloud* cloud, apt_query q, apt_bins bins, float sigma, const double* z_scale,
+                              const double* grad_h, float* grad_xyz, double* grad_z_scale, int32_t* status, void* ws,
+                              size_t ws_bytes, void* stream);
+
 /* Number of eligible targets of a query, for sizing kNN outputs:
  * n_targets[1] (int64, device) is overwritten.  Workspace as APT_OP_KNN. */
 apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_targets, void* ws,

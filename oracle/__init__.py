@@ -54,6 +54,8 @@ def _load():
             "orc_permute_labels": ([_p, _i64, _u64, _p], None),
             "orc_smooth_fwd": ([_p, _p, _p, _i64, _i32, _i32, _f32, _f32, _i32, _f32, _f64, _p], None),
             "orc_smooth_bwd": ([_p, _p, _p, _i64, _i32, _i32, _f32, _f32, _i32, _f32, _f64, _p, _p, _p], None),
+            "orc_smooth_fd": ([_p, _p, _p, _i64, _i32, _i32, _f32, _f32, _i32, _f32, _f64, _p, _p, _i64, _f64, _p],
+                              None),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -172,3 +174,17 @@ def smooth_bwd(xyz, lab, d_bnd, A: int, B: int, d_srf: float, r_max: float, n_bi
     _load().orc_smooth_bwd(xyz.ctypes.data, lab.ctypes.data, _ptr(d_bnd), xyz.shape[0], A, B, d_srf,
                            r_max, n_bins, sigma, s, gh.ctypes.data, g.ctypes.data, gs.ctypes.data)
     return g, float(gs[0])
+
+
+def smooth_fd(xyz, lab, d_bnd, A: int, B: int, d_srf: float, r_max: float, n_bins: int, sigma: float,
+              s: float, resid, ions, step: float = 1e-4) -> np.ndarray:
+    """Central finite differences of sum_b (h_b - t_b)^2 (resid = h - t) with
+    respect to the coordinates of `ions`: float64 [len(ions), 3]."""
+    xyz, lab, d_bnd = _cloud(xyz, lab, d_bnd)
+    r = np.ascontiguousarray(resid, dtype=np.float64)
+    assert r.shape == (n_bins,)
+    ids = np.ascontiguousarray(ions, dtype=np.int64)
+    fd = np.zeros((len(ids), 3), dtype=np.float64)
+    _load().orc_smooth_fd(xyz.ctypes.data, lab.ctypes.data, _ptr(d_bnd), xyz.shape[0], A, B, d_srf, r_max, n_bins,
+                          sigma, s, r.ctypes.data, ids.ctypes.data, len(ids), step, fd.ctypes.data)
+    return fd

@@ -645,3 +645,102 @@ void orc_smooth_bwd(const float* xyz, const uint8_t* lab, const float* d_bnd, in
     *grad_s = st.grad_s;
     free((void*)st.e);
 }
+
+/* Central finite differences of L = sum_b (h_b - t_b)^2 with respect to the
+ * stored coordinates of a list of ions, step `step` (nm), given
+ * resid[b] = h_b - t_b at the unperturbed positions.  Moving one ion changes
+ * only the pairs it takes part in (as target and as neighbour), so with
+ * c(P) = the smoothed counts of those pairs with the ion at P and
+ * dp = c(P + step) - c(P), dm = c(P - step) - c(P):
+ *   L(+) - L(-) = sum_b (dp_b - dm_b) (2 resid_b + dp_b + dm_b)
+ * exactly; fd = that / (2 step).  Serial. */
+static void ion_pairs_at(const smooth_state* st, const float* xyz, const uint8_t* lab, const float* d_bnd,
+                         int32_t A, int32_t B, float d_srf, double cut, const ogrid* gB, const ogrid* gA,
+                         const scaled_ctx* ctx, int64_t m, const double P[3], double* c) {
+    const int as_target = is_target(m, lab, d_bnd, A, d_srf);
+    const int as_nbr = is_species(lab[m], B);
+    for (int role = 0; role < 2; ++role) {
+        if (role == 0 && !as_target) continue;
+        if (role == 1 && !as_nbr) continue;
+        const ogrid* g = role == 0 ? gB : gA;
+        int64_t cc[3];
+        for (int a = 0; a < 3; ++a) cc[a] = ocell_axis(g, a, P[a]);
+        for (int64_t z = cc[2] - 1; z <= cc[2] + 1; ++z) {
+            if (z < 0 || z >= g->dim[2]) continue;
+            for (int64_t y = cc[1] - 1; y <= cc[1] + 1; ++y) {
+                if (y < 0 || y >= g->dim[1]) continue;
+                for (int64_t x = cc[0] - 1; x <= cc[0] + 1; ++x) {
+                    if (x < 0 || x >= g->dim[0]) continue;
+                    int64_t cell = (z * g->dim[1] + y) * g->dim[0] + x;
+                    for (int64_t t = g->start[cell]; t < g->start[cell + 1]; ++t) {
+                        int64_t j = g->item[t];
+                        if (j == m) continue;
+                        if (role == 1 && !is_target(j, lab, d_bnd, A, d_srf)) continue;
+                        double dX = pos_scaled(ctx, j, 0) - P[0];
+                        double dY = pos_scaled(ctx, j, 1) - P[1];
+                        double dZ = pos_scaled(ctx, j, 2) - P[2];
+                        double D = sqrt(((dX * dX) + (dY * dY)) + (dZ * dZ));
+                        if (!(D < cut)) continue;
+                        int32_t b0, b1;
+                        window(st, D, &b0, &b1);
+                        for (int32_t b = b0; b <= b1; ++b)
+                            c[b] += bin_mass((st->e[b] - D) / st->sigma, (st->e[b + 1] - D) / st->sigma);
+                    }
+                }
+            }
+        }
+    }
+    (void)xyz;
+}
+
+void orc_smooth_fd(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n, int32_t A, int32_t B,
+                   float d_srf, float r_max, int32_t n_bins, float sigma, double s, const double* resid,
+                   const int64_t* ions, int64_t n_ions, double step, double* fd) {
+    smooth_state st;
+    memset(&st, 0, sizeof st);
+    st.e = bin_edges(r_max, n_bins);
+    st.n_bins = n_bins;
+    st.sigma = (double)sigma;
+    const double cut = (double)r_max + 6.0 * (double)sigma;
+    const double reach = cut * (1.0 + 1e-6) + 2.0 * step * (fabs(s) > 1.0 ? fabs(s) : 1.0);
+    scaled_ctx ctx = {xyz, s};
+    ogrid gB, gA;
+    ogrid_build(&gB, n, lab, B, pos_scaled, &ctx, reach);
+    ogrid_build(&gA, n, lab, A, pos_scaled, &ctx, reach);
+    double* c0 = (double*)malloc(sizeof(double) * (size_t)n_bins);
+    double* cp = (double*)malloc(sizeof(double) * (size_t)n_bins);
+    double* cm = (double*)malloc(sizeof(double) * (size_t)n_bins);
+    for (int64_t q = 0; q < n_ions; ++q) {
+        const int64_t m = ions[q];
+        for (int a = 0; a < 3; ++a) fd[3 * q + a] = 0.0;
+        if (!finite3(xyz + 3 * m)) continue;
+        double P0[3];
+        for (int a = 0; a < 3; ++a) P0[a] = pos_scaled(&ctx, m, a);
+        memset(c0, 0, sizeof(double) * (size_t)n_bins);
+        ion_pairs_at(&st, xyz, lab, d_bnd, A, B, d_srf, cut, &gB, &gA, &ctx, m, P0, c0);
+        for (int a = 0; a < 3; ++a) {
+            double P[3];
+            memset(cp, 0, sizeof(double) * (size_t)n_bins);
+            memset(cm, 0, sizeof(double) * (size_t)n_bins);
+            for (int sg = 0; sg < 2; ++sg) {
+                for (int u = 0; u < 3; ++u) P[u] = P0[u];
+                const double v = (double)xyz[3 * m + a] + (sg == 0 ? step : -step);
+                P[a] = a == 2 ? s * v : v;
+                ion_pairs_at(&st, xyz, lab, d_bnd, A, B, d_srf, cut, &gB, &gA, &ctx, m, P, sg == 0 ? cp : cm);
+            }
+            double dL = 0.0;
+            for (int32_t b = 0; b < n_bins; ++b) {
+                const double dp = cp[b] - c0[b], dm = cm[b] - c0[b];
+                dL += (dp - dm) * (2.0 * resid[b] + dp + dm);
+            }
+            fd[3 * q + a] = dL / (2.0 * step);
+        }
+    }
+    free(c0);
+    free(cp);
+    free(cm);
+    ogrid_free(&gB);
+    ogrid_free(&gA);
+    free((void*)st.e);
+}
+

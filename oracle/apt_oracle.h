@@ -65,6 +65,12 @@ void orc_smooth_fwd(const float* xyz, const uint8_t* lab, const float* d_bnd, in
 void orc_smooth_bwd(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n,
                     int32_t A, int32_t B, float d_srf, float r_max, int32_t n_bins, float sigma,
                     double s, const double* grad_h, double* grad_xyz, double* grad_s);
+/* Central finite differences of L = sum_b (h_b - t_b)^2 (resid = h - t) with
+ * respect to the coordinates of ions[0..n_ions), from the pairs each ion
+ * takes part in; fd[n_ions][3]. */
+void orc_smooth_fd(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n, int32_t A, int32_t B,
+                   float d_srf, float r_max, int32_t n_bins, float sigma, double s, const double* resid,
+                   const int64_t* ions, int64_t n_ions, double step, double* fd);
 
 #ifdef __cplusplus
 }

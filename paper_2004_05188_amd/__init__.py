@@ -72,6 +72,10 @@ _SIGS = {
                  _Bins, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_knn_rdf": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, ctypes.c_int32, ctypes.c_float, ctypes.c_int64,
                      _P, _P, _P, _Bins, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "apt_rdf_smooth_fwd": ([ctypes.POINTER(_Cloud), _Query, _Bins, ctypes.c_float, _P, _P, _P, _P, ctypes.c_size_t,
+                            _P], ctypes.c_int),
+    "apt_rdf_smooth_bwd": ([ctypes.POINTER(_Cloud), _Query, _Bins, ctypes.c_float, _P, _P, _P, _P, _P, _P,
+                            ctypes.c_size_t, _P], ctypes.c_int),
 }
 
 
@@ -330,3 +334,79 @@ def knn_rdf(cloud: Cloud, target: int, neighbor: int, d_srf: float, k: int, r_ma
 
 def knn(cloud: Cloud, target: int, neighbor: int, d_srf: float, k: int, **kw) -> KnnResult:
     return knn_rdf(cloud, target, neighbor, d_srf, k, want_rdf=False, **kw)
+
+
+# ---------------------------------------------------------------- smoothed RDF --
+def _zscale(z_scale, dev):
+    if z_scale is None:
+        return None
+    _need(z_scale, torch.float64, None, "z_scale")
+    if z_scale.numel() != 1:
+        raise AptError("z_scale must hold one value")
+    if z_scale.device != dev:
+        raise AptError("z_scale is on another device")
+    return z_scale
+
+
+def rdf_smooth(cloud: Cloud, target: int, neighbor: int, d_srf: float, r_max: float, n_bins: int, sigma: float,
+               z_scale: torch.Tensor | None = None, ws: Workspace | None = None, out: torch.Tensor | None = None,
+               status: torch.Tensor | None = None) -> torch.Tensor:
+    """Gaussian-smoothed RDF (float64 [n_bins]) with positions (x, y, s z),
+    s = z_scale (float64 device tensor with one value, or None for 1)."""
+    dev = cloud.device
+    zs = _zscale(z_scale, dev)
+    buf, nb = _ws(ws, OP_SMOOTH, cloud)
+    out = out if out is not None else torch.empty(n_bins, dtype=torch.float64, device=dev)
+    _need(out, torch.float64, (n_bins,), "out")
+    status = status if status is not None else torch.empty(1, dtype=torch.int32, device=dev)
+    _check(lib().apt_rdf_smooth_fwd(cloud.c(), _query(target, neighbor, d_srf), _bins(r_max, n_bins),
+                                    float(sigma), _ptr(zs), _ptr(out), _ptr(status), _ptr(buf), nb,
+                                    _stream(cloud.xyz)), "apt_rdf_smooth_fwd")
+    return out
+
+
+def rdf_smooth_grad(cloud: Cloud, target: int, neighbor: int, d_srf: float, r_max: float, n_bins: int,
+                    sigma: float, grad_h: torch.Tensor, z_scale: torch.Tensor | None = None,
+                    want_grad_s: bool = True, ws: Workspace | None = None, status: torch.Tensor | None = None):
+    """Adjoint of rdf_smooth: (dL/dxyz float32 [n, 3], dL/ds float64 [1] or None)."""
+    dev = cloud.device
+    zs = _zscale(z_scale, dev)
+    _need(grad_h, torch.float64, (n_bins,), "grad_h")
+    buf, nb = _ws(ws, OP_SMOOTH, cloud)
+    gx = torch.empty((cloud.n, 3), dtype=torch.float32, device=dev)
+    gs = torch.empty(1, dtype=torch.float64, device=dev) if want_grad_s else None
+    status = status if status is not None else torch.empty(1, dtype=torch.int32, device=dev)
+    _check(lib().apt_rdf_smooth_bwd(cloud.c(), _query(target, neighbor, d_srf), _bins(r_max, n_bins),
+                                    float(sigma), _ptr(zs), _ptr(grad_h), _ptr(gx), _ptr(gs), _ptr(status),
+                                    _ptr(buf), nb, _stream(cloud.xyz)), "apt_rdf_smooth_bwd")
+    return gx, gs
+
+
+class RdfSmooth(torch.autograd.Function):
+    """h = RdfSmooth.apply(xyz, z_scale, lab, d_bnd, target, neighbor, d_srf, r_max, n_bins, sigma)
+
+    Differentiable in xyz (float32 [n, 3]) and z_scale (float64 tensor with
+    one value); the backward recomputes the pairs in the library's adjoint
+    kernel.  lab and d_bnd are constants (d_bnd may be None)."""
+
+    @staticmethod
+    def forward(ctx, xyz, z_scale, lab, d_bnd, target, neighbor, d_srf, r_max, n_bins, sigma):
+        xyz_d = xyz.detach()
+        zs = z_scale.detach().reshape(1) if z_scale is not None else None
+        cloud = Cloud(xyz_d, lab, d_bnd)
+        h = rdf_smooth(cloud, target, neighbor, d_srf, r_max, n_bins, sigma, z_scale=zs)
+        ctx.save_for_backward(xyz_d, zs, lab, d_bnd)
+        ctx.args = (target, neighbor, d_srf, r_max, n_bins, sigma)
+        ctx.zshape = None if z_scale is None else z_scale.shape
+        return h
+
+    @staticmethod
+    def backward(ctx, grad_h):
+        xyz, zs, lab, d_bnd = ctx.saved_tensors
+        target, neighbor, d_srf, r_max, n_bins, sigma = ctx.args
+        want_s = zs is not None and ctx.needs_input_grad[1]
+        gx, gs = rdf_smooth_grad(Cloud(xyz, lab, d_bnd), target, neighbor, d_srf, r_max, n_bins, sigma,
+                                 grad_h.contiguous().to(torch.float64), z_scale=zs, want_grad_s=want_s)
+        return (gx if ctx.needs_input_grad[0] else None, gs.reshape(ctx.zshape) if want_s else None,
+                None, None, None, None, None, None, None, None)
+

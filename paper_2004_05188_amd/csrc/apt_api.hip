@@ -11,6 +11,7 @@
 #include "apt_bin.hpp"
 #include "apt_pair.hpp"
 #include "apt_perm.hpp"
+#include "apt_smooth.hpp"
 
 namespace apt {
 
@@ -340,21 +341,25 @@ __global__ void k_finish(FinishArgs a) {
 // workspace: plan, tid (eligible targets ascending), order (their ranks in
 // cell order, with rank, index and position), neighbour SoA in cell order
 // and cell_start.
+// zscale (device, may be NULL) scales z before binning; sel_union makes
+// targets and neighbours both the ions that take part in a pair in either
+// role.
 static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams& pp, const PlainWs& w,
-                              int32_t* status, hipStream_t st) {
+                              int32_t* status, hipStream_t st, const double* zscale = nullptr,
+                              int sel_union = 0) {
     const int64_t n = cl->n;
     const int G = count_blocks(n);
     const int64_t chunk = count_chunk(n, G);
     const int cus = device_info().cus;
 
-    CountArgs ca{cl->xyz, cl->lab, cl->d_bnd, n, chunk, q.target, q.neighbor, q.d_srf, nullptr,
-                 w.part_cnt, w.part_bbox, w.part_nf};
+    CountArgs ca{cl->xyz, cl->lab, cl->d_bnd, n, chunk, q.target, q.neighbor, q.d_srf, zscale,
+                 w.part_cnt, w.part_bbox, w.part_nf, sel_union};
     hipLaunchKernelGGL(k_count, dim3(G), dim3(kBlock), 0, st, ca);
-    PlanArgs pa{G, w.part_cnt, w.part_bbox, w.part_nf, w.part_off, pp, nullptr, w.plan, status};
+    PlanArgs pa{G, w.part_cnt, w.part_bbox, w.part_nf, w.part_off, pp, zscale, w.plan, status};
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, pa);
     const bool all_b = q.neighbor == APT_ANY;
     CompactArgs cm{cl->lab, cl->d_bnd, n, chunk, q.target, q.neighbor, q.d_srf, w.part_off, w.tid,
-                   all_b ? nullptr : w.bsel};
+                   all_b ? nullptr : w.bsel, sel_union};
     hipLaunchKernelGGL(k_compact, dim3(G), dim3(kBlock), 0, st, cm);
 
     const int passes = sort_passes_max(pp.cell_cap);
@@ -369,16 +374,16 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
         }
     };
     // targets in cell order
-    KeyArgs kt{w.plan, cl->xyz, w.tid, nullptr, 1, 1, w.K[0], w.V[0]};
+    KeyArgs kt{w.plan, cl->xyz, w.tid, zscale, 1, 1, w.K[0], w.V[0]};
     hipLaunchKernelGGL(k_keys, dim3(Gk), dim3(kBlock), 0, st, kt);
     sort(1);
     OrderArgs oa{w.plan, cl->xyz, w.tid, {w.V[0], w.V[1]}, w.t_rank, w.t_id, w.tx, w.ty, w.tz};
     hipLaunchKernelGGL(k_take_order, dim3(Gk), dim3(kBlock), 0, st, oa);
     // neighbours in cell order
-    KeyArgs kb{w.plan, cl->xyz, all_b ? nullptr : w.bsel, nullptr, 0, 0, w.K[0], w.V[0]};
+    KeyArgs kb{w.plan, cl->xyz, all_b ? nullptr : w.bsel, zscale, 0, 0, w.K[0], w.V[0]};
     hipLaunchKernelGGL(k_keys, dim3(Gk), dim3(kBlock), 0, st, kb);
     sort(0);
-    GatherArgs ga{w.plan, cl->xyz, nullptr, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.bpos, w.cell_start};
+    GatherArgs ga{w.plan, cl->xyz, zscale, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.bpos, w.cell_start};
     hipLaunchKernelGGL(k_gather, dim3(Gk), dim3(kBlock), 0, st, ga);
     return hip_check("binning launch");
 }
@@ -679,6 +684,116 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
     return hip_check("batched launch");
 }
 
+// Workspace of the smoothed RDF: the plain binning, the edges and the
+// per-wavefront partial results.
+constexpr size_t kSmoothPart = (size_t)1 << 21;
+struct SmoothWs {
+    PlainWs plain;
+    double* E;
+    double* part;
+    size_t bytes;
+};
+static SmoothWs carve_smooth(void* base, int64_t n) {
+    SmoothWs w;
+    w.plain = carve_plain(base, n);
+    Carve c{base ? reinterpret_cast<char*>(base) + w.plain.bytes : nullptr};
+    w.E = c.take<double>(kSmoothMaxBins + 1);
+    w.part = c.take<double>(kSmoothPart);
+    w.bytes = w.plain.bytes + c.off;
+    return w;
+}
+
+// Forward (bwd == false: h) or adjoint (grad_h -> grad_xyz, grad_s).
+static apt_status run_smooth(bool bwd, const apt_cloud* cl, apt_query q, apt_bins rb, float sigma,
+                             const double* zscale, double* h, const double* grad_h, float* grad_xyz,
+                             double* grad_s, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+    apt_status s;
+    if ((s = check_cloud(cl)) != APT_OK) return s;
+    if ((s = check_query(q)) != APT_OK) return s;
+    if ((s = check_bins(rb, "bins")) != APT_OK) return s;
+    if (rb.n_bins > kSmoothMaxBins) return fail(APT_E_UNSUPPORTED, "smoothed RDF supports at most 4096 bins");
+    if (!(sigma > 0.0f) || !isfinite(sigma)) return fail(APT_E_ARG, "sigma must be finite and > 0");
+    if (!status) return fail(APT_E_ARG, "status is NULL");
+    if (!bwd && !h) return fail(APT_E_ARG, "h is NULL");
+    if (bwd && !grad_h) return fail(APT_E_ARG, "grad_h is NULL");
+    if (bwd && cl->n > 0 && !grad_xyz) return fail(APT_E_ARG, "grad_xyz is NULL");
+    const double sig = (double)sigma;
+    const double w6 = 6.0 * sig;
+    const double cut = (double)rb.r_max + 6.0 * sig;
+    const double width = (double)rb.r_max / rb.n_bins;
+    const double mw = floor(2.0 * w6 / width) + 3.0;     // most bins one window meets, with a margin
+    if (!(mw <= (double)kSmoothTerms))
+        return fail(APT_E_UNSUPPORTED, "sigma spans more than 1021 bins (12 sigma / bin width)");
+    if (!((float)(cut * (1.0 + 2e-5)) < 1e30f)) return fail(APT_E_ARG, "r_max + 6 sigma is too large");
+    SmoothWs w = carve_smooth(ws, cl->n);
+    if ((s = check_ws(ws, ws_bytes, w.bytes)) != APT_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    const int cus = device_info().cus;
+
+    InitArgs ia{status, nullptr, 0, nullptr, 0, nullptr, nullptr};
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, ia);
+    hipLaunchKernelGGL(k_smooth_edges, dim3(16), dim3(256), 0, st, w.E, rb.r_max, rb.n_bins);
+    if (bwd && cl->n > 0) hipLaunchKernelGGL(k_fill_f32, dim3(cus * 4), dim3(256), 0, st, grad_xyz, 3 * cl->n);
+
+    const apt_tuning tu = tuning();
+    const float r_pre = (float)(cut * (1.0 + 2e-5));
+    PlanParams pp;
+    pp.h_min = r_pre * tu.h_min_frac;
+    pp.occ = tu.cell_occ;
+    pp.k = 0;
+    pp.cell_cap = cell_cap_for(cl->n);
+    pp.tile_policy = 1;
+    pp.r_enum = r_pre;
+    {
+        TraceSpan span("binning", st);
+        if ((s = run_binning(cl, q, pp, w.plain, status, st, zscale, bwd ? 1 : 0)) != APT_OK) return s;
+    }
+    SmoothArgs sa{};
+    sa.plan = w.plain.plan;
+    sa.xyz = cl->xyz;
+    sa.lab = cl->lab;
+    sa.d_bnd = cl->d_bnd;
+    sa.zscale = zscale;
+    sa.t_id = w.plain.t_id;
+    sa.bpos = w.plain.bpos;
+    sa.cell_start = w.plain.cell_start;
+    sa.A = q.target;
+    sa.B = q.neighbor;
+    sa.d_srf = q.d_srf;
+    sa.uni = bwd ? 1 : 0;
+    sa.n_bins = rb.n_bins;
+    sa.hcap = (int)fmin(64.0, floor((double)kSmoothTerms / mw));
+    sa.r_pre = r_pre;
+    sa.sigma = sig;
+    sa.cut = cut;
+    sa.w6 = w6;
+    sa.inv_width = rb.n_bins / (double)rb.r_max;
+    sa.E = w.E;
+    sa.grad_h = grad_h;
+    sa.part = w.part;
+    sa.grad_xyz = grad_xyz;
+    if (!bwd) {
+        int W = (int)(kSmoothPart / (size_t)rb.n_bins);
+        if (W > kSmoothWaves) W = kSmoothWaves;
+        sa.W = W;
+        TraceSpan span("smooth", st);
+        hipLaunchKernelGGL(k_smooth_fwd, dim3(W), dim3(kWave), smooth_lds_bytes(true, rb.n_bins), st, sa);
+        SmoothReduceArgs ra{w.part, W, rb.n_bins, h};
+        hipLaunchKernelGGL(k_smooth_reduce, dim3((rb.n_bins + 255) / 256), dim3(256), 0, st, ra);
+    } else {
+        sa.W = kSmoothWaves;
+        TraceSpan span("smooth", st);
+        hipLaunchKernelGGL(k_smooth_bwd, dim3(kSmoothWaves), dim3(kWave), smooth_lds_bytes(false, rb.n_bins), st,
+                           sa);
+        if (grad_s) {
+            SmoothReduceArgs ra{w.part, kSmoothWaves, 1, grad_s};
+            hipLaunchKernelGGL(k_smooth_reduce, dim3(1), dim3(64), 0, st, ra);
+        }
+    }
+    return hip_check("smoothed RDF launch");
+}
+
 }  // namespace apt
 
 using namespace apt;
@@ -749,6 +864,8 @@ size_t apt_workspace_size(int32_t op, int64_t n, int32_t n_pairs, int32_t n_rep)
         case APT_OP_BATCHED:
             if (n_rep < 1) return 0;
             return carve_batched(nullptr, n, batch_reps(n, n_rep)).bytes;
+        case APT_OP_SMOOTH:
+            return carve_smooth(nullptr, n).bytes;
         default:
             return 0;
     }
@@ -823,6 +940,19 @@ apt_status apt_knn_rdf(const apt_cloud* cloud, apt_query q, apt_bins rdf_bins, u
     if (k < 1) return fail(APT_E_ARG, "k must be >= 1");
     return run_plain(cloud, q, &rdf_bins, rdf_hist, k, r_knn_max, capacity, target_id, dist, nbr_id,
                      &knn_bins, knn_hist, n_targets, status, ws, ws_bytes, stream);
+}
+
+apt_status apt_rdf_smooth_fwd(const apt_cloud* cloud, apt_query q, apt_bins bins, float sigma, const double* z_scale,
+                              double* h, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+    return run_smooth(false, cloud, q, bins, sigma, z_scale, h, nullptr, nullptr, nullptr, status, ws, ws_bytes,
+                      stream);
+}
+
+apt_status apt_rdf_smooth_bwd(const apt_cloud* cloud, apt_query q, apt_bins bins, float sigma, const double* z_scale,
+                              const double* grad_h, float* grad_xyz, double* grad_z_scale, int32_t* status, void* ws,
+                              size_t ws_bytes, void* stream) {
+    return run_smooth(true, cloud, q, bins, sigma, z_scale, nullptr, grad_h, grad_xyz, grad_z_scale, status, ws,
+                      ws_bytes, stream);
 }
 
 }  // extern "C"

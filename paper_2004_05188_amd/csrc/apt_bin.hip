@@ -27,9 +27,8 @@ __global__ __launch_bounds__(kBlock) void k_count(CountArgs a) {
     int nf = 0;
     const double sd = a.zscale ? *a.zscale : 1.0;
     for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
-        const uint8_t l = a.lab[i];
-        const bool isT = (a.A == APT_ANY || l == a.A) && (a.d_bnd == nullptr || a.d_bnd[i] >= a.d_srf);
-        const bool isB = (a.B == APT_ANY || l == a.B);
+        bool isT, isB;
+        select_ion(a.lab[i], a.d_bnd, i, a.A, a.B, a.d_srf, a.sel_union, &isT, &isB);
         nt += isT;
         nb += isB;
         float p[3] = {a.xyz[3 * i], a.xyz[3 * i + 1], a.xyz[3 * i + 2]};
@@ -247,9 +246,8 @@ __global__ __launch_bounds__(kBlock) void k_compact(CompactArgs a) {
             const int64_t i = tile + (int64_t)it * kBlock + threadIdx.x;
             bool isT = false, isB = false;
             if (i < end) {
-                const uint8_t l = a.lab[i];
-                isT = (a.A == APT_ANY || l == a.A) && (a.d_bnd == nullptr || a.d_bnd[i] >= a.d_srf);
-                isB = a.bsel != nullptr && (a.B == APT_ANY || l == a.B);
+                select_ion(a.lab[i], a.d_bnd, i, a.A, a.B, a.d_srf, a.sel_union, &isT, &isB);
+                isB = isB && a.bsel != nullptr;
             }
             mt[it] = __ballot(isT);
             mb[it] = __ballot(isB);

@@ -16,6 +16,7 @@ struct CountArgs {
     uint32_t* part_cnt;     // [G][2] targets, neighbours
     float* part_bbox;       // [G][6]
     int32_t* part_nf;       // [G]
+    int32_t sel_union;      // 1: targets and neighbours are both (eligible A) or B
 };
 
 struct PlanArgs {
@@ -40,6 +41,7 @@ struct CompactArgs {
     const uint32_t* part_off;
     uint32_t* tid;          // [nT]
     uint32_t* bsel;         // [nB] or NULL (neighbours = all ions)
+    int32_t sel_union;      // as CountArgs::sel_union
 };
 
 struct KeyArgs {
@@ -85,6 +87,21 @@ struct GatherArgs {
     float4* bpos;           // [nB] (x, y, z, ion index as bits) in cell order
     uint32_t* cell_start;   // [n_cells + 1]
 };
+
+// Target / neighbour membership of ion i.  In union mode both are the ions
+// that are an eligible target or a neighbour (the adjoint of the smoothed
+// RDF visits every ion that takes part in a pair, in either role).
+__device__ __forceinline__ void select_ion(uint8_t l, const float* d_bnd, int64_t i, int A, int B, float d_srf,
+                                           int sel_union, bool* isT, bool* isB) {
+    const bool t = (A == APT_ANY || l == A) && (d_bnd == nullptr || d_bnd[i] >= d_srf);
+    const bool b = (B == APT_ANY || l == B);
+    if (sel_union) {
+        *isT = *isB = t || b;
+    } else {
+        *isT = t;
+        *isB = b;
+    }
+}
 
 __global__ void k_count(CountArgs a);
 __global__ void k_plan(PlanArgs a);

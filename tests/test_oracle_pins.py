@@ -467,3 +467,34 @@ def test_smooth_adjoint_invariants(orc, synth):
             assert np.abs(torque).max() <= 1e-9 * scale * 5
         # dL/ds = (1/s) sum_i z_i dL/dz_i
         assert abs(gs - (P[:, 2] * g[:, 2]).sum() / s) <= 1e-9 * (abs(gs) + scale)
+
+
+def test_smooth_local_fd_equals_full_recompute(orc, synth):
+    """The per-ion finite differences (only the moved ion's pairs are
+    re-evaluated) equal differences of the full loss, in both roles."""
+    s = synth.Specimen(shape="box", L=(5.0, 5.0, 5.0), n=1500, seed=52, p_m_sc=0.3,
+                       n_clusters=3, r_c=0.8, p_c_sc=0.6)
+    xyz, lab, _ = s.generate()
+    d = (np.minimum(xyz.min(1), 5.0 - xyz.max(1))).astype(np.float32)   # distance to the box faces
+    rng = np.random.default_rng(3)
+    target = rng.uniform(0, 20, 50)
+    args = (SC, ANY, 0.4, 1.0, 50, 0.05)
+    for sc in (1.0, 1.05):
+        h = orc.smooth_fwd(xyz, lab, d, *args, sc)
+        ions = np.concatenate([rng.choice(np.flatnonzero(lab == SC), 3, replace=False),
+                               rng.choice(np.flatnonzero(lab != SC), 3, replace=False)])
+        step = 2.0 ** -12           # exact in FP32 at these coordinates
+        fd = orc.smooth_fd(xyz, lab, d, *args, sc, h - target, ions, step)
+        for q, i in enumerate(ions):
+            for a in range(3):
+                xp, xm = xyz.copy(), xyz.copy()
+                xp[i, a] += np.float32(step)
+                xm[i, a] -= np.float32(step)
+                Lp = ((orc.smooth_fwd(xp, lab, d, *args, sc) - target) ** 2).sum()
+                Lm = ((orc.smooth_fwd(xm, lab, d, *args, sc) - target) ** 2).sum()
+                full = (Lp - Lm) / (2 * step)
+                assert abs(fd[q, a] - full) <= 1e-7 * max(abs(full), 1.0), (sc, i, a, fd[q, a], full)
+        # and they agree with the adjoint to the truncation error of the step
+        g, _ = orc.smooth_bwd(xyz, lab, d, *args, sc, 2 * (h - target))
+        gi = g[ions]
+        assert np.abs(fd - gi).max() <= 2e-3 * np.abs(gi).max()
