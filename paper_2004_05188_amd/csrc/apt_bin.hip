@@ -215,7 +215,13 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
     P.rk_tile = pp.k > 0 ? (float)fmin(1.6 / 1.15 * (double)P.rk0, (double)P.r_all) : 0.0f;
     if (pp.tile_policy == 1) P.tile_mode = 0;
     else if (pp.tile_policy == 2) P.tile_mode = pp.k <= 16 ? 1 : 0;
-    else P.tile_mode = (pp.k <= 16 && totT >= totB && totT >= 4096) ? 1 : 0;
+    else {
+        // a tile pays when its 64 targets fill a region no larger than the
+        // search reach, so that they share most of their candidates
+        const double R = fmax((double)pp.r_enum, (double)P.rk_tile);
+        const double v64 = 64.0 * vol / (double)(totT > 0 ? totT : 1);
+        P.tile_mode = (pp.k <= 16 && totT >= totB && totT >= 4096 && v64 <= R * R * R) ? 1 : 0;
+    }
     *a.plan = P;
     if (s_nf[0] && a.status) atomicOr(a.status, APT_STATUS_NONFINITE);
 }
@@ -530,9 +536,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
 // 8. squared bin edges, e_b = b * r_max / n_bins in FP64
 // ------------------------------------------------------------------------
 __global__ void k_edges(double* E2, float r_max, int n_bins) {
+#pragma clang fp contract(off)
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b <= n_bins; b += gridDim.x * blockDim.x) {
-        const double e = __ddiv_rn(__dmul_rn((double)b, (double)r_max), (double)n_bins);
-        E2[b] = __dmul_rn(e, e);
+        const double e = ((double)b * (double)r_max) / (double)n_bins;
+        E2[b] = e * e;
     }
 }
 

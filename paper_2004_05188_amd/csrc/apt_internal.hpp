@@ -92,12 +92,17 @@ __device__ __forceinline__ uint32_t cell_id(const GridPlan& P, float x, float y,
 }
 
 // ------------------------------------------------------- exact binning --
-// FP64 squared distance of two stored FP32 positions, no fused operations.
+// FP64 squared distance of two stored FP32 positions, evaluated exactly as
+// ((dx*dx + dy*dy) + dz*dz) with every operation rounded on its own.  HIP's
+// __dmul_rn / __dadd_rn are inline functions whose operations may still be
+// fused after inlining, so plain operators are used under a no-contraction
+// pragma instead.
 __device__ __forceinline__ double exact_D2(float xi, float yi, float zi, float xj, float yj, float zj) {
-    double dx = __dsub_rn((double)xj, (double)xi);
-    double dy = __dsub_rn((double)yj, (double)yi);
-    double dz = __dsub_rn((double)zj, (double)zi);
-    return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+#pragma clang fp contract(off)
+    const double dx = (double)xj - (double)xi;
+    const double dy = (double)yj - (double)yi;
+    const double dz = (double)zj - (double)zi;
+    return (dx * dx + dy * dy) + dz * dz;
 }
 
 // Largest b with E2[b] <= D2, or n_bins when D2 >= E2[n_bins].

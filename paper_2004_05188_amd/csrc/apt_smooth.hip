@@ -34,7 +34,7 @@ size_t smooth_lds_bytes(bool fwd, int n_bins) {
 
 __global__ void k_smooth_edges(double* E, float r_max, int n_bins) {
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b <= n_bins; b += gridDim.x * blockDim.x)
-        E[b] = __ddiv_rn(__dmul_rn((double)b, (double)r_max), (double)n_bins);
+        E[b] = ((double)b * (double)r_max) / (double)n_bins;
 }
 
 __global__ void k_fill_f32(float* p, int64_t n) {
@@ -93,7 +93,7 @@ __device__ __forceinline__ void smooth_body(const SmoothArgs& a) {
     for (uint32_t t = blockIdx.x; t < P.nT; t += (uint32_t)a.W) {
         const uint32_t m = a.t_id[t];
         const float xm = a.xyz[3 * (size_t)m], ym = a.xyz[3 * (size_t)m + 1], zm = a.xyz[3 * (size_t)m + 2];
-        const double Xm = (double)xm, Ym = (double)ym, Zm = __dmul_rn(s, (double)zm);
+        const double Xm = (double)xm, Ym = (double)ym, Zm = s * (double)zm;
         const float pz = (float)Zm;
         const bool mT = BWD ? smooth_is_target(a, m) : true;
         const bool mB = BWD ? smooth_is_nbr(a, m) : false;
@@ -185,13 +185,13 @@ __device__ __forceinline__ void smooth_body(const SmoothArgs& a) {
                     }
                     if (t1 + t2 > 0) {
                         const float zo = a.xyz[3 * (size_t)o + 2];
-                        dX = __dsub_rn((double)c.x, Xm);
-                        dY = __dsub_rn((double)c.y, Ym);
-                        dZ = __dsub_rn(__dmul_rn(s, (double)zo), Zm);
-                        D = __dsqrt_rn(__dadd_rn(__dadd_rn(__dmul_rn(dX, dX), __dmul_rn(dY, dY)), __dmul_rn(dZ, dZ)));
+                        dX = (double)c.x - Xm;
+                        dY = (double)c.y - Ym;
+                        dZ = s * (double)zo - Zm;
+                        D = sqrt((dX * dX + dY * dY) + dZ * dZ);
                         hit = D < a.cut;
                         mul = (t1 + t2) | (t1 << 8);
-                        zz = __dsub_rn((double)zo, (double)zm);
+                        zz = (double)zo - (double)zm;
                     }
                 }
             }
