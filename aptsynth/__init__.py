@@ -204,3 +204,44 @@ def frustum2g(seed: int = 1, n: int = 2_000_000_000) -> Specimen:
 
 
 WORKLOADS = {"box240k": box240k, "frustum7m": frustum7m, "box1m": box1m, "frustum2g": frustum2g}
+
+
+def to_device(spec: Specimen, torch, device, with_d_bnd: bool = True, chunk: int = 1 << 25, on_chunk=None,
+              log=None):
+    """Generate the specimen chunk by chunk straight into device tensors.
+
+    Each chunk is generated into pinned host buffers and copied to the GPU
+    (two buffers, so generation overlaps the copy).  on_chunk(i0, xyz, lab,
+    d_bnd) may inspect each host chunk before it is reused.  Returns
+    (xyz float32 [n,3], lab uint8 [n], d_bnd float32 [n] or None) on device."""
+    n = spec.n
+    xyz_d = torch.empty((n, 3), dtype=torch.float32, device=device)
+    lab_d = torch.empty(n, dtype=torch.uint8, device=device)
+    d_d = torch.empty(n, dtype=torch.float32, device=device) if with_d_bnd else None
+    m = min(chunk, max(n, 1))
+    bufs = [(torch.empty((m, 3), dtype=torch.float32, pin_memory=True),
+             torch.empty(m, dtype=torch.uint8, pin_memory=True),
+             torch.empty(m, dtype=torch.float32, pin_memory=True)) for _ in range(2)]
+    events = [None, None]
+    stream = torch.cuda.Stream(device=device)
+    centres = spec.centres()
+    for q, i0 in enumerate(range(0, n, m)):
+        i1 = min(n, i0 + m)
+        b = q & 1
+        if events[b] is not None:
+            events[b].synchronize()          # the copy out of this buffer is done
+        hx, hl, hd = (t[: i1 - i0] for t in bufs[b])
+        spec.generate(i0, i1, hx.numpy(), hl.numpy(), hd.numpy(), centres=centres)
+        if on_chunk is not None:
+            on_chunk(i0, hx.numpy(), hl.numpy(), hd.numpy())
+        with torch.cuda.stream(stream):
+            xyz_d[i0:i1].copy_(hx, non_blocking=True)
+            lab_d[i0:i1].copy_(hl, non_blocking=True)
+            if d_d is not None:
+                d_d[i0:i1].copy_(hd, non_blocking=True)
+            events[b] = torch.cuda.Event()
+            events[b].record(stream)
+        if log is not None and (q % 8 == 7 or i1 == n):
+            log(f"generated {i1} of {n} ions")
+    stream.synchronize()
+    return xyz_d, lab_d, d_d

@@ -77,6 +77,17 @@ struct TraceSpan {
     }
 };
 
+// Grid of a one-target-per-wavefront kernel: exactly the workgroups that
+// fit on the device at once, so that the static deal of targets runs in a
+// single round (a second, partly filled round would leave CUs idle).  A
+// multiple of the CU count, hence of the XCD count.
+template <class K>
+static int resident_grid(K kern, size_t lds) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kBlock, lds) != hipSuccess || nb < 1) nb = 2;
+    return device_info().cus * nb;
+}
+
 // ------------------------------------------------------------ sizing --
 constexpr int kCountTile = 4096;
 
@@ -490,13 +501,12 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     pa.strag = w.strag;
     pa.strag_count = w.strag_count;
     const size_t lds = pair_lds_bytes(do_rdf, do_knn, n_bins, in_lds);
-    const int Gp = device_info().cus * 8;
     if (pp.tile_policy != 1) {
         // 64 targets per wavefront when the plan chooses it (exits otherwise)
         TraceSpan span("tile", st);
         const bool self = pa.self_possible != 0;
         const size_t tl = tile_lds_bytes(do_rdf, n_bins);
-        auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(Gp), dim3(kBlock), tl, st, pa); };
+        auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(resident_grid(kern, tl)), dim3(kBlock), tl, st, pa); };
         const int km = !do_knn ? 0 : k <= 4 ? 4 : k <= 10 ? 10 : 16;
         if (do_rdf) {
             if (km == 0) self ? go(k_pair_tile<kRdfLds | kSelf, 0>) : go(k_pair_tile<kRdfLds, 0>);
@@ -512,7 +522,7 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     {
         TraceSpan span("pair", st);
         const bool self = pa.self_possible != 0;
-        auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(Gp), dim3(kBlock), lds, st, pa); };
+        auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(resident_grid(kern, lds)), dim3(kBlock), lds, st, pa); };
         // RDF histograms in LDS unless there are too many bins
         if (do_rdf && !in_lds) {
             if (do_knn) self ? go(k_pair<kRdfGlobal | kSelf, true>) : go(k_pair<kRdfGlobal, true>);
