@@ -215,7 +215,7 @@ apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_tar
  * depend on it, only speed):
  *   tile_policy  0 automatic, 1 one target per wavefront, 2 64 targets per
  *                wavefront with LDS-staged neighbours and a register kNN list
- *                (used only when k <= 16 and n_bins <= 3072)
+ *                (used only when k <= 16 and n_bins <= 2048)
  *   cell_occ     neighbours per grid cell aimed at (default 4)
  *   h_min_frac   smallest cell edge as a fraction of r_max (default 0.5)
  * apt_set_tuning(NULL) restores the defaults. */

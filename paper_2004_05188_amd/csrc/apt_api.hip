@@ -88,6 +88,9 @@ static int resident_grid(K kern, size_t lds) {
     return device_info().cus * nb;
 }
 
+// LDS one workgroup may take
+constexpr size_t kMaxLds = 64u * 1024u;
+
 // ------------------------------------------------------------ sizing --
 constexpr int kCountTile = 4096;
 
@@ -373,10 +376,12 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
                    all_b ? nullptr : w.bsel, sel_union};
     hipLaunchKernelGGL(k_compact, dim3(G), dim3(kBlock), 0, st, cm);
 
+    // target keys (block-raster order) may need one byte more than cell ids
     const int passes = sort_passes_max(pp.cell_cap);
+    const int passes_T = passes < 4 ? passes + 1 : 4;
     const int Gk = cus * 8;
     auto sort = [&](int is_T) {
-        for (int p = 0; p < passes; ++p) {
+        for (int p = 0; p < (is_T ? passes_T : passes); ++p) {
             SortArgs sa{w.plan, is_T, p, kSortBlocks, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.rs_counts,
                         w.rs_totals};
             hipLaunchKernelGGL(k_rs_upsweep, dim3(kSortBlocks), dim3(kBlock), 0, st, sa);
@@ -434,14 +439,15 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     if (knn_hist) hipLaunchKernelGGL(k_edges, dim3(64), dim3(256), 0, st, w.KE2, kb->r_max, kb->n_bins);
 
     const apt_tuning tu = tuning();
-    const bool rdf_lds = do_rdf && (size_t)kWavesPerBlock * rb->n_bins * 4u <= 48u * 1024u;
+    const bool rdf_lds = do_rdf && pair_lds_bytes(true, do_knn, rb->n_bins, true) <= kMaxLds;
+    const bool tile_fits = !do_rdf || tile_lds_bytes(true, rb->n_bins) <= kMaxLds;
     PlanParams pp;
     pp.h_min = do_rdf ? rb->r_max * tu.h_min_frac : 0.0f;
     pp.occ = tu.cell_occ;
     pp.k = do_knn ? k : 0;
     pp.cell_cap = cell_cap_for(cl->n);
     // tiles need an LDS histogram and at most 16 kNN keys per lane
-    pp.tile_policy = ((do_rdf && !rdf_lds) || (do_knn && k > 16)) ? 1 : tu.tile_policy;
+    pp.tile_policy = (!tile_fits || (do_knn && k > 16)) ? 1 : tu.tile_policy;
     pp.r_enum = do_rdf ? rb->r_max : 0.0f;
     {
         TraceSpan span("binning", st);
@@ -480,7 +486,7 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
         pa.r_enum = (float)(rmax * (1.0 + 4e-5));
         pa.E2 = w.E2;
         pa.hist = rdf_hist;
-        in_lds = (size_t)kWavesPerBlock * n_bins * 4u <= 48u * 1024u;
+        in_lds = rdf_lds;
         pa.hist_in_lds = in_lds ? 1 : 0;
     }
     if (do_knn) {
@@ -554,7 +560,7 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
     if (k > APT_MAX_K) return fail(APT_E_UNSUPPORTED, "k must be in [1, 256]");
     if (knn_hist && (s = check_bins(kb, "knn_bins")) != APT_OK) return s;
     if (!status) return fail(APT_E_ARG, "status is NULL");
-    if ((size_t)kWavesPerBlock * rb.n_bins * 4u > 48u * 1024u)
+    if (batched_lds_bytes(rb.n_bins) > kMaxLds)
         return fail(APT_E_UNSUPPORTED, "batched RDF supports at most 3072 bins");
     // species -> class; every species of the pairs gets one class
     uint8_t slot[256];

@@ -17,7 +17,7 @@
 namespace apt {
 
 size_t batched_lds_bytes(int n_bins) {
-    size_t b = (size_t)kWavesPerBlock * (size_t)n_bins * 4u;
+    size_t b = (size_t)kWavesPerBlock * (size_t)hist_stride(n_bins) * 4u;
     b = (b + 15) & ~size_t(15);
     return b + (size_t)kWavesPerBlock * kKnnCap * 8u;
 }
@@ -186,11 +186,11 @@ __global__ __launch_bounds__(kBlock) void k_pair_batched(BatchPairArgs a) {
     T.hi_b = 1.0f - a.delta_b;
     T.inv_w64 = a.inv_w64;
     T.E2 = a.E2;
-    T.hist_l = reinterpret_cast<uint32_t*>(smem) + (size_t)w * a.n_bins;
+    T.hist_l = reinterpret_cast<uint32_t*>(smem) + (size_t)w * hist_stride(a.n_bins);
     T.k = a.k;
     T.rknn = INFINITY;
     T.rknn2 = INFINITY;
-    size_t off = ((size_t)kWavesPerBlock * a.n_bins * 4u + 15) & ~size_t(15);
+    size_t off = ((size_t)kWavesPerBlock * hist_stride(a.n_bins) * 4u + 15) & ~size_t(15);
     T.kbuf = reinterpret_cast<uint64_t*>(smem + off) + (size_t)w * kKnnCap;
     for (int b = l; b < a.n_bins; b += kWave) T.hist_l[b] = 0;
     wave_sync();

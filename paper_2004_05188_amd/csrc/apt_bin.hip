@@ -195,6 +195,24 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
     uint32_t passes = 1;
     while (passes < 4 && ((P.n_cells - 1u) >> (8u * passes)) != 0u) ++passes;
     P.passes = passes;
+    // targets in block-raster order when its keys fit 32 bits
+    {
+        const uint64_t nbx = ((uint64_t)P.dim[0] + 7) / 8, nby = ((uint64_t)P.dim[1] + 7) / 8,
+                       nbz = ((uint64_t)P.dim[2] + 7) / 8;
+        const uint64_t kmax = nbx * nby * nbz * 512u - 1u;
+        if (kmax <= 0xFFFFFFFFull) {
+            P.tblock = 8;
+            P.nbx = (int32_t)nbx;
+            P.nby = (int32_t)nby;
+            uint32_t pt = 1;
+            while (pt < 4 && (kmax >> (8u * pt)) != 0u) ++pt;
+            P.passes_T = pt;
+        } else {
+            P.tblock = 1;
+            P.nbx = P.nby = 0;
+            P.passes_T = passes;
+        }
+    }
     // (x - lo) * inv_h in FP32 misplaces a point by at most ~3 ulps of the
     // extent; cull with a margin well above that
     P.eps = (float)fmin(fmax(1e-5, 8.0 * 5.9604645e-8 * (emax + amax)), 3.0e38);
@@ -298,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(KeyArgs a) {
         const uint32_t id = a.src ? a.src[j] : j;
         float x = a.xyz[3 * (size_t)id], y = a.xyz[3 * (size_t)id + 1], z = a.xyz[3 * (size_t)id + 2];
         if (a.zscale) z = (float)((double)z * sd);
-        a.keys[j] = cell_id(P, x, y, z);
+        a.keys[j] = a.count_is_T ? target_key(P, x, y, z) : cell_id(P, x, y, z);
         a.vals[j] = a.val_is_index ? j : id;
     }
 }
@@ -313,7 +331,9 @@ constexpr int kRsItems = 8;
 constexpr int kRsTile = kBlock * kRsItems;   // 2048
 constexpr int kRadix = 256;
 
-__device__ __forceinline__ bool rs_active(const GridPlan& P, int pass) { return (uint32_t)pass < P.passes; }
+__device__ __forceinline__ bool rs_active(const GridPlan& P, const SortArgs& a) {
+    return (uint32_t)a.pass < (a.count_is_T ? P.passes_T : P.passes);
+}
 
 __device__ __forceinline__ void rs_chunk(uint32_t n, int G, uint32_t* chunk) {
     uint32_t c = (n + (uint32_t)G - 1u) / (uint32_t)G;
@@ -322,7 +342,7 @@ __device__ __forceinline__ void rs_chunk(uint32_t n, int G, uint32_t* chunk) {
 
 __global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortArgs a) {
     const GridPlan P = *a.plan;
-    if (!rs_active(P, a.pass)) return;
+    if (!rs_active(P, a)) return;
     const uint32_t n = a.count_is_T ? P.nT : P.nB;
     const uint32_t* __restrict__ keys = a.keys[a.pass & 1];
     __shared__ uint32_t s_h[kWavesPerBlock][kRadix];
@@ -350,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortArgs a) {
 // The downsweep adds the digit bases (a scan of the 256 totals).
 __global__ __launch_bounds__(kBlock) void k_rs_scan(SortArgs a) {
     const GridPlan P = *a.plan;
-    if (!rs_active(P, a.pass)) return;
+    if (!rs_active(P, a)) return;
     __shared__ uint32_t s_w[kWavesPerBlock];
     const int d = blockIdx.x, t = threadIdx.x, w = t / kWave, l = lane_id();
     const int G = a.G;
@@ -379,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scan(SortArgs a) {
 
 __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortArgs a) {
     const GridPlan P = *a.plan;
-    if (!rs_active(P, a.pass)) return;
+    if (!rs_active(P, a)) return;
     const uint32_t n = a.count_is_T ? P.nT : P.nB;
     const uint32_t* __restrict__ kin = a.keys[a.pass & 1];
     const uint32_t* __restrict__ vin = a.vals[a.pass & 1];
@@ -492,7 +512,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortArgs a) {
 // ------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_take_order(OrderArgs a) {
     const GridPlan P = *a.plan;
-    const uint32_t* __restrict__ v = a.vals[P.passes & 1];
+    const uint32_t* __restrict__ v = a.vals[P.passes_T & 1];
     for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < P.nT; t += gridDim.x * kBlock) {
         const uint32_t rank = v[t];
         const uint32_t id = a.tid[rank];

@@ -26,7 +26,10 @@ struct GridPlan {
     uint32_t n_cells;
     uint32_t nT;        // eligible targets
     uint32_t nB;        // neighbour ions
-    uint32_t passes;    // active radix passes over the cell ids
+    uint32_t passes;    // active radix passes over the cell ids (neighbours)
+    uint32_t passes_T;  // active radix passes over the target keys
+    int32_t tblock;     // targets are ordered by blocks of tblock^3 cells (8), or by cell (1)
+    int32_t nbx, nby;   // blocks per axis (x, y)
     float eps;          // culling margin covering FP32 cell-assignment error (nm)
     float r_all;        // a radius that reaches every cell from any point of the box
     float rk0;          // first kNN search radius
@@ -78,6 +81,9 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
     return v;
 }
 
+// Counters of one wavefront's LDS RDF histogram.
+__host__ __device__ constexpr int hist_stride(int n_bins) { return n_bins; }
+
 // ------------------------------------------------------------- cells --
 __device__ __forceinline__ int cell_axis(const GridPlan& P, int a, float x) {
     float f = (x - P.lo[a]) * P.inv_h;
@@ -89,6 +95,18 @@ __device__ __forceinline__ int cell_axis(const GridPlan& P, int a, float x) {
 __device__ __forceinline__ uint32_t cell_id(const GridPlan& P, float x, float y, float z) {
     return ((uint32_t)cell_axis(P, 2, z) * (uint32_t)P.dim[1] + (uint32_t)cell_axis(P, 1, y)) *
                (uint32_t)P.dim[0] + (uint32_t)cell_axis(P, 0, x);
+}
+
+// Sort key of a target: its cell in block-raster order (blocks of 8^3 cells
+// in raster order, cells in raster order inside a block), so that any run
+// of consecutive targets is a compact region of space; plain cell order
+// when the plan chose tblock = 1.
+__device__ __forceinline__ uint32_t target_key(const GridPlan& P, float x, float y, float z) {
+    const uint32_t cx = (uint32_t)cell_axis(P, 0, x), cy = (uint32_t)cell_axis(P, 1, y),
+                   cz = (uint32_t)cell_axis(P, 2, z);
+    if (P.tblock == 1) return (cz * (uint32_t)P.dim[1] + cy) * (uint32_t)P.dim[0] + cx;
+    const uint32_t blk = ((cz >> 3) * (uint32_t)P.nby + (cy >> 3)) * (uint32_t)P.nbx + (cx >> 3);
+    return (blk << 9) | ((cz & 7u) << 6) | ((cy & 7u) << 3) | (cx & 7u);
 }
 
 // ------------------------------------------------------- exact binning --

@@ -26,7 +26,7 @@ namespace apt {
 
 size_t pair_lds_bytes(bool rdf, bool knn, int n_bins, bool hist_in_lds) {
     size_t b = 0;
-    if (rdf && hist_in_lds) b += (size_t)kWavesPerBlock * (size_t)n_bins * 4u;
+    if (rdf && hist_in_lds) b += (size_t)kWavesPerBlock * (size_t)hist_stride(n_bins) * 4u;
     b = (b + 15) & ~size_t(15);
     if (knn) b += (size_t)kWavesPerBlock * kKnnCap * 8u;
     return b;
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
     T.hi_b = 1.0f - a.delta_b;
     T.inv_w64 = a.inv_w64;
     T.E2 = a.E2;
-    T.hist_l = reinterpret_cast<uint32_t*>(smem) + (size_t)w * a.n_bins;
+    T.hist_l = reinterpret_cast<uint32_t*>(smem) + (size_t)w * hist_stride(a.n_bins);
     T.hist_g = a.hist;
     T.k = a.k;
     T.rk0 = P.rk0;
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
     if (LDS_HIST)
         for (int b = l; b < a.n_bins; b += kWave) T.hist_l[b] = 0;
     if (KNN) {
-        size_t off = LDS_HIST ? (size_t)kWavesPerBlock * a.n_bins * 4u : 0;
+        size_t off = LDS_HIST ? (size_t)kWavesPerBlock * hist_stride(a.n_bins) * 4u : 0;
         off = (off + 15) & ~size_t(15);
         T.kbuf = reinterpret_cast<uint64_t*>(smem + off) + (size_t)w * kKnnCap;
     }
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
 }
 
 size_t tile_lds_bytes(bool rdf, int n_bins) {
-    size_t b = rdf ? (size_t)kWavesPerBlock * (size_t)n_bins * 4u : 0;
+    size_t b = rdf ? (size_t)kWavesPerBlock * (size_t)hist_stride(n_bins) * 4u : 0;
     b = (b + 15) & ~size_t(15);
     return b + (size_t)kWavesPerBlock * kStage * sizeof(float4);
 }
@@ -171,11 +171,11 @@ __global__ __launch_bounds__(kBlock) void k_pair_tile(PairArgs a) {
     T.hi_b = 1.0f - a.delta_b;
     T.inv_w64 = a.inv_w64;
     T.E2 = a.E2;
-    T.hist_l = reinterpret_cast<uint32_t*>(smem) + (size_t)w * a.n_bins;
+    T.hist_l = reinterpret_cast<uint32_t*>(smem) + (size_t)w * hist_stride(a.n_bins);
     T.hist_g = a.hist;
     T.k = a.k;
     T.kbuf = nullptr;
-    size_t off = LDS_HIST ? (size_t)kWavesPerBlock * a.n_bins * 4u : 0;
+    size_t off = LDS_HIST ? (size_t)kWavesPerBlock * hist_stride(a.n_bins) * 4u : 0;
     off = (off + 15) & ~size_t(15);
     float4* stage = reinterpret_cast<float4*>(smem + off) + (size_t)w * kStage;
     if (LDS_HIST)
