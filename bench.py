@@ -103,7 +103,7 @@ def batched_vs_looped(aptstat, torch, cloud, ws, n_rep, n_loop):
                         kb_nbins=KB_NBINS, ws=ws)
     torch.cuda.synchronize()
     log(f"[bench] batched: {n_rep} replicates x {len(pairs)} pairs")
-    for stage in ("pair", "binning", "permute", "partition"):
+    for stage in ("pair", "tile", "binning", "permute", "partition"):
         aptstat.trace_read(stage)
     aptstat.trace_enable(True)
     t0 = time.perf_counter()
@@ -112,7 +112,7 @@ def batched_vs_looped(aptstat, torch, cloud, ws, n_rep, n_loop):
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
     aptstat.trace_enable(False)
-    stages = {s_: aptstat.trace_read(s_)[0] for s_ in ("pair", "binning", "permute", "partition")}
+    stages = {s_: aptstat.trace_read(s_)[0] for s_ in ("pair", "tile", "binning", "permute", "partition")}
     # looped: the definition of the batched result, call by call
     lab_r = torch.empty_like(cloud.lab)
     outs = (torch.empty(1, dtype=torch.int64, device=dev), torch.empty((1, K), dtype=torch.float32, device=dev),

@@ -260,6 +260,7 @@ struct BatchWs {
     uint32_t* Pcell;
     uint32_t* CS;
     uint64_t* items;
+    uint64_t* titems;
     uint64_t* work;
     size_t bytes;
 };
@@ -278,6 +279,7 @@ static BatchWs carve_batched(void* base, int64_t n, int R) {
     w.Pcell = c.take<uint32_t>(N * R);
     w.CS = c.take<uint32_t>((size_t)R * (kMaxClasses - 1) * ((size_t)cell_cap_for(n) + 1));
     w.items = c.take<uint64_t>((size_t)R * kMaxPairs + 1);
+    w.titems = c.take<uint64_t>((size_t)R * kMaxPairs + 1);
     w.work = c.take<uint64_t>(8);
     w.bytes = w.plain.bytes + w.perm.bytes + c.off;
     return w;
@@ -634,7 +636,6 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
             TraceSpan span("permute", st);
             run_permute(cl->lab, n, seeds + r0, nr, w.LR, n, w.perm, status, st);
         }
-        TraceSpan span("partition", st);
         PartArgs pa{};
         pa.plan = w.plain.plan;
         pa.S = w.plain.bpos;
@@ -653,11 +654,14 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
         pa.Pcell = w.Pcell;
         pa.CS = w.CS;
         pa.cs_stride = (int64_t)cell_cap_for(n) + 1;
-        hipLaunchKernelGGL(k_bpart_count, dim3(Gp, nr), dim3(kBlock), 0, st, pa);
-        device_excl_scan(w.cnt, (int64_t)nr * Cn * Gp, w.perm.part, st);
-        hipLaunchKernelGGL(k_bpart_scatter, dim3(Gp, nr), dim3(kBlock), 0, st, pa);
-        hipLaunchKernelGGL(k_bpart_cells, dim3(cus * 4, nr), dim3(kBlock), 0, st, pa);
-        hipLaunchKernelGGL(k_bpart_empty, dim3(64, nr * (Cn - 1)), dim3(kBlock), 0, st, pa);
+        {
+            TraceSpan span("partition", st);
+            hipLaunchKernelGGL(k_bpart_count, dim3(Gp, nr), dim3(kBlock), 0, st, pa);
+            device_excl_scan(w.cnt, (int64_t)nr * Cn * Gp, w.perm.part, st);
+            hipLaunchKernelGGL(k_bpart_scatter, dim3(Gp, nr), dim3(kBlock), 0, st, pa);
+            hipLaunchKernelGGL(k_bpart_cells, dim3(cus * 4, nr), dim3(kBlock), 0, st, pa);
+            hipLaunchKernelGGL(k_bpart_empty, dim3(64, nr * (Cn - 1)), dim3(kBlock), 0, st, pa);
+        }
 
         BatchPairArgs ba{};
         ba.plan = w.plain.plan;
@@ -679,7 +683,9 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
             ba.pairs[p].d_srf = pairs[p].d_srf;
         }
         ba.items = w.items;
+        ba.titems = w.titems;
         ba.work = w.work;
+        ba.tile_ok = (k <= 16 && batched_tile_lds_bytes(rb.n_bins) <= kMaxLds) ? 1 : 0;
         ba.n_bins = rb.n_bins;
         ba.r_enum = (float)((double)rb.r_max * (1.0 + 4e-5));
         ba.thr2 = (float)(((double)rb.r_max * (1.0 + 2e-5)) * ((double)rb.r_max * (1.0 + 2e-5)));
@@ -694,8 +700,20 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
         ba.KE2 = w.plain.KE2;
         ba.knn_hist = knn_hist;
         hipLaunchKernelGGL(k_batch_items, dim3(1), dim3(64), 0, st, ba);
-        TraceSpan span2("pair", st);
-        hipLaunchKernelGGL(k_pair_batched, dim3(cus * 8), dim3(kBlock), lds, st, ba);
+        {
+            TraceSpan span2("pair", st);
+            hipLaunchKernelGGL(k_pair_batched, dim3(cus * 8), dim3(kBlock), lds, st, ba);
+        }
+        if (ba.tile_ok) {
+            TraceSpan span3("tile", st);
+            const size_t tl = batched_tile_lds_bytes(rb.n_bins);
+            auto go = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3(resident_grid(kern, tl)), dim3(kBlock), tl, st, ba);
+            };
+            if (k <= 4) go(k_pair_batched_tile<4>);
+            else if (k <= 10) go(k_pair_batched_tile<10>);
+            else go(k_pair_batched_tile<16>);
+        }
     }
     return hip_check("batched launch");
 }

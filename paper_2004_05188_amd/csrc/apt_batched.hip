@@ -22,6 +22,14 @@ size_t batched_lds_bytes(int n_bins) {
     return b + (size_t)kWavesPerBlock * kKnnCap * 8u;
 }
 
+// tiles: histogram + staging buffer (which later holds a straggler's kNN keys)
+size_t batched_tile_lds_bytes(int n_bins) {
+    static_assert(kStage * sizeof(float4) >= kKnnCap * sizeof(uint64_t), "key buffer inside the stage");
+    size_t b = (size_t)kWavesPerBlock * (size_t)hist_stride(n_bins) * 4u;
+    b = (b + 15) & ~size_t(15);
+    return b + (size_t)kWavesPerBlock * kStage * sizeof(float4);
+}
+
 __device__ __forceinline__ int class_of(const PartArgs& a, int r, uint32_t id) {
     return a.slot[a.LR[(size_t)r * (size_t)a.n + id]];
 }
@@ -155,18 +163,52 @@ __global__ __launch_bounds__(kBlock) void k_bpart_empty(PartArgs a) {
         cs[cc] = (uint32_t)s0;
 }
 
-// ---- 4. prefix of the target-segment sizes over (replicate, pair)
+// first kNN radius of a pair: 1.15 x the Poisson mean k-th distance at the
+// neighbour class's density over the bounding box
+__device__ inline float batch_rk0(const GridPlan& P, uint64_t nb, int k) {
+    double vol = 1.0;
+    for (int ax = 0; ax < 3; ++ax) vol *= fmax((double)P.hi[ax] - (double)P.lo[ax], 1e-3);
+    const double rho = (double)(nb > 0 ? nb : 1) / vol;
+    return (float)fmin(1.15 * cbrt(3.0 * ((double)k + 0.5) / (4.0 * M_PI * rho)), (double)P.r_all);
+}
+
+// Is pair p tiled (64 targets per wavefront)?  As in the plain path: targets
+// at least as many as neighbours and dense enough that 64 of them fill no
+// more than the cube of the search reach.  Class sizes are the same in
+// every replicate (a permutation keeps them), so the choice is per pair.
+__device__ inline bool batch_tiled(const BatchPairArgs& a, const GridPlan& P, int p) {
+    if (!a.tile_ok) return false;
+    const uint64_t na = seg_end(a.cnt, 0, a.C, a.G, a.pairs[p].a, a.n) - seg_start(a.cnt, 0, a.C, a.G, a.pairs[p].a);
+    const uint64_t nb = seg_end(a.cnt, 0, a.C, a.G, a.pairs[p].b, a.n) - seg_start(a.cnt, 0, a.C, a.G, a.pairs[p].b);
+    if (na < nb || na < 4096) return false;
+    double vol = 1.0;
+    for (int ax = 0; ax < 3; ++ax) vol *= fmax((double)P.hi[ax] - (double)P.lo[ax], 1e-3);
+    const double rk_tile = 1.6 / 1.15 * (double)batch_rk0(P, nb, a.k);
+    const double R = fmax((double)a.r_enum, rk_tile);
+    return 64.0 * vol / (double)na <= R * R * R;
+}
+
+// ---- 4. prefixes of the work over (replicate, pair): targets of the pairs
+//         run one per wavefront, tiles of the tiled pairs
 __global__ void k_batch_items(BatchPairArgs a) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    uint64_t acc = 0;
+    const GridPlan P = *a.plan;
+    bool tiled[kMaxPairs];
+    for (int p = 0; p < a.n_pairs; ++p) tiled[p] = batch_tiled(a, P, p);
+    uint64_t acc = 0, tacc = 0;
     for (int r = 0; r < a.R; ++r)
         for (int p = 0; p < a.n_pairs; ++p) {
             a.items[r * a.n_pairs + p] = acc;
+            a.titems[r * a.n_pairs + p] = tacc;
             const int q = a.pairs[p].a;
-            acc += seg_end(a.cnt, r, a.C, a.G, q, a.n) - seg_start(a.cnt, r, a.C, a.G, q);
+            const uint64_t len = seg_end(a.cnt, r, a.C, a.G, q, a.n) - seg_start(a.cnt, r, a.C, a.G, q);
+            if (tiled[p]) tacc += (len + kWave - 1) / kWave;
+            else acc += len;
         }
     a.items[a.R * a.n_pairs] = acc;
-    *a.work = 0;
+    a.titems[a.R * a.n_pairs] = tacc;
+    a.work[0] = 0;
+    a.work[1] = 0;
 }
 
 // ---- 5. the pair launch over (replicate, pair, target)
@@ -239,12 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_batched(BatchPairArgs a) {
                 const uint64_t b1 = seg_end(a.cnt, r, a.C, a.G, bp.b, a.n);
                 T.bpos = a.Pp;
                 T.cell_start = a.CS + ((size_t)r * (a.C - 1) + bp.b) * (size_t)a.cs_stride;
-                // first kNN radius: 1.15 x the Poisson mean k-th distance at the
-                // neighbour density of the bounding box
-                double vol = 1.0;
-                for (int ax = 0; ax < 3; ++ax) vol *= fmax((double)P.hi[ax] - (double)P.lo[ax], 1e-3);
-                const double rho = (double)(b1 - b0 > 0 ? b1 - b0 : 1) / vol;
-                T.rk0 = (float)fmin(1.15 * cbrt(3.0 * ((double)a.k + 0.5) / (4.0 * M_PI * rho)), (double)P.r_all);
+                T.rk0 = batch_rk0(P, b1 - b0, a.k);
                 T.hist_g = a.rdf_hist + ((size_t)(a.rep0 + r) * a.n_pairs + p) * a.n_bins;
                 d_srf = bp.d_srf;
             }
@@ -273,5 +310,142 @@ __global__ __launch_bounds__(kBlock) void k_pair_batched(BatchPairArgs a) {
     }
     if (cur >= 0) flush_hist(T.hist_l, T.hist_g, a.n_bins);
 }
+
+// ---- 6. the tiled pairs: 64 consecutive targets of a class segment per
+//         wavefront (RDF and kNN from LDS-staged neighbours); a target whose
+//         k-th neighbour lies beyond the tile's certified radius is finished
+//         by the one-target-per-wavefront search right away (kNN only)
+template <int KMAX>
+__global__ __launch_bounds__(kBlock) void k_pair_batched_tile(BatchPairArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const GridPlan P = *a.plan;
+    const int RP = a.R * a.n_pairs;
+    const uint64_t total = a.titems[RP];
+    if (total == 0) return;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int l = lane_id();
+    PairTask T;
+    T.n_bins = a.n_bins;
+    T.r_enum = a.r_enum;
+    T.thr2 = a.thr2;
+    T.inv_w = a.inv_w;
+    T.lo_b = a.delta_b;
+    T.hi_b = 1.0f - a.delta_b;
+    T.inv_w64 = a.inv_w64;
+    T.E2 = a.E2;
+    T.hist_l = reinterpret_cast<uint32_t*>(smem) + (size_t)w * hist_stride(a.n_bins);
+    T.k = a.k;
+    T.rknn = INFINITY;
+    T.rknn2 = INFINITY;
+    size_t off = ((size_t)kWavesPerBlock * hist_stride(a.n_bins) * 4u + 15) & ~size_t(15);
+    float4* stage = reinterpret_cast<float4*>(smem + off) + (size_t)w * kStage;
+    T.kbuf = reinterpret_cast<uint64_t*>(stage);      // used only after the tile pass
+    for (int b = l; b < a.n_bins; b += kWave) T.hist_l[b] = 0;
+    wave_sync();
+
+    int cur = -1;
+    uint32_t since_flush = 0;
+    uint64_t seg_a0 = 0, seg_len = 0;
+    float d_srf = 0.0f, Rk = 0.0f;
+    int rp = 0;
+    for (;;) {
+        uint64_t g = 0;
+        if (l == 0) g = atomicAdd((unsigned long long*)&a.work[1], 1ull);
+        {
+            const uint64_t b = __shfl((unsigned long long)g, 0, kWave);
+            g = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32)) << 32) |
+                (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+        }
+        if (g >= total) break;
+        {
+            int lo = 0, hi = RP;      // titems[lo] <= g < titems[hi]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (a.titems[mid] <= g) lo = mid; else hi = mid;
+            }
+            rp = lo;
+        }
+        const int r = rp / a.n_pairs, p = rp % a.n_pairs;
+        const BatchPair bp = a.pairs[p];
+        if (rp != cur) {
+            if (cur >= 0) {
+                flush_hist(T.hist_l, T.hist_g, a.n_bins);
+                since_flush = 0;
+            }
+            cur = rp;
+            seg_a0 = seg_start(a.cnt, r, a.C, a.G, bp.a);
+            seg_len = seg_end(a.cnt, r, a.C, a.G, bp.a, a.n) - seg_a0;
+            const uint64_t b0 = seg_start(a.cnt, r, a.C, a.G, bp.b);
+            const uint64_t b1 = seg_end(a.cnt, r, a.C, a.G, bp.b, a.n);
+            T.bpos = a.Pp;
+            T.cell_start = a.CS + ((size_t)r * (a.C - 1) + bp.b) * (size_t)a.cs_stride;
+            T.rk0 = batch_rk0(P, b1 - b0, a.k);
+            Rk = fminf(1.6f / 1.15f * T.rk0, P.r_all);
+            T.hist_g = a.rdf_hist + ((size_t)(a.rep0 + r) * a.n_pairs + p) * a.n_bins;
+            d_srf = bp.d_srf;
+        }
+        const uint64_t slot = (g - a.titems[rp]) * kWave + (uint64_t)l;
+        bool valid = slot < seg_len;
+        uint32_t i = 0;
+        float px = 0.0f, py = 0.0f, pz = 0.0f;
+        if (valid) {
+            const float4 rec = a.Pp[seg_a0 + slot];
+            i = __builtin_bit_cast(uint32_t, rec.w);
+            px = rec.x;
+            py = rec.y;
+            pz = rec.z;
+            valid = a.d_bnd == nullptr || a.d_bnd[i] >= d_srf;
+        }
+        uint32_t hits = 0;
+        TopK<KMAX> top;
+        run_tile<kRdfLds | kSelf, KMAX>(P, T, valid, px, py, pz, i, Rk, stage, top, hits);
+        uint64_t kth = top.key[0];
+#pragma unroll
+        for (int q = 1; q < KMAX; ++q)
+            if (q == a.k - 1) kth = top.key[q];
+        const bool fin = isfinite(px) && isfinite(py) && isfinite(pz);
+        const bool certified = valid && (kth != ~0ull || !fin);
+        uint64_t* kh = a.knn_hist ? a.knn_hist + ((size_t)(a.rep0 + r) * a.n_pairs + p) * (size_t)(a.kb_nbins + 1)
+                                  : nullptr;
+        if (kh && certified) {
+            int b = a.kb_nbins;
+            if (kth != ~0ull) {
+                const uint32_t j = (uint32_t)kth;
+                b = exact_bin(exact_D2(px, py, pz, a.xyz[3 * (size_t)j], a.xyz[3 * (size_t)j + 1],
+                                       a.xyz[3 * (size_t)j + 2]),
+                              a.KE2, a.kb_nbins, a.kb_inv_w64);
+            }
+            atomicAdd((unsigned long long*)&kh[b], 1ull);
+        }
+        // the rest: one target at a time over the whole wavefront
+        uint64_t rest = __ballot(valid && !certified);
+        while (rest) {
+            const int ln = __builtin_ctzll(rest);
+            rest &= rest - 1;
+            const uint32_t ti = (uint32_t)__builtin_amdgcn_readlane((int)i, ln);
+            const float tx = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, px), ln));
+            const float ty = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, py), ln));
+            const float tz = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, pz), ln));
+            uint32_t h2 = 0;
+            wave_sync();
+            const int found = run_target<kSelf, true>(P, T, tx, ty, tz, ti, h2, false);
+            if (kh && l == 0) {
+                const int b = kth_bin(found, a.k, T.kbuf, a.xyz, tx, ty, tz, a.KE2, a.kb_nbins, a.kb_inv_w64);
+                atomicAdd((unsigned long long*)&kh[b], 1ull);
+            }
+            wave_sync();
+        }
+        since_flush += wave_sum(hits);
+        if (since_flush >= 0x7FFFFFFFu - (uint32_t)min((uint64_t)a.n * kWave, (uint64_t)0x7FFFFFFFu)) {
+            flush_hist(T.hist_l, T.hist_g, a.n_bins);
+            since_flush = 0;
+        }
+    }
+    if (cur >= 0) flush_hist(T.hist_l, T.hist_g, a.n_bins);
+}
+
+template __global__ void k_pair_batched_tile<4>(BatchPairArgs);
+template __global__ void k_pair_batched_tile<10>(BatchPairArgs);
+template __global__ void k_pair_batched_tile<16>(BatchPairArgs);
 
 }  // namespace apt

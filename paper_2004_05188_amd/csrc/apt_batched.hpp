@@ -48,8 +48,10 @@ struct BatchPairArgs {
     int64_t n;
     int32_t rep0;             // replicate index of the first replicate of this launch
     BatchPair pairs[kMaxPairs];
-    uint64_t* items;          // [R * n_pairs + 1] prefix of target-segment sizes
-    uint64_t* work;           // work counter (zeroed before the launch)
+    uint64_t* items;          // [R * n_pairs + 1] prefix of target counts (one-per-wavefront pairs)
+    uint64_t* titems;         // [R * n_pairs + 1] prefix of 64-target tiles (tiled pairs)
+    uint64_t* work;           // [2] work counters: targets, tiles (zeroed by k_batch_items)
+    int32_t tile_ok;          // tiles allowed (k <= 16, LDS fits)
     // RDF
     int32_t n_bins;
     float r_enum, thr2, inv_w, delta_b;
@@ -70,6 +72,9 @@ __global__ void k_bpart_cells(PartArgs a);
 __global__ void k_bpart_empty(PartArgs a);
 __global__ void k_batch_items(BatchPairArgs a);
 __global__ void k_pair_batched(BatchPairArgs a);
+template <int KMAX>
+__global__ void k_pair_batched_tile(BatchPairArgs a);
 size_t batched_lds_bytes(int n_bins);
+size_t batched_tile_lds_bytes(int n_bins);
 
 }  // namespace apt
