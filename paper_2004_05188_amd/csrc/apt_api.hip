@@ -624,6 +624,13 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
         hipLaunchKernelGGL(k_gather, dim3(Gk), dim3(kBlock), 0, st, ga);
     }
 
+    {
+        // occupied cells of the all-ion grid (work[4] holds the count)
+        InitArgs oa{nullptr, nullptr, 0, nullptr, 0, nullptr, reinterpret_cast<uint32_t*>(w.work + 4)};
+        hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, oa);
+        hipLaunchKernelGGL(k_occupied, dim3(cus * 4), dim3(kBlock), 0, st, w.plain.plan, w.plain.cell_start,
+                           reinterpret_cast<uint32_t*>(w.work + 4));
+    }
     const int Gp = part_blocks(n);
     const int64_t pchunk = ((n + Gp - 1) / Gp + kPartTile - 1) / kPartTile * kPartTile;
     const size_t lds = batched_lds_bytes(rb.n_bins);
@@ -686,6 +693,7 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
         ba.titems = w.titems;
         ba.work = w.work;
         ba.tile_ok = (k <= 16 && batched_tile_lds_bytes(rb.n_bins) <= kMaxLds) ? 1 : 0;
+        ba.occ = reinterpret_cast<const uint32_t*>(w.work + 4);
         ba.n_bins = rb.n_bins;
         ba.r_enum = (float)((double)rb.r_max * (1.0 + 4e-5));
         ba.thr2 = (float)(((double)rb.r_max * (1.0 + 2e-5)) * ((double)rb.r_max * (1.0 + 2e-5)));

@@ -163,11 +163,31 @@ __global__ __launch_bounds__(kBlock) void k_bpart_empty(PartArgs a) {
         cs[cc] = (uint32_t)s0;
 }
 
+// Cells that hold at least one ion (all ions are binned here), counted once
+// per call: their volume is the specimen's, unlike the bounding box's (a
+// needle fills less than half of its box).  *occ must be zero on entry.
+__global__ __launch_bounds__(kBlock) void k_occupied(const GridPlan* plan, const uint32_t* cell_start,
+                                                     uint32_t* occ) {
+    const uint32_t nc = plan->n_cells;
+    uint32_t c = 0;
+    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < nc; q += gridDim.x * kBlock)
+        c += cell_start[q + 1] > cell_start[q];
+    c = wave_sum(c);
+    if (lane_id() == 0 && c) atomicAdd(occ, c);
+}
+
+// volume the ions occupy: the occupied cells (never more than the box)
+__device__ inline double batch_volume(const BatchPairArgs& a, const GridPlan& P) {
+    double box = 1.0;
+    for (int ax = 0; ax < 3; ++ax) box *= fmax((double)P.hi[ax] - (double)P.lo[ax], 1e-3);
+    const double h = (double)P.h;
+    const double v = (double)(*a.occ) * h * h * h;
+    return v > 0.0 && v < box ? v : box;
+}
+
 // first kNN radius of a pair: 1.15 x the Poisson mean k-th distance at the
-// neighbour class's density over the bounding box
-__device__ inline float batch_rk0(const GridPlan& P, uint64_t nb, int k) {
-    double vol = 1.0;
-    for (int ax = 0; ax < 3; ++ax) vol *= fmax((double)P.hi[ax] - (double)P.lo[ax], 1e-3);
+// neighbour class's density over the occupied volume
+__device__ inline float batch_rk0(const GridPlan& P, double vol, uint64_t nb, int k) {
     const double rho = (double)(nb > 0 ? nb : 1) / vol;
     return (float)fmin(1.15 * cbrt(3.0 * ((double)k + 0.5) / (4.0 * M_PI * rho)), (double)P.r_all);
 }
@@ -181,9 +201,8 @@ __device__ inline bool batch_tiled(const BatchPairArgs& a, const GridPlan& P, in
     const uint64_t na = seg_end(a.cnt, 0, a.C, a.G, a.pairs[p].a, a.n) - seg_start(a.cnt, 0, a.C, a.G, a.pairs[p].a);
     const uint64_t nb = seg_end(a.cnt, 0, a.C, a.G, a.pairs[p].b, a.n) - seg_start(a.cnt, 0, a.C, a.G, a.pairs[p].b);
     if (na < nb || na < 4096) return false;
-    double vol = 1.0;
-    for (int ax = 0; ax < 3; ++ax) vol *= fmax((double)P.hi[ax] - (double)P.lo[ax], 1e-3);
-    const double rk_tile = 1.6 / 1.15 * (double)batch_rk0(P, nb, a.k);
+    const double vol = batch_volume(a, P);
+    const double rk_tile = 1.6 / 1.15 * (double)batch_rk0(P, vol, nb, a.k);
     const double R = fmax((double)a.r_enum, rk_tile);
     return 64.0 * vol / (double)na <= R * R * R;
 }
@@ -239,6 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_batched(BatchPairArgs a) {
 
     const int RP = a.R * a.n_pairs;
     const uint64_t total = a.items[RP];
+    const double vol = batch_volume(a, P);
     int cur = -1;                     // (replicate, pair) of the LDS histogram contents
     uint32_t since_flush = 0;
     uint64_t seg_a0 = 0;
@@ -281,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_batched(BatchPairArgs a) {
                 const uint64_t b1 = seg_end(a.cnt, r, a.C, a.G, bp.b, a.n);
                 T.bpos = a.Pp;
                 T.cell_start = a.CS + ((size_t)r * (a.C - 1) + bp.b) * (size_t)a.cs_stride;
-                T.rk0 = batch_rk0(P, b1 - b0, a.k);
+                T.rk0 = batch_rk0(P, vol, b1 - b0, a.k);
                 T.hist_g = a.rdf_hist + ((size_t)(a.rep0 + r) * a.n_pairs + p) * a.n_bins;
                 d_srf = bp.d_srf;
             }
@@ -322,6 +342,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_batched_tile(BatchPairArgs a) {
     const int RP = a.R * a.n_pairs;
     const uint64_t total = a.titems[RP];
     if (total == 0) return;
+    const double vol = batch_volume(a, P);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int l = lane_id();
     PairTask T;
@@ -379,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_batched_tile(BatchPairArgs a) {
             const uint64_t b1 = seg_end(a.cnt, r, a.C, a.G, bp.b, a.n);
             T.bpos = a.Pp;
             T.cell_start = a.CS + ((size_t)r * (a.C - 1) + bp.b) * (size_t)a.cs_stride;
-            T.rk0 = batch_rk0(P, b1 - b0, a.k);
+            T.rk0 = batch_rk0(P, vol, b1 - b0, a.k);
             Rk = fminf(1.6f / 1.15f * T.rk0, P.r_all);
             T.hist_g = a.rdf_hist + ((size_t)(a.rep0 + r) * a.n_pairs + p) * a.n_bins;
             d_srf = bp.d_srf;

@@ -51,6 +51,7 @@ struct BatchPairArgs {
     uint64_t* items;          // [R * n_pairs + 1] prefix of target counts (one-per-wavefront pairs)
     uint64_t* titems;         // [R * n_pairs + 1] prefix of 64-target tiles (tiled pairs)
     uint64_t* work;           // [2] work counters: targets, tiles (zeroed by k_batch_items)
+    const uint32_t* occ;      // [1] cells holding at least one ion (the specimen's volume in cells)
     int32_t tile_ok;          // tiles allowed (k <= 16, LDS fits)
     // RDF
     int32_t n_bins;
@@ -71,6 +72,7 @@ __global__ void k_bpart_scatter(PartArgs a);
 __global__ void k_bpart_cells(PartArgs a);
 __global__ void k_bpart_empty(PartArgs a);
 __global__ void k_batch_items(BatchPairArgs a);
+__global__ void k_occupied(const GridPlan* plan, const uint32_t* cell_start, uint32_t* occ);
 __global__ void k_pair_batched(BatchPairArgs a);
 template <int KMAX>
 __global__ void k_pair_batched_tile(BatchPairArgs a);
