@@ -333,7 +333,8 @@ __global__ void k_init(InitArgs a) {
     if (t == 0) {
         if (a.status) *a.status = 0;
         if (a.n_targets) *a.n_targets = 0;
-        if (a.counter) *a.counter = 0;
+        if (a.counter)
+            for (int c = 0; c < 4; ++c) a.counter[c] = 0;   // [0] stragglers, [1..2] occupied cells
     }
     if (a.h1)
         for (int b = t; b < a.n1; b += st) a.h1[b] = 0;
@@ -397,12 +398,20 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
     sort(1);
     OrderArgs oa{w.plan, cl->xyz, w.tid, {w.V[0], w.V[1]}, w.t_rank, w.t_id, w.tx, w.ty, w.tz};
     hipLaunchKernelGGL(k_take_order, dim3(Gk), dim3(kBlock), 0, st, oa);
+    if (pp.k > 0 && !zscale)   // occupied target cells (the sorted keys are overwritten next)
+        hipLaunchKernelGGL(k_target_cells, dim3(cus * 2), dim3(kBlock), 0, st, w.plan, w.K[0], w.K[1],
+                           w.strag_count + 1);
     // neighbours in cell order
     KeyArgs kb{w.plan, cl->xyz, all_b ? nullptr : w.bsel, zscale, 0, 0, w.K[0], w.V[0]};
     hipLaunchKernelGGL(k_keys, dim3(Gk), dim3(kBlock), 0, st, kb);
     sort(0);
     GatherArgs ga{w.plan, cl->xyz, zscale, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.bpos, w.cell_start};
     hipLaunchKernelGGL(k_gather, dim3(Gk), dim3(kBlock), 0, st, ga);
+    if (pp.k > 0 && !zscale) {
+        hipLaunchKernelGGL(k_neighbour_cells, dim3(cus * 2), dim3(kBlock), 0, st, w.plan, w.cell_start,
+                           w.strag_count + 1);
+        hipLaunchKernelGGL(k_refine_radii, dim3(1), dim3(64), 0, st, w.plan, w.strag_count + 1, pp.k);
+    }
     return hip_check("binning launch");
 }
 

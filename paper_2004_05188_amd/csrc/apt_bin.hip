@@ -553,7 +553,52 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
 }
 
 // ------------------------------------------------------------------------
-// 8. squared bin edges, e_b = b * r_max / n_bins in FP64
+// 8. the kNN radii from the volume the ions occupy.  The plan's first
+//    guesses use the bounding box, which a needle fills less than half;
+//    once the cells are known, the occupied cells of the denser set
+//    (distinct target cells, or non-empty neighbour cells) measure the
+//    specimen's volume.  occ[0] / occ[1] must be zero on entry.
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_target_cells(const GridPlan* plan, const uint32_t* keys0,
+                                                         const uint32_t* keys1, uint32_t* occ) {
+    const GridPlan& P = *plan;
+    const uint32_t* __restrict__ key = (P.passes_T & 1) ? keys1 : keys0;   // sorted target keys
+    uint32_t c = 0;
+    for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < P.nT; t += gridDim.x * kBlock)
+        c += (t == 0 || key[t] != key[t - 1]);
+    c = wave_sum(c);
+    if (lane_id() == 0 && c) atomicAdd(&occ[0], c);
+}
+
+__global__ __launch_bounds__(kBlock) void k_neighbour_cells(const GridPlan* plan, const uint32_t* cell_start,
+                                                            uint32_t* occ) {
+    const uint32_t nc = plan->n_cells;
+    uint32_t c = 0;
+    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < nc; q += gridDim.x * kBlock)
+        c += cell_start[q + 1] > cell_start[q];
+    c = wave_sum(c);
+    if (lane_id() == 0 && c) atomicAdd(&occ[1], c);
+}
+
+__global__ void k_refine_radii(GridPlan* plan, const uint32_t* occ, int32_t k) {
+    if (threadIdx.x != 0 || blockIdx.x != 0 || k <= 0) return;
+    GridPlan& P = *plan;
+    double box = 1.0;
+    for (int ax = 0; ax < 3; ++ax) box *= fmax((double)P.hi[ax] - (double)P.lo[ax], 1e-3);
+    const double h = (double)P.h;
+    double vol = (double)max(occ[0], occ[1]) * h * h * h;
+    if (!(vol > 0.0) || vol > box) vol = box;
+    const double rho = (double)(P.nB > 0 ? P.nB : 1) / vol;
+    const double r = 1.15 * cbrt(3.0 * ((double)k + 0.5) / (4.0 * M_PI * rho));
+    P.rk0 = (float)fmin(r, (double)P.r_all);
+    // tiles: certified within 1.6x the Poisson mean k-th distance (species
+    // that cluster leave the matrix poorer than the mean: a tighter radius
+    // sends too many targets to the one-by-one search)
+    P.rk_tile = (float)fmin(1.6 / 1.15 * (double)P.rk0, (double)P.r_all);
+}
+
+// ------------------------------------------------------------------------
+// 9. squared bin edges, e_b = b * r_max / n_bins in FP64
 // ------------------------------------------------------------------------
 __global__ void k_edges(double* E2, float r_max, int n_bins) {
 #pragma clang fp contract(off)

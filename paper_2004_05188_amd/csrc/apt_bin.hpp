@@ -113,5 +113,8 @@ __global__ void k_rs_downsweep(SortArgs a);
 __global__ void k_take_order(OrderArgs a);
 __global__ void k_gather(GatherArgs a);
 __global__ void k_edges(double* E2, float r_max, int n_bins);
+__global__ void k_target_cells(const GridPlan* plan, const uint32_t* keys0, const uint32_t* keys1, uint32_t* occ);
+__global__ void k_neighbour_cells(const GridPlan* plan, const uint32_t* cell_start, uint32_t* occ);
+__global__ void k_refine_radii(GridPlan* plan, const uint32_t* occ, int32_t k);
 
 }  // namespace apt

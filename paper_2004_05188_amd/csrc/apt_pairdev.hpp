@@ -332,6 +332,127 @@ __device__ __forceinline__ void run_tile(const GridPlan& P, const PairTask& T, b
     (void)l;
 }
 
+// As run_tile, for callers that need only each lane's k-th neighbour key
+// (the k-th distance histogram).  The scan keeps the KMAX smallest FP32
+// squared distances per lane with a min/max network (two instructions a
+// slot, no keys); a second, smaller enumeration (radius: the largest k-th
+// distance of the tile) then finds the k-th neighbour's index: the smallest
+// index among the candidates at exactly that distance when the k-1 nearer
+// ones are strictly nearer.  Returns the k-th key (FP32 d2 bits << 32 |
+// index), or ~0 when it is not settled here: fewer than k neighbours within
+// Rk, or the k-th distance shared by several of the k nearest (the caller
+// finishes those targets exactly).
+template <int FLAGS, int KMAX>
+__device__ __forceinline__ uint64_t run_tile_kth(const GridPlan& P, const PairTask& T, bool valid, float px,
+                                                 float py, float pz, uint32_t i, float Rk, int k, float4* stage,
+                                                 uint32_t& hits) {
+    constexpr bool RDF = (FLAGS & (kRdfLds | kRdfGlobal)) != 0;
+    constexpr bool LDS_HIST = (FLAGS & kRdfLds) != 0;
+    constexpr bool SELF = (FLAGS & kSelf) != 0;
+    static_assert(KMAX > 0, "k-th key needs KMAX > 0");
+    const bool fin = valid && isfinite(px) && isfinite(py) && isfinite(pz);
+    float x0 = fin ? px : INFINITY, y0 = fin ? py : INFINITY, z0 = fin ? pz : INFINITY;
+    float x1 = fin ? px : -INFINITY, y1 = fin ? py : -INFINITY, z1 = fin ? pz : -INFINITY;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        x0 = fminf(x0, __shfl_xor(x0, d, kWave));
+        y0 = fminf(y0, __shfl_xor(y0, d, kWave));
+        z0 = fminf(z0, __shfl_xor(z0, d, kWave));
+        x1 = fmaxf(x1, __shfl_xor(x1, d, kWave));
+        y1 = fmaxf(y1, __shfl_xor(y1, d, kWave));
+        z1 = fmaxf(z1, __shfl_xor(z1, d, kWave));
+    }
+    if (!__any(fin)) return ~0ull;
+    const float rk2 = Rk * Rk;
+    const float R = RDF ? fmaxf(T.r_enum, Rk * 1.000001f) : Rk * 1.000001f;
+    float top[KMAX];
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) top[q] = INFINITY;
+
+    auto scan = [&](int m) {
+        wave_sync();
+        for (int j = 0; j < m; ++j) {
+            const float4 c = stage[j];
+            const float dx = c.x - px, dy = c.y - py, dz = c.z - pz;
+            const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            const uint32_t cj = __builtin_bit_cast(uint32_t, c.w);
+            const bool me = fin && (!SELF || cj != i);
+            if (RDF && me && d2 < T.thr2) {
+                const float t = __builtin_amdgcn_sqrtf(d2) * T.inv_w;
+                int b = (int)t;
+                const float fr = t - (float)b;
+                if (__builtin_expect(fr < T.lo_b || fr > T.hi_b, 0))
+                    b = exact_bin(exact_D2(px, py, pz, c.x, c.y, c.z), T.E2, T.n_bins, T.inv_w64);
+                if (b < T.n_bins) {
+                    if (LDS_HIST) atomicAdd(&T.hist_l[b], 1u);
+                    else atomicAdd((unsigned long long*)&T.hist_g[b], 1ull);
+                    ++hits;
+                }
+            }
+            const bool in = me && d2 <= rk2;
+            if (__ballot(in && d2 < top[KMAX - 1])) {
+                float x = in ? d2 : INFINITY;
+#pragma unroll
+                for (int q = 0; q < KMAX; ++q) {
+                    const float lo = fminf(x, top[q]);
+                    x = fmaxf(x, top[q]);
+                    top[q] = lo;
+                }
+            }
+        }
+        wave_sync();
+    };
+    int m = 0;
+    auto stage_one = [&](auto&& sc) {
+        return [&, sc](bool v, float4 c) {
+            const uint64_t bal = __ballot(v);
+            const int nn = __popcll(bal);
+            if (m + nn > kStage) {
+                sc(m);
+                m = 0;
+            }
+            if (v) stage[m + __popcll(bal & lanemask_lt())] = c;
+            m += nn;
+        };
+    };
+    enumerate_box(P, T.cell_start, T.bpos, x0, y0, z0, x1, y1, z1, R, stage_one(scan));
+    if (m > 0) scan(m);
+
+    // the k-th distance and how many of the k nearest lie strictly nearer
+    float tau = top[0];
+#pragma unroll
+    for (int q = 1; q < KMAX; ++q)
+        if (q == k - 1) tau = top[q];
+    int nearer = 0;
+#pragma unroll
+    for (int q = 0; q < KMAX; ++q) nearer += (q < k && top[q] < tau);
+    bool settled = fin && tau <= rk2 && nearer == k - 1;
+    // second pass: the smallest index at exactly the k-th distance
+    float tmax = settled ? tau : 0.0f;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) tmax = fmaxf(tmax, __shfl_xor(tmax, d, kWave));
+    uint32_t jk = 0xFFFFFFFFu;
+    if (__any(settled)) {
+        auto scan2 = [&](int mm) {
+            wave_sync();
+            for (int j = 0; j < mm; ++j) {
+                const float4 c = stage[j];
+                const float dx = c.x - px, dy = c.y - py, dz = c.z - pz;
+                const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                const uint32_t cj = __builtin_bit_cast(uint32_t, c.w);
+                const bool me = settled && (!SELF || cj != i);
+                if (me && d2 == tau && cj < jk) jk = cj;
+            }
+            wave_sync();
+        };
+        m = 0;
+        enumerate_box(P, T.cell_start, T.bpos, x0, y0, z0, x1, y1, z1, sqrtf(tmax) * 1.000001f, stage_one(scan2));
+        if (m > 0) scan2(m);
+    }
+    settled = settled && jk != 0xFFFFFFFFu;
+    return settled ? (((uint64_t)__builtin_bit_cast(uint32_t, tau) << 32) | (uint64_t)jk) : ~0ull;
+}
+
 // Flush a per-wavefront u32 LDS histogram into a global u64 histogram.
 __device__ __forceinline__ void flush_hist(uint32_t* hist_l, uint64_t* hist_g, int n_bins) {
     for (int b = lane_id(); b < n_bins; b += kWave) {
