@@ -370,6 +370,38 @@ def test_batched_many_replicates_cross_blocks(gpu, synth):
     assert torch.equal(rh, lr) and torch.equal(kh, lk)
 
 
+def test_batched_lattice_ties_equal_looped(gpu, orc):
+    """A simple cubic lattice (every distance shared by many pairs) with
+    three species: dense Al targets take the tiles, whose k-th key is settled
+    by the smallest index at the k-th distance, or left to the exact
+    one-by-one search when the k-th distance is shared inside the k nearest.
+    Equal to looped plain calls and to the oracle."""
+    _say("case batched lattice ties")
+    aptstat, torch, ws = gpu
+    gl = np.arange(26, dtype=np.float32) * 0.5
+    X, Y, Z = np.meshgrid(gl, gl, gl, indexing="ij")
+    xyz = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1).astype(np.float32)
+    rng = np.random.default_rng(12)
+    xyz = xyz[rng.permutation(len(xyz))]
+    lab = rng.choice(np.array([AL, SC, SI], np.uint8), len(xyz), p=[0.9, 0.04, 0.06])
+    hi = 12.5
+    d = np.minimum(xyz, hi - xyz).min(1).astype(np.float32)
+    args = _to_dev(torch, xyz, lab, d)
+    seeds = [5, 6, 7]
+    pairs = [(AL, SC), (AL, SI), (SC, AL)]
+    for k in (1, 6, 10):
+        rh, kh, st = aptstat.rdf_batched(aptstat.Cloud(*args), [(A, B, 1.0) for A, B in pairs], seeds,
+                                         r_max=2.0, n_bins=40, k=k, kb_rmax=3.0, kb_nbins=300, ws=ws)
+        lr, lk = _looped(gpu, args, pairs, seeds, 1.0, 2.0, 40, k, 3.0, 300)
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0
+        assert torch.equal(rh, lr) and torch.equal(kh, lk), k
+        lab_r = orc.permute_labels(lab, seeds[0])
+        for p, (A, B) in enumerate(pairs):
+            ok = orc.knn(xyz, lab_r, d, A, B, 1.0, k, kb_rmax=3.0, kb_nbins=300)[3]
+            assert np.array_equal(kh[0, p].cpu().numpy().astype(np.uint64), ok), (k, p)
+
+
 # ---------------------------------------------------------------------------
 # 64 targets per wavefront (tile mode) and one target per wavefront, forced
 # ---------------------------------------------------------------------------
