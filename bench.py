@@ -84,6 +84,41 @@ def cpu_baseline(spec_name, queries, d_srf, use_d, seconds_budget=25.0):
                       f"(RDF + kNN k={K} + k-th histogram), {dt:.1f} s"}
 
 
+def smooth_timing(aptstat, torch, reps=10):
+    """Gaussian-smoothed RDF (forward and adjoint) on the differentiable
+    workload: 1e6 ions in a 32 nm cube with 500 Sc clusters, Sc -> Sc,
+    sigma 0.02 nm, 200 bins to 2 nm, z scale 1.05; loss sum (h - t)^2 with
+    the target curve of the next seed."""
+    import aptsynth
+
+    dev = torch.device("cuda:0")
+    ws = aptstat.Workspace()
+    curves = []
+    for seed in (1, 2):
+        xyz, lab, d = aptsynth.to_device(aptsynth.box1m(seed), torch, dev, with_d_bnd=False)
+        curves.append((xyz, lab))
+    zs = torch.tensor([1.05], dtype=torch.float64, device=dev)
+    args = (SC, SC, 0.0, R_MAX, N_BINS, 0.02)
+    t = aptstat.rdf_smooth(aptstat.Cloud(*curves[1]), *args, z_scale=zs, ws=ws)
+    cloud = aptstat.Cloud(*curves[0])
+    h = aptstat.rdf_smooth(cloud, *args, z_scale=zs, ws=ws)
+    gh = (2.0 * (h - t)).contiguous()
+    aptstat.rdf_smooth_grad(cloud, *args, gh, z_scale=zs, ws=ws)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for _ in range(reps):
+        aptstat.rdf_smooth(cloud, *args, z_scale=zs, ws=ws, out=h)
+    ev[1].record()
+    for _ in range(reps):
+        aptstat.rdf_smooth_grad(cloud, *args, gh, z_scale=zs, ws=ws)
+    ev[2].record()
+    torch.cuda.synchronize()
+    return {"workload": "box1m", "query": "Sc->Sc", "sigma_nm": 0.02, "z_scale": 1.05,
+            "forward_ms": ev[0].elapsed_time(ev[1]) / reps, "adjoint_ms": ev[1].elapsed_time(ev[2]) / reps,
+            "smoothed_mass": float(h.sum().item())}
+
+
 PAIRS6 = [(AL, SC), (AL, SI), (SC, AL), (SC, SI), (SI, AL), (SI, SC)]
 
 
@@ -150,6 +185,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="frustum7m", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-smooth", action="store_true", help="skip the smoothed-RDF timing")
     ap.add_argument("--batched-reps", type=int, default=256,
                     help="replicates of the batched null-model measurement (0 = skip)")
     ap.add_argument("--looped-reps", type=int, default=16,
@@ -264,6 +300,9 @@ def main():
     }
     if args.batched_reps > 0 and args.workload == "frustum7m":
         line["batched"] = batched_vs_looped(aptstat, torch, cloud, ws, args.batched_reps, args.looped_reps)
+    if args.workload == "frustum7m" and not args.no_smooth:
+        log("[bench] smoothed RDF on box1m")
+        line["smooth"] = smooth_timing(aptstat, torch)
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host")
         line["cpu_baseline"] = cpu_baseline(gen_name, queries, d_srf, use_d)

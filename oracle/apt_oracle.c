@@ -12,7 +12,7 @@
  * processing queues"):
  *   - a target ("central") ion is an ion of species A whose distance to the
  *     specimen edge is at least d_srf (Methods: "Ion-to-edge distancing";
- *     caption of the table of AM case-study tasks: "at least d_srf");
+ *     the table of AM case-study tasks states the distance as a minimum);
  *   - neighbours are ions of species B other than the target itself; the
  *     edge filter applies to targets only;
  *   - kNN: the distances to each target's k-th nearest neighbours;
