@@ -216,14 +216,19 @@ apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_tar
  *   tile_policy  0 automatic, 1 one target per wavefront, 2 64 targets per
  *                wavefront with LDS-staged neighbours and a register kNN list
  *                (used only when k <= 16 and n_bins <= 2048)
- *   cell_occ     neighbours per grid cell aimed at (default 4)
+ *   cell_occ     neighbours per grid cell aimed at with one target per
+ *                wavefront (default 4)
  *   h_min_frac   smallest cell edge as a fraction of r_max (default 0.5)
- * apt_set_tuning(NULL) restores the defaults. */
+ *   tile_occ     neighbours per grid cell aimed at with 64 targets per
+ *                wavefront (default 1; 0 selects the default)
+ * Out-of-range values (tile_policy outside 0..2, cell_occ or h_min_frac not
+ * finite and > 0, tile_occ not finite and >= 0) return APT_E_ARG and leave
+ * the tuning unchanged.  apt_set_tuning(NULL) restores the defaults. */
 typedef struct {
     int32_t tile_policy;
     float cell_occ;
     float h_min_frac;
-    float reserved;
+    float tile_occ;
 } apt_tuning;
 apt_status apt_set_tuning(const apt_tuning* t);
 apt_status apt_get_tuning(apt_tuning* t);

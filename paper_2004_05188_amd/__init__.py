@@ -45,7 +45,7 @@ class _Query(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("tile_policy", ctypes.c_int32), ("cell_occ", ctypes.c_float), ("h_min_frac", ctypes.c_float),
-                ("reserved", ctypes.c_float)]
+                ("tile_occ", ctypes.c_float)]
 
 
 class _Bins(ctypes.Structure):
@@ -167,16 +167,17 @@ class Workspace:
         return self.buf
 
 
-def set_tuning(tile_policy: int = 0, cell_occ: float = 4.0, h_min_frac: float = 0.5):
+def set_tuning(tile_policy: int = 0, cell_occ: float = 4.0, h_min_frac: float = 0.5, tile_occ: float = 1.0):
     """Process-wide speed knobs (results do not depend on them)."""
-    t = _Tuning(int(tile_policy), float(cell_occ), float(h_min_frac), 0.0)
+    t = _Tuning(int(tile_policy), float(cell_occ), float(h_min_frac), float(tile_occ))
     _check(lib().apt_set_tuning(ctypes.byref(t)), "apt_set_tuning")
 
 
 def get_tuning() -> dict:
     t = _Tuning()
     _check(lib().apt_get_tuning(ctypes.byref(t)), "apt_get_tuning")
-    return {"tile_policy": t.tile_policy, "cell_occ": t.cell_occ, "h_min_frac": t.h_min_frac}
+    return {"tile_policy": t.tile_policy, "cell_occ": t.cell_occ, "h_min_frac": t.h_min_frac,
+            "tile_occ": t.tile_occ}
 
 
 def trace_enable(on: bool = True):
@@ -185,7 +186,8 @@ def trace_enable(on: bool = True):
 
 
 def trace_read(stage: str):
-    """(total ms, launches) of one stage ("binning" or "pair") since the last read."""
+    """(total ms, launches) of one stage ("binning", "pair", "tile", "permute" or
+    "partition") since the last read."""
     ms, n = ctypes.c_double(0.0), ctypes.c_int64(0)
     _check(lib().apt_trace_read(stage.encode(), ctypes.byref(ms), ctypes.byref(n)), "apt_trace_read")
     return ms.value, n.value

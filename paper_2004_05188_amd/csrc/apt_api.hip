@@ -44,7 +44,7 @@ static DevInfo device_info() {
 
 // ------------------------------------------------------------- tuning --
 static std::mutex g_tune_mu;
-static apt_tuning g_tune = {0, 4.0f, 0.5f, 0.0f};
+static apt_tuning g_tune = {0, 4.0f, 0.5f, 1.0f};
 
 static apt_tuning tuning() {
     std::lock_guard<std::mutex> g(g_tune_mu);
@@ -455,6 +455,7 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     PlanParams pp;
     pp.h_min = do_rdf ? rb->r_max * tu.h_min_frac : 0.0f;
     pp.occ = tu.cell_occ;
+    pp.tile_occ = tu.tile_occ;
     pp.k = do_knn ? k : 0;
     pp.cell_cap = cell_cap_for(cl->n);
     // tiles need an LDS histogram and at most 16 kNN keys per lane
@@ -792,6 +793,7 @@ static apt_status run_smooth(bool bwd, const apt_cloud* cl, apt_query q, apt_bin
     PlanParams pp;
     pp.h_min = r_pre * tu.h_min_frac;
     pp.occ = tu.cell_occ;
+    pp.tile_occ = 0.0f;
     pp.k = 0;
     pp.cell_cap = cell_cap_for(cl->n);
     pp.tile_policy = 1;
@@ -854,12 +856,15 @@ extern "C" {
 const char* apt_last_error(void) { return g_err.c_str(); }
 
 apt_status apt_set_tuning(const apt_tuning* t) {
-    apt_tuning v = {0, 4.0f, 0.5f, 0.0f};
+    apt_tuning v = {0, 4.0f, 0.5f, 1.0f};
     if (t) {
         if (t->tile_policy < 0 || t->tile_policy > 2) return fail(APT_E_ARG, "tile_policy must be 0, 1 or 2");
         if (!(t->cell_occ > 0.0f) || !(t->h_min_frac > 0.0f) || !isfinite(t->cell_occ) || !isfinite(t->h_min_frac))
             return fail(APT_E_ARG, "cell_occ and h_min_frac must be finite and > 0");
+        if (!(t->tile_occ >= 0.0f) || !isfinite(t->tile_occ))
+            return fail(APT_E_ARG, "tile_occ must be finite and >= 0");
         v = *t;
+        if (v.tile_occ == 0.0f) v.tile_occ = 1.0f;
     }
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune = v;

@@ -165,12 +165,28 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
         amax = fmax(amax, fmax(fabs((double)l), fabs((double)h)));
     }
     const PlanParams& pp = a.pp;
-    // cell edge: at least h_min, and large enough to hold ~occ neighbours
     double vol = 1.0;
     for (int c = 0; c < 3; ++c) vol *= fmax(ext[c], 1e-3);
     const double rho = (double)(totB > 0 ? totB : 1) / vol;
     const double emax = fmax(ext[0], fmax(ext[1], ext[2]));
-    double h = fmax((double)pp.h_min, cbrt((double)pp.occ / rho));
+    // the Poisson mean k-th neighbour distance with a margin: the first kNN
+    // search radius (clamped to the cloud's diagonal below)
+    const double rk_raw = pp.k > 0 ? 1.15 * cbrt(3.0 * ((double)pp.k + 0.5) / (4.0 * M_PI * rho)) : 0.0;
+    // 64 consecutive targets (cell order) per wavefront when the targets are at
+    // least as dense as the neighbours; their kNN is certified within rk_tile
+    if (pp.tile_policy == 1) P.tile_mode = 0;
+    else if (pp.tile_policy == 2) P.tile_mode = pp.k <= 16 ? 1 : 0;
+    else {
+        // a tile pays when its 64 targets fill a region no larger than the
+        // search reach, so that they share most of their candidates
+        const double R = fmax((double)pp.r_enum, 1.6 / 1.15 * rk_raw);
+        const double v64 = 64.0 * vol / (double)(totT > 0 ? totT : 1);
+        P.tile_mode = (pp.k <= 16 && totT >= totB && totT >= 4096 && v64 <= R * R * R) ? 1 : 0;
+    }
+    // cell edge: at least h_min, and large enough to hold ~occ neighbours
+    // (tiles gather every candidate of their 64 targets: smaller cells pay)
+    const double occ = (P.tile_mode && pp.tile_occ > 0.0f) ? (double)pp.tile_occ : (double)pp.occ;
+    double h = fmax((double)pp.h_min, cbrt(occ / rho));
     if (totB == 0 || !(h > 0.0)) h = emax + 1.0;
     if (h < 1e-6 * (emax + 1.0)) h = 1e-6 * (emax + 1.0);
     if (h > 3.0e38) h = 3.0e38;
@@ -220,26 +236,10 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
     const double diag = sqrt((ext[0] + hd) * (ext[0] + hd) + (ext[1] + hd) * (ext[1] + hd) +
                              (ext[2] + hd) * (ext[2] + hd));
     P.r_all = (float)fmin(diag + 2.0 * hd, 3.0e38);
-    if (pp.k > 0) {
-        double r = 1.15 * cbrt(3.0 * ((double)pp.k + 0.5) / (4.0 * M_PI * rho));
-        P.rk0 = (float)fmin(r, (double)P.r_all);
-    } else {
-        P.rk0 = 0.0f;
-    }
+    P.rk0 = pp.k > 0 ? (float)fmin(rk_raw, (double)P.r_all) : 0.0f;
     P.zscale = a.zscale ? (float)*a.zscale : 1.0f;
     P.nonfinite = s_nf[0];
-    // 64 consecutive targets (cell order) per wavefront when the targets are at
-    // least as dense as the neighbours; their kNN is certified within rk_tile
     P.rk_tile = pp.k > 0 ? (float)fmin(1.6 / 1.15 * (double)P.rk0, (double)P.r_all) : 0.0f;
-    if (pp.tile_policy == 1) P.tile_mode = 0;
-    else if (pp.tile_policy == 2) P.tile_mode = pp.k <= 16 ? 1 : 0;
-    else {
-        // a tile pays when its 64 targets fill a region no larger than the
-        // search reach, so that they share most of their candidates
-        const double R = fmax((double)pp.r_enum, (double)P.rk_tile);
-        const double v64 = 64.0 * vol / (double)(totT > 0 ? totT : 1);
-        P.tile_mode = (pp.k <= 16 && totT >= totB && totT >= 4096 && v64 <= R * R * R) ? 1 : 0;
-    }
     *a.plan = P;
     if (s_nf[0] && a.status) atomicOr(a.status, APT_STATUS_NONFINITE);
 }
@@ -327,9 +327,11 @@ __global__ __launch_bounds__(kBlock) void k_keys(KeyArgs a) {
 //    inside each wavefront with ballots, then placed through LDS so that
 //    the global writes of one digit are contiguous.
 // ------------------------------------------------------------------------
-constexpr int kRsItems = 8;
-constexpr int kRsTile = kBlock * kRsItems;   // 2048
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kBlock * kRsItems;   // 4096
 constexpr int kRadix = 256;
+constexpr int kRsUp = 8;                     // keys per thread in flight in the upsweep
+constexpr int kGatherItems = 4;              // random position reads per thread in flight
 
 __device__ __forceinline__ bool rs_active(const GridPlan& P, const SortArgs& a) {
     return (uint32_t)a.pass < (a.count_is_T ? P.passes_T : P.passes);
@@ -355,8 +357,19 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortArgs a) {
     if (end > n) end = n;
     const int w = threadIdx.x / kWave;
     const uint32_t shift = 8u * (uint32_t)a.pass;
-    for (uint64_t i = beg + threadIdx.x; i < end; i += kBlock)
-        atomicAdd(&s_h[w][(keys[i] >> shift) & 0xFFu], 1u);
+    // kRsUp independent coalesced loads in flight per thread before the
+    // LDS counts (one load at a time leaves the pass latency-bound)
+    for (uint64_t i0 = beg + threadIdx.x; i0 < end; i0 += (uint64_t)kBlock * kRsUp) {
+        uint32_t k[kRsUp];
+#pragma unroll
+        for (int u = 0; u < kRsUp; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * kBlock;
+            k[u] = i < end ? keys[i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kRsUp; ++u)
+            if (i0 + (uint64_t)u * kBlock < end) atomicAdd(&s_h[w][(k[u] >> shift) & 0xFFu], 1u);
+    }
     __syncthreads();
     for (int d = threadIdx.x; d < kRadix; d += kBlock) {
         uint32_t s = 0;
@@ -433,17 +446,33 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortArgs a) {
     }
     __syncthreads();
 
+    // the next tile's keys and values are loaded while this one is ranked
+    // and written (register double buffer)
+    uint32_t nkey[kRsItems], nval[kRsItems];
+    auto load_tile = [&](uint64_t tile) {
+#pragma unroll
+        for (int j = 0; j < kRsItems; ++j) {
+            const uint64_t i = tile + (uint64_t)w * (kRsItems * kWave) + (uint64_t)j * kWave + l;
+            nkey[j] = i < end ? kin[i] : 0u;
+            nval[j] = i < end ? vin[i] : 0u;
+        }
+    };
+    if (beg < end) load_tile(beg);
     for (uint64_t tile = beg; tile < end; tile += kRsTile) {
-        for (int i = t; i < kWavesPerBlock * kRadix; i += kBlock) (&s_wcnt[0][0])[i] = 0;
-        __syncthreads();
         uint32_t key[kRsItems], val[kRsItems], pos[kRsItems];
         bool ok[kRsItems];
 #pragma unroll
         for (int j = 0; j < kRsItems; ++j) {
+            key[j] = nkey[j];
+            val[j] = nval[j];
+        }
+        if (tile + kRsTile < end) load_tile(tile + kRsTile);
+        for (int i = t; i < kWavesPerBlock * kRadix; i += kBlock) (&s_wcnt[0][0])[i] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kRsItems; ++j) {
             const uint64_t i = tile + (uint64_t)w * (kRsItems * kWave) + (uint64_t)j * kWave + l;
             ok[j] = i < end;
-            key[j] = ok[j] ? kin[i] : 0u;
-            val[j] = ok[j] ? vin[i] : 0u;
             const uint32_t d = (key[j] >> shift) & 0xFFu;
             uint64_t peers = __ballot(ok[j]);
 #pragma unroll
@@ -513,14 +542,37 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortArgs a) {
 __global__ __launch_bounds__(kBlock) void k_take_order(OrderArgs a) {
     const GridPlan P = *a.plan;
     const uint32_t* __restrict__ v = a.vals[P.passes_T & 1];
-    for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < P.nT; t += gridDim.x * kBlock) {
-        const uint32_t rank = v[t];
-        const uint32_t id = a.tid[rank];
-        a.t_rank[t] = rank;
-        a.t_id[t] = id;
-        a.tx[t] = a.xyz[3 * (size_t)id];
-        a.ty[t] = a.xyz[3 * (size_t)id + 1];
-        a.tz[t] = a.xyz[3 * (size_t)id + 2];
+    const uint64_t nT = P.nT, stride = (uint64_t)gridDim.x * kBlock;
+    // kGatherItems targets per thread in flight: the position reads are random
+    for (uint64_t t0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t0 < nT; t0 += stride * kGatherItems) {
+        uint32_t rank[kGatherItems], id[kGatherItems];
+        float x[kGatherItems], y[kGatherItems], z[kGatherItems];
+#pragma unroll
+        for (int u = 0; u < kGatherItems; ++u) {
+            const uint64_t t = t0 + (uint64_t)u * stride;
+            rank[u] = t < nT ? v[t] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherItems; ++u) id[u] = t0 + (uint64_t)u * stride < nT ? a.tid[rank[u]] : 0u;
+#pragma unroll
+        for (int u = 0; u < kGatherItems; ++u) {
+            if (t0 + (uint64_t)u * stride < nT) {
+                x[u] = a.xyz[3 * (size_t)id[u]];
+                y[u] = a.xyz[3 * (size_t)id[u] + 1];
+                z[u] = a.xyz[3 * (size_t)id[u] + 2];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherItems; ++u) {
+            const uint64_t t = t0 + (uint64_t)u * stride;
+            if (t < nT) {
+                a.t_rank[t] = rank[u];
+                a.t_id[t] = id[u];
+                a.tx[t] = x[u];
+                a.ty[t] = y[u];
+                a.tz[t] = z[u];
+            }
+        }
     }
 }
 
@@ -538,17 +590,34 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
         for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c <= nc; c += stride) a.cell_start[c] = 0;
         return;
     }
-    for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < nB; p += stride) {
-        const uint32_t id = val[p];
-        float z = a.xyz[3 * (size_t)id + 2];
-        if (a.zscale) z = (float)((double)z * sd);
-        a.bpos[p] = make_float4(a.xyz[3 * (size_t)id], a.xyz[3 * (size_t)id + 1], z,
-                                __builtin_bit_cast(float, id));
-        const uint32_t c = key[p];
-        const uint32_t cprev = p == 0 ? 0u : key[p - 1] + 1u;
-        for (uint32_t q = cprev; q <= c; ++q) a.cell_start[q] = p;
-        if (p == nB - 1)
-            for (uint32_t q = c + 1; q <= nc; ++q) a.cell_start[q] = nB;
+    // kGatherItems ions per thread in flight: the position reads are random
+    const uint64_t st64 = stride;
+    for (uint64_t p0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p0 < nB; p0 += st64 * kGatherItems) {
+        uint32_t id[kGatherItems];
+        float x[kGatherItems], y[kGatherItems], z[kGatherItems];
+#pragma unroll
+        for (int u = 0; u < kGatherItems; ++u) id[u] = p0 + (uint64_t)u * st64 < nB ? val[p0 + (uint64_t)u * st64] : 0u;
+#pragma unroll
+        for (int u = 0; u < kGatherItems; ++u) {
+            if (p0 + (uint64_t)u * st64 < nB) {
+                x[u] = a.xyz[3 * (size_t)id[u]];
+                y[u] = a.xyz[3 * (size_t)id[u] + 1];
+                z[u] = a.xyz[3 * (size_t)id[u] + 2];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kGatherItems; ++u) {
+            const uint64_t pp = p0 + (uint64_t)u * st64;
+            if (pp >= nB) continue;
+            const uint32_t p = (uint32_t)pp;
+            const float zz = a.zscale ? (float)((double)z[u] * sd) : z[u];
+            a.bpos[p] = make_float4(x[u], y[u], zz, __builtin_bit_cast(float, id[u]));
+            const uint32_t c = key[p];
+            const uint32_t cprev = p == 0 ? 0u : key[p - 1] + 1u;
+            for (uint32_t q = cprev; q <= c; ++q) a.cell_start[q] = p;
+            if (p == nB - 1)
+                for (uint32_t q = c + 1; q <= nc; ++q) a.cell_start[q] = nB;
+        }
     }
 }
 

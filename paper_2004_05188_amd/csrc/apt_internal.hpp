@@ -47,6 +47,7 @@ struct PlanParams {
     uint32_t cell_cap;  // largest number of cells the workspace holds
     int32_t tile_policy;  // 0: automatic, 1: one target per wavefront, 2: 64 targets per wavefront
     float r_enum;       // RDF enumeration radius (0: no RDF)
+    float tile_occ;     // aimed-for neighbours per cell with 64 targets per wavefront (<= 0: occ)
 };
 
 // ---------------------------------------------------------------- waves --

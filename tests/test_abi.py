@@ -111,3 +111,23 @@ def test_knn_argument_validation(aptstat):
     assert L.apt_knn(*args(10, math.nan, 10, p)) == -1
     assert L.apt_knn(*args(10, math.inf, -1, p)) == -1         # capacity < 0
     assert L.apt_knn(*args(10, math.inf, 10, None)) == -1      # NULL rows
+
+
+def test_tuning_round_trip_and_validation(aptstat):
+    """The tuning is host state: set, read back, rejected when out of range
+    (unchanged then), and NULL restores the defaults."""
+    try:
+        aptstat.set_tuning(2, 3.0, 0.7, 0.5)
+        assert aptstat.get_tuning() == {"tile_policy": 2, "cell_occ": 3.0, "h_min_frac": 0.699999988079071,
+                                        "tile_occ": 0.5}
+        for bad in ((3, 4.0, 0.5, 1.0), (0, 0.0, 0.5, 1.0), (0, 4.0, math.nan, 1.0), (0, 4.0, 0.5, -1.0),
+                    (0, 4.0, 0.5, math.inf)):
+            with pytest.raises(aptstat.AptError):
+                aptstat.set_tuning(*bad)
+            assert aptstat.get_tuning()["tile_occ"] == 0.5
+        aptstat.set_tuning(0, 4.0, 0.5, 0.0)           # 0 selects the default tile occupancy
+        assert aptstat.get_tuning()["tile_occ"] == 1.0
+        assert aptstat.lib().apt_set_tuning(None) == 0
+        assert aptstat.get_tuning() == {"tile_policy": 0, "cell_occ": 4.0, "h_min_frac": 0.5, "tile_occ": 1.0}
+    finally:
+        aptstat.set_tuning()
