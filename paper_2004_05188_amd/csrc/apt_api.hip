@@ -187,15 +187,20 @@ struct PermWs {
     size_t bytes;
 };
 
+// Up to kPermLdsMax labels the two-level form runs (coarse buckets, no key
+// array); beyond, fine buckets of about 32 keys with keys and indices.
+static bool perm_two_level(int64_t n) { return n <= kPermLdsMax; }
+
 static PermWs carve_perm(void* base, int64_t n, int reps) {
     Carve c{reinterpret_cast<char*>(base)};
     PermWs w;
-    const size_t nb = (size_t)1 << perm_bucket_bits(n);
+    const bool two = perm_two_level(n);
+    const size_t nb = (size_t)1 << (two ? perm_coarse_bits(n) : perm_bucket_bits(n));
     const size_t N = (size_t)(n > 0 ? n : 1);
     w.count = c.take<uint32_t>(nb * reps);
     w.cursor = c.take<uint32_t>(nb * reps);
     w.part = c.take<uint32_t>(1024);
-    w.ekey = c.take<uint64_t>(N * reps);
+    w.ekey = two ? nullptr : c.take<uint64_t>(N * reps);
     w.eidx = c.take<uint32_t>(N * reps);
     w.bytes = c.off;
     return w;
@@ -207,9 +212,10 @@ static void run_permute(const uint8_t* lab, int64_t n, const uint64_t* seeds, in
     for (int r0 = 0; r0 < reps; r0 += kMaxRepPerLaunch) {
         const int nr = reps - r0 < kMaxRepPerLaunch ? reps - r0 : kMaxRepPerLaunch;
         PermArgs pa{};
+        const bool two = perm_two_level(n);
         pa.lab = lab;
         pa.n = n;
-        pa.bits = perm_bucket_bits(n);
+        pa.bits = two ? perm_coarse_bits(n) : perm_bucket_bits(n);
         pa.n_rep = nr;
         for (int r = 0; r < nr; ++r) pa.seeds[r] = seeds[r0 + r];
         pa.count = w.count;
@@ -221,6 +227,15 @@ static void run_permute(const uint8_t* lab, int64_t n, const uint64_t* seeds, in
         pa.status = status;
         const int64_t nb = (int64_t)1 << pa.bits;
         const int cus = device_info().cus;
+        if (two) {
+            const int gd = n > 0 ? (int)((n + kPermChunk - 1) / kPermChunk) : 1;
+            hipLaunchKernelGGL(k_perm_zero, dim3(cus * 4), dim3(kBlock), 0, st, pa);
+            hipLaunchKernelGGL(k_permc_count, dim3(gd, nr), dim3(kBlock), perm_deal_lds_bytes(pa.bits) / 2, st, pa);
+            device_excl_scan(w.count, nb * nr, w.part, st);
+            hipLaunchKernelGGL(k_permc_place, dim3(gd, nr), dim3(kBlock), perm_deal_lds_bytes(pa.bits), st, pa);
+            hipLaunchKernelGGL(k_permc_sort, dim3((unsigned)nb, nr), dim3(kBlock), 0, st, pa);
+            continue;
+        }
         int gx = (int)((n + kBlock * 4 - 1) / (kBlock * 4));
         if (gx > cus * 8) gx = cus * 8;
         if (gx < 1) gx = 1;

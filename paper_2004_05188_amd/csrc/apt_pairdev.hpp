@@ -52,13 +52,18 @@ __device__ __forceinline__ void enumerate_box(const GridPlan& P, const uint32_t*
     const float R2 = Re * Re;
     const int cy0 = cell_axis(P, 1, y0 - Re), cy1 = cell_axis(P, 1, y1 + Re);
     const int cz0 = cell_axis(P, 2, z0 - Re), cz1 = cell_axis(P, 2, z1 + Re);
-    const int ny = cy1 - cy0 + 1;
-    const int nrows = ny * (cz1 - cz0 + 1);
+    const int ny = cy1 - cy0 + 1, nz = cz1 - cz0 + 1;
+    const int nrows = ny * nz;
+    // rows centre-out along z and y (middle of each range first, then
+    // alternately below and above): the nearest candidates come first, so
+    // that a k-smallest list fills early and later, farther candidates
+    // seldom change it (visiting order never changes a result)
+    auto centre_out = [](int i, int L) { return L / 2 + ((i & 1) ? -((i + 1) >> 1) : (i >> 1)); };
     for (int rb = 0; rb < nrows; rb += kWave) {
         const int r = rb + l;
         uint32_t st = 0, len = 0;
         if (r < nrows) {
-            const int cz = cz0 + r / ny, cy = cy0 + r % ny;
+            const int cz = cz0 + centre_out(r / ny, nz), cy = cy0 + centre_out(r % ny, ny);
             const float ya = P.lo[1] + (float)cy * P.h - P.eps, yb = P.lo[1] + (float)(cy + 1) * P.h + P.eps;
             const float za = P.lo[2] + (float)cz * P.h - P.eps, zb = P.lo[2] + (float)(cz + 1) * P.h + P.eps;
             const float dy = fmaxf(0.0f, fmaxf(ya - y1, y0 - yb));

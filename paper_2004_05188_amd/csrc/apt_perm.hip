@@ -194,4 +194,174 @@ __global__ __launch_bounds__(kBlock) void k_perm_sort(PermArgs a) {
     }
 }
 
+// ------------------------------------------------ two-level form (LDS) --
+// For n <= kPermLdsMax: coarse buckets by the top `bits` key bits (at most
+// 2^13, about 2048 keys each), counted and filled with one global atomic per
+// (workgroup, bucket); a coarse bucket is then split by the next six bits in
+// LDS and every fine bucket (about 32 keys) ordered by one wavefront.  Only
+// the indices travel through memory; keys are recomputed from them.
+
+int perm_coarse_bits(int64_t n) {
+    int b = 0;
+    while (b < 13 && ((int64_t)2048 << b) < n) ++b;
+    return b;
+}
+
+size_t perm_deal_lds_bytes(int coarse_bits) { return (size_t)2 * 4u << coarse_bits; }
+
+__device__ __forceinline__ uint32_t coarse_of(uint64_t key, int bits) {
+    return bits ? (uint32_t)(key >> (64 - bits)) : 0u;
+}
+__device__ __forceinline__ uint32_t fine_of(uint64_t key, int bits) {
+    return (uint32_t)(key >> (64 - bits - kPermFineBits)) & ((1u << kPermFineBits) - 1u);
+}
+
+// block counts of the coarse buckets, added to count[r][b]
+__global__ __launch_bounds__(kBlock) void k_permc_count(PermArgs a) {
+    extern __shared__ uint32_t s_h[];
+    const int r = blockIdx.y;
+    const uint64_t seed = a.seeds[r];
+    const int nb = 1 << a.bits;
+    for (int b = threadIdx.x; b < nb; b += kBlock) s_h[b] = 0;
+    __syncthreads();
+    const int64_t beg = (int64_t)blockIdx.x * kPermChunk;
+    const int64_t end = beg + kPermChunk < a.n ? beg + kPermChunk : a.n;
+    for (int64_t i = beg + threadIdx.x; i < end; i += kBlock)
+        atomicAdd(&s_h[coarse_of(splitmix64(seed, (uint64_t)i), a.bits)], 1u);
+    __syncthreads();
+    uint32_t* cnt = a.count + (size_t)r * nb;
+    for (int b = threadIdx.x; b < nb; b += kBlock)
+        if (s_h[b]) atomicAdd(&cnt[b], s_h[b]);
+}
+
+// indices into their coarse buckets (count[] now holds the global starts);
+// the order inside a bucket is arbitrary: k_permc_sort orders it
+__global__ __launch_bounds__(kBlock) void k_permc_place(PermArgs a) {
+    extern __shared__ uint32_t s_mem[];
+    const int nb = 1 << a.bits;
+    uint32_t* s_h = s_mem;
+    uint32_t* s_base = s_mem + nb;
+    const int r = blockIdx.y;
+    const uint64_t seed = a.seeds[r];
+    for (int b = threadIdx.x; b < nb; b += kBlock) s_h[b] = 0;
+    __syncthreads();
+    const int64_t beg = (int64_t)blockIdx.x * kPermChunk;
+    const int64_t end = beg + kPermChunk < a.n ? beg + kPermChunk : a.n;
+    for (int64_t i = beg + threadIdx.x; i < end; i += kBlock)
+        atomicAdd(&s_h[coarse_of(splitmix64(seed, (uint64_t)i), a.bits)], 1u);
+    __syncthreads();
+    const uint32_t* start = a.count + (size_t)r * nb;
+    uint32_t* cur = a.cursor + (size_t)r * nb;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+        const uint32_t h = s_h[b];
+        s_base[b] = h ? start[b] + atomicAdd(&cur[b], h) : 0u;
+        s_h[b] = 0;
+    }
+    __syncthreads();
+    for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
+        const uint32_t b = coarse_of(splitmix64(seed, (uint64_t)i), a.bits);
+        a.eidx[s_base[b] + atomicAdd(&s_h[b], 1u)] = (uint32_t)i;
+    }
+}
+
+// one coarse bucket per workgroup: fine buckets in LDS, each ordered by
+// (key, index) by one wavefront (ranks by counting for up to 64 keys, a
+// bitonic sort beyond), labels gathered to their ranks
+__global__ __launch_bounds__(kBlock) void k_permc_sort(PermArgs a) {
+    constexpr int kItems = (kPermCoarseCap + kBlock - 1) / kBlock;
+    constexpr int kFine = 1 << kPermFineBits;
+    static_assert(kFine == kWave, "one wavefront scans the fine counts");
+    __shared__ uint64_t s_k[kPermCoarseCap];
+    __shared__ uint32_t s_v[kPermCoarseCap];
+    __shared__ uint32_t s_fc[kFine], s_fo[kFine];
+    __shared__ uint64_t w_k[kWavesPerBlock][kPermFineCap];
+    __shared__ uint32_t w_v[kWavesPerBlock][kPermFineCap];
+    const int r = blockIdx.y;
+    const uint64_t seed = a.seeds[r];
+    const int nb = 1 << a.bits;
+    const int t = threadIdx.x, l = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(t / kWave);
+    const uint32_t* start = a.count + (size_t)r * nb;
+    const uint64_t rbase = (uint64_t)r * (uint64_t)a.n;
+    const uint8_t* lab = a.lab;
+    uint8_t* out = a.out + (size_t)r * a.out_stride;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        const uint64_t s0 = start[b];
+        const uint64_t s1 = b + 1 < nb ? (uint64_t)start[b + 1] : rbase + (uint64_t)a.n;
+        const int c = (int)(s1 - s0);
+        if (c > kPermCoarseCap) {
+            // probability below 1e-100 for random keys; reported, output invalid
+            if (t == 0 && a.status) atomicOr(a.status, APT_STATUS_CAPACITY);
+            continue;
+        }
+        if (t < kFine) s_fc[t] = 0;
+        __syncthreads();
+        uint64_t kk[kItems];
+        uint32_t vv[kItems];
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            const int q = t + j * kBlock;
+            vv[j] = q < c ? a.eidx[s0 + (uint64_t)q] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            kk[j] = splitmix64(seed, (uint64_t)vv[j]);
+            if (t + j * kBlock < c) atomicAdd(&s_fc[fine_of(kk[j], a.bits)], 1u);
+        }
+        __syncthreads();
+        if (t < kFine) {
+            // kFine == kWave: wavefront 0 scans the fine counts
+            const uint32_t x = s_fc[t];
+            const uint32_t ex = wave_incl_scan(x) - x;
+            s_fo[t] = ex;
+            s_fc[t] = ex;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kItems; ++j) {
+            if (t + j * kBlock < c) {
+                const uint32_t p = atomicAdd(&s_fc[fine_of(kk[j], a.bits)], 1u);
+                s_k[p] = kk[j];
+                s_v[p] = vv[j];
+            }
+        }
+        __syncthreads();
+        for (int f = w; f < kFine; f += kWavesPerBlock) {
+            const int o0 = (int)s_fo[f];
+            const int m = (f + 1 < kFine ? (int)s_fo[f + 1] : c) - o0;
+            if (m > kPermFineCap) {
+                if (l == 0 && a.status) atomicOr(a.status, APT_STATUS_CAPACITY);
+                continue;
+            }
+            if (m == 0) continue;
+            if (m <= kWave) {
+                // lane q's rank among the m (key, index) pairs, the others
+                // broadcast from their lanes: no sorting network, no LDS
+                // round trips
+                const uint64_t mk = l < m ? s_k[o0 + l] : ~0ull;
+                const uint32_t mv = l < m ? s_v[o0 + l] : ~0u;
+                const uint32_t mk_lo = (uint32_t)mk, mk_hi = (uint32_t)(mk >> 32);
+                int rank = 0;
+                for (int j = 0; j < m; ++j) {
+                    const uint64_t kj = ((uint64_t)readlane(mk_hi, j) << 32) | (uint64_t)readlane(mk_lo, j);
+                    const uint32_t vj = readlane(mv, j);
+                    rank += (kj < mk || (kj == mk && vj < mv)) ? 1 : 0;
+                }
+                if (l < m) out[s0 - rbase + (uint64_t)(o0 + rank)] = lab[mv];
+            } else {
+                for (int q = l; q < m; q += kWave) {
+                    w_k[w][q] = s_k[o0 + q];
+                    w_v[w][q] = s_v[o0 + q];
+                }
+                int N = 2;
+                while (N < m) N <<= 1;
+                wave_sort_pairs(w_k[w], w_v[w], m, N);
+                for (int q = l; q < m; q += kWave) out[s0 - rbase + (uint64_t)(o0 + q)] = lab[w_v[w][q]];
+            }
+            wave_sync();
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace apt

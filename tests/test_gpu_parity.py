@@ -280,8 +280,8 @@ def test_frustum7m_queries(gpu, orc, needle7m, A, B):
 # label permutation (null model)
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n,seed", [(0, 1), (1, 5), (31, 7), (1000, 11), (240_000, 2**64 - 1),
-                                    (7_696_902, 123457)])
+@pytest.mark.parametrize("n,seed", [(0, 1), (1, 5), (31, 7), (1000, 11), (2049, 3), (240_000, 2**64 - 1),
+                                    (7_696_902, 123457), (16_777_216, 8), (17_000_000, 99)])
 def test_permute_labels_bit_exact(gpu, orc, synth, n, seed):
     _say(f"case permute n={n} seed={seed}")
     aptstat, torch, ws = gpu
