@@ -214,14 +214,16 @@ apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_tar
 /* Process-wide tuning of the plain entry points (host only; results do not
  * depend on it, only speed):
  *   tile_policy  0 automatic, 1 one target per wavefront, 2 64 targets per
- *                wavefront with LDS-staged neighbours and a register kNN list
- *                (used only when k <= 16 and n_bins <= 2048)
+ *                wavefront with LDS-staged neighbours and a register kNN list,
+ *                3 one target per lane, each lane walking its own cells with a
+ *                register kNN list (2 and 3 only when k <= 16 and
+ *                n_bins <= 2048)
  *   cell_occ     neighbours per grid cell aimed at with one target per
  *                wavefront (default 4)
  *   h_min_frac   smallest cell edge as a fraction of r_max (default 0.5)
  *   tile_occ     neighbours per grid cell aimed at with 64 targets per
- *                wavefront (default 1; 0 selects the default)
- * Out-of-range values (tile_policy outside 0..2, cell_occ or h_min_frac not
+ *                wavefront or one per lane (default 1; 0 selects the default)
+ * Out-of-range values (tile_policy outside 0..3, cell_occ or h_min_frac not
  * finite and > 0, tile_occ not finite and >= 0) return APT_E_ARG and leave
  * the tuning unchanged.  apt_set_tuning(NULL) restores the defaults. */
 typedef struct {

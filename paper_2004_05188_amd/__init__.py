@@ -168,7 +168,10 @@ class Workspace:
 
 
 def set_tuning(tile_policy: int = 0, cell_occ: float = 4.0, h_min_frac: float = 0.5, tile_occ: float = 1.0):
-    """Process-wide speed knobs (results do not depend on them)."""
+    """Process-wide speed knobs (results do not depend on them).
+
+    tile_policy: 0 automatic, 1 one target per wavefront, 2 64 targets per
+    wavefront sharing staged candidates, 3 one target per lane."""
     t = _Tuning(int(tile_policy), float(cell_occ), float(h_min_frac), float(tile_occ))
     _check(lib().apt_set_tuning(ctypes.byref(t)), "apt_set_tuning")
 

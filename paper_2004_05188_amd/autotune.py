@@ -17,7 +17,7 @@ from . import Cloud, Workspace, count_targets, get_tuning, knn_rdf, set_tuning, 
 STAGES = ("binning", "pair", "tile")
 
 DEFAULT_GRID = {
-    "tile_policy": (1, 2),
+    "tile_policy": (1, 2, 3),
     "cell_occ": (2.0, 4.0, 8.0),
     "h_min_frac": (0.35, 0.5, 0.7),
     "tile_occ": (0.5, 1.0, 2.0),
@@ -45,7 +45,7 @@ def autotune(cloud: Cloud, queries, d_srf: float = 0.0, k: int = 10, r_max: floa
         # the cell occupancy of the mode not chosen does not matter
         if st[0] == 1:
             st = (st[0], st[1], st[2], before["tile_occ"])
-        elif st[0] == 2:
+        elif st[0] in (2, 3):
             st = (st[0], before["cell_occ"], st[2], st[3])
         if st not in settings:
             settings.append(st)

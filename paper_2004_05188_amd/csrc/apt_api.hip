@@ -873,7 +873,7 @@ const char* apt_last_error(void) { return g_err.c_str(); }
 apt_status apt_set_tuning(const apt_tuning* t) {
     apt_tuning v = {0, 4.0f, 0.5f, 1.0f};
     if (t) {
-        if (t->tile_policy < 0 || t->tile_policy > 2) return fail(APT_E_ARG, "tile_policy must be 0, 1 or 2");
+        if (t->tile_policy < 0 || t->tile_policy > 3) return fail(APT_E_ARG, "tile_policy must be 0, 1, 2 or 3");
         if (!(t->cell_occ > 0.0f) || !(t->h_min_frac > 0.0f) || !isfinite(t->cell_occ) || !isfinite(t->h_min_frac))
             return fail(APT_E_ARG, "cell_occ and h_min_frac must be finite and > 0");
         if (!(t->tile_occ >= 0.0f) || !isfinite(t->tile_occ))

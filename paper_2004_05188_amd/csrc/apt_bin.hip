@@ -174,8 +174,12 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
     const double rk_raw = pp.k > 0 ? 1.15 * cbrt(3.0 * ((double)pp.k + 0.5) / (4.0 * M_PI * rho)) : 0.0;
     // 64 consecutive targets (cell order) per wavefront when the targets are at
     // least as dense as the neighbours; their kNN is certified within rk_tile
+    // (one target per lane, mode 2, only when asked for: on the sparse needle
+    // queries its lanes' serial walks were no faster than one target per
+    // wavefront)
     if (pp.tile_policy == 1) P.tile_mode = 0;
     else if (pp.tile_policy == 2) P.tile_mode = pp.k <= 16 ? 1 : 0;
+    else if (pp.tile_policy == 3) P.tile_mode = pp.k <= 16 ? 2 : 0;
     else {
         // a tile pays when its 64 targets fill a region no larger than the
         // search reach, so that they share most of their candidates

@@ -206,7 +206,8 @@ __global__ __launch_bounds__(kBlock) void k_pair_tile(PairArgs a) {
         }
         uint32_t hits = 0;
         TopK<KMAX> top;
-        run_tile<FLAGS, KMAX>(P, T, valid, px, py, pz, i, Rk, stage, top, hits);
+        if (P.tile_mode == 2) run_lane<FLAGS, KMAX>(P, T, valid, px, py, pz, i, Rk, top, hits);
+        else run_tile<FLAGS, KMAX>(P, T, valid, px, py, pz, i, Rk, stage, top, hits);
         if (KMAX > 0) {
             // certified: k keys within Rk, or the radius already is r_knn_max
             uint64_t kth = top.key[0];

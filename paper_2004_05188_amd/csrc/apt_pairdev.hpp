@@ -42,6 +42,15 @@ __device__ inline void wave_sort_keys(uint64_t* buf, int c) {
 // so that several memory round trips overlap.
 constexpr int kUnroll = 4;
 
+// The i-th of L rows centre-out (middle of the range first, then
+// alternately below and above; a permutation of [0, L)): the nearest
+// candidates come first, so that a k-smallest list fills early and later,
+// farther candidates seldom change it (the visiting order never changes a
+// result).
+__device__ __forceinline__ int centre_out(int i, int L) {
+    return L / 2 + ((i & 1) ? -((i + 1) >> 1) : (i >> 1));
+}
+
 template <class F>
 __device__ __forceinline__ void enumerate_box(const GridPlan& P, const uint32_t* __restrict__ cell_start,
                                               const float4* __restrict__ bpos, float x0, float y0, float z0,
@@ -54,11 +63,6 @@ __device__ __forceinline__ void enumerate_box(const GridPlan& P, const uint32_t*
     const int cz0 = cell_axis(P, 2, z0 - Re), cz1 = cell_axis(P, 2, z1 + Re);
     const int ny = cy1 - cy0 + 1, nz = cz1 - cz0 + 1;
     const int nrows = ny * nz;
-    // rows centre-out along z and y (middle of each range first, then
-    // alternately below and above): the nearest candidates come first, so
-    // that a k-smallest list fills early and later, farther candidates
-    // seldom change it (visiting order never changes a result)
-    auto centre_out = [](int i, int L) { return L / 2 + ((i & 1) ? -((i + 1) >> 1) : (i >> 1)); };
     for (int rb = 0; rb < nrows; rb += kWave) {
         const int r = rb + l;
         uint32_t st = 0, len = 0;
@@ -335,6 +339,93 @@ __device__ __forceinline__ void run_tile(const GridPlan& P, const PairTask& T, b
     });
     if (m > 0) scan(m);
     (void)l;
+}
+
+// One target per lane for sparse neighbours: each lane walks the cell rows
+// within R of its own target (rows trimmed to the x-range the sphere
+// reaches, as in enumerate_box) and reads the records one by one, kLaneU of
+// them in flight; no staging, and no lane waits on a shared candidate list.
+// Same results as run_tile (same candidate set, order-free updates).
+constexpr int kLaneU = 4;
+
+template <int FLAGS, int KMAX>
+__device__ __forceinline__ void run_lane(const GridPlan& P, const PairTask& T, bool valid, float px, float py,
+                                         float pz, uint32_t i, float Rk, TopK<KMAX>& top, uint32_t& hits) {
+    constexpr bool RDF = (FLAGS & (kRdfLds | kRdfGlobal)) != 0;
+    constexpr bool LDS_HIST = (FLAGS & kRdfLds) != 0;
+    constexpr bool SELF = (FLAGS & kSelf) != 0;
+#pragma unroll
+    for (int m = 0; m < (KMAX > 0 ? KMAX : 1); ++m) top.key[m] = ~0ull;
+    const bool fin = valid && isfinite(px) && isfinite(py) && isfinite(pz);
+    const float rk2 = Rk * Rk;
+    float R = 0.0f;
+    if (RDF) R = T.r_enum;
+    if (KMAX > 0) R = fmaxf(R, Rk * 1.000001f);
+    const float Re = R + P.eps;
+    const float R2 = Re * Re;
+    const int cy0 = cell_axis(P, 1, py - Re), cy1 = cell_axis(P, 1, py + Re);
+    const int cz0 = cell_axis(P, 2, pz - Re), cz1 = cell_axis(P, 2, pz + Re);
+    const int ny = cy1 - cy0 + 1, nz = cz1 - cz0 + 1;
+    const int nrows = fin ? ny * nz : 0;
+    int r = 0;                     // next row of this lane
+    uint32_t j = 0, j1 = 0;        // records left in the current row
+    for (;;) {
+        // advance to the next row with records (rows beyond R are empty)
+        while (j >= j1 && r < nrows) {
+            const int cz = cz0 + centre_out(r / ny, nz), cy = cy0 + centre_out(r % ny, ny);
+            ++r;
+            const float ya = P.lo[1] + (float)cy * P.h - P.eps, yb = P.lo[1] + (float)(cy + 1) * P.h + P.eps;
+            const float za = P.lo[2] + (float)cz * P.h - P.eps, zb = P.lo[2] + (float)(cz + 1) * P.h + P.eps;
+            const float dy = fmaxf(0.0f, fmaxf(ya - py, py - yb));
+            const float dz = fmaxf(0.0f, fmaxf(za - pz, pz - zb));
+            const float d2r = dy * dy + dz * dz;
+            if (d2r <= R2) {
+                const float ex = sqrtf(R2 - d2r) + P.eps;
+                const int cx0 = cell_axis(P, 0, px - ex), cx1 = cell_axis(P, 0, px + ex);
+                const uint32_t base = ((uint32_t)cz * (uint32_t)P.dim[1] + (uint32_t)cy) * (uint32_t)P.dim[0];
+                j = T.cell_start[base + (uint32_t)cx0];
+                j1 = T.cell_start[base + (uint32_t)cx1 + 1u];
+            }
+        }
+        if (j >= j1) break;
+        float4 c[kLaneU];
+#pragma unroll
+        for (int u = 0; u < kLaneU; ++u) c[u] = T.bpos[j + (uint32_t)u < j1 ? j + (uint32_t)u : j];
+#pragma unroll
+        for (int u = 0; u < kLaneU; ++u) {
+            if (j + (uint32_t)u >= j1) break;
+            const float dx = c[u].x - px, dy = c[u].y - py, dz = c[u].z - pz;
+            const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            const uint32_t cj = __builtin_bit_cast(uint32_t, c[u].w);
+            const bool me = !SELF || cj != i;
+            if (RDF && me && d2 < T.thr2) {
+                const float t = __builtin_amdgcn_sqrtf(d2) * T.inv_w;
+                int b = (int)t;
+                const float fr = t - (float)b;
+                if (__builtin_expect(fr < T.lo_b || fr > T.hi_b, 0))
+                    b = exact_bin(exact_D2(px, py, pz, c[u].x, c[u].y, c[u].z), T.E2, T.n_bins, T.inv_w64);
+                if (b < T.n_bins) {
+                    if (LDS_HIST) atomicAdd(&T.hist_l[b], 1u);
+                    else atomicAdd((unsigned long long*)&T.hist_g[b], 1ull);
+                    ++hits;
+                }
+            }
+            if (KMAX > 0) {
+                const uint64_t key = ((uint64_t)__builtin_bit_cast(uint32_t, d2) << 32) | (uint64_t)cj;
+                if (me && d2 <= rk2 && key < top.key[KMAX - 1]) {
+                    uint64_t x = key;
+#pragma unroll
+                    for (int q = 0; q < KMAX; ++q) {
+                        const uint64_t lo = x < top.key[q] ? x : top.key[q];
+                        const uint64_t hi = x < top.key[q] ? top.key[q] : x;
+                        top.key[q] = lo;
+                        x = hi;
+                    }
+                }
+            }
+        }
+        j += kLaneU;
+    }
 }
 
 // As run_tile, for callers that need only each lane's k-th neighbour key
