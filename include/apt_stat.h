@@ -235,11 +235,16 @@ typedef struct {
 apt_status apt_set_tuning(const apt_tuning* t);
 apt_status apt_get_tuning(apt_tuning* t);
 
-/* Tracing: while enabled (on != 0), every call records HIP events on its
- * stream around its stages; apt_trace_read waits for the recorded events,
- * returns the summed time (ms) and number of launches of one stage
- * ("binning" = bounding box to sorted SoA, "pair" = the pair kernel) and
- * forgets that stage's records.  Host only; off by default. */
+/* Tracing: while enabled, every call records HIP events on its stream
+ * around its stages (on = 1) or around the one-target-per-wavefront pair
+ * kernel only (on = 2: fewer events, each of which the GPU executes as a
+ * command of its own); on = 0 disables it, other values return APT_E_ARG.
+ * apt_trace_read waits for the recorded events, returns the summed time
+ * (ms) and number of launches of one stage ("binning" = bounding box to
+ * sorted records, "pair" = the pair kernel, "tile" = the 64-target kernel,
+ * "permute" and "partition" = the batched replicates' label permutation and
+ * class split) and forgets that stage's records.  Host only; off by
+ * default. */
 apt_status apt_trace_enable(int32_t on);
 apt_status apt_trace_read(const char* stage, double* ms_total, int64_t* launches);
 

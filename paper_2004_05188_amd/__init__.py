@@ -183,9 +183,10 @@ def get_tuning() -> dict:
             "tile_occ": t.tile_occ}
 
 
-def trace_enable(on: bool = True):
-    """Record HIP events around the stages of every following call."""
-    _check(lib().apt_trace_enable(1 if on else 0), "apt_trace_enable")
+def trace_enable(on: bool = True, pair_only: bool = False):
+    """Record HIP events around the stages of every following call (only
+    around the pair kernel with pair_only)."""
+    _check(lib().apt_trace_enable((2 if pair_only else 1) if on else 0), "apt_trace_enable")
 
 
 def trace_read(stage: str):

@@ -1,10 +1,13 @@
 // Host side of the C ABI: argument checks, workspace layout and the launch
 // sequence of each entry point.  Nothing here allocates device memory.
 #include <math.h>
+#include <string.h>
 
 #include <atomic>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "apt_batched.hpp"
@@ -55,25 +58,54 @@ static apt_tuning tuning() {
 struct TraceRec {
     std::string stage;
     hipEvent_t a, b;
+    int dev;
 };
 static std::mutex g_trace_mu;
 static std::vector<TraceRec> g_trace;
 static std::atomic<int> g_trace_on{0};
+// events are reused (creating two per stage per call costs host time that
+// a fast call cannot hide); one free list per device
+static std::map<int, std::vector<hipEvent_t>> g_event_pool;   // guarded by g_trace_mu
+
+static hipEvent_t take_event(int dev) {
+    {
+        std::lock_guard<std::mutex> g(g_trace_mu);
+        auto& v = g_event_pool[dev];
+        if (!v.empty()) {
+            hipEvent_t e = v.back();
+            v.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
 
 struct TraceSpan {
     hipEvent_t a = nullptr, b = nullptr;
     const char* stage;
     hipStream_t st;
+    int dev = 0;
     TraceSpan(const char* s, hipStream_t stream) : stage(s), st(stream) {
-        if (!g_trace_on.load()) return;
-        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { a = b = nullptr; return; }
+        const int on = g_trace_on.load();
+        if (!on || (on == 2 && strcmp(s, "pair") != 0)) return;
+        if (hipGetDevice(&dev) != hipSuccess) return;
+        a = take_event(dev);
+        b = take_event(dev);
+        if (!a || !b) {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+            a = b = nullptr;
+            return;
+        }
         (void)hipEventRecord(a, st);
     }
     ~TraceSpan() {
         if (!a) return;
         (void)hipEventRecord(b, st);
         std::lock_guard<std::mutex> g(g_trace_mu);
-        g_trace.push_back(TraceRec{stage, a, b});
+        g_trace.push_back(TraceRec{stage, a, b, dev});
     }
 };
 
@@ -81,11 +113,26 @@ struct TraceSpan {
 // fit on the device at once, so that the static deal of targets runs in a
 // single round (a second, partly filled round would leave CUs idle).  A
 // multiple of the CU count, hence of the XCD count.
+// The occupancy query is remembered per (device, kernel, LDS bytes): it
+// costs host time on every call otherwise.
 template <class K>
 static int resident_grid(K kern, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void*, size_t>, int> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    const auto key = std::make_tuple(dev, reinterpret_cast<const void*>(kern), lds);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kBlock, lds) != hipSuccess || nb < 1) nb = 2;
-    return device_info().cus * nb;
+    const int grid = device_info().cus * nb;
+    std::lock_guard<std::mutex> g(mu);
+    cache[key] = grid;
+    return grid;
 }
 
 // LDS one workgroup may take
@@ -893,7 +940,8 @@ apt_status apt_get_tuning(apt_tuning* t) {
 }
 
 apt_status apt_trace_enable(int32_t on) {
-    g_trace_on.store(on ? 1 : 0);
+    if (on < 0 || on > 2) return fail(APT_E_ARG, "apt_trace_enable: on must be 0, 1 or 2");
+    g_trace_on.store(on);
     return APT_OK;
 }
 
@@ -913,8 +961,14 @@ apt_status apt_trace_read(const char* stage, double* ms_total, int64_t* launches
         if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess)
             s = fail(APT_E_HIP, "apt_trace_read: event wait failed");
         tot += ms;
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
+    }
+    {
+        // back to the free lists (both events have completed)
+        std::lock_guard<std::mutex> g(g_trace_mu);
+        for (auto& r : mine) {
+            g_event_pool[r.dev].push_back(r.a);
+            g_event_pool[r.dev].push_back(r.b);
+        }
     }
     *ms_total = tot;
     *launches = (int64_t)mine.size();

@@ -131,3 +131,16 @@ def test_tuning_round_trip_and_validation(aptstat):
         assert aptstat.get_tuning() == {"tile_policy": 0, "cell_occ": 4.0, "h_min_frac": 0.5, "tile_occ": 1.0}
     finally:
         aptstat.set_tuning()
+
+
+def test_trace_enable_modes(aptstat):
+    """0 off, 1 every stage, 2 the pair kernel only; anything else is refused."""
+    L = aptstat.lib()
+    try:
+        for on in (0, 1, 2):
+            assert L.apt_trace_enable(on) == 0
+        for bad in (-1, 3, 7):
+            assert L.apt_trace_enable(bad) == -1
+            assert "apt_trace_enable" in _err(aptstat)
+    finally:
+        assert L.apt_trace_enable(0) == 0
