@@ -183,7 +183,7 @@ apt_status apt_rdf_batched(const apt_cloud* cloud, const apt_query* pairs, int32
  *   w_b(D) = Phi((e_{b+1} - D) / sigma) - Phi((e_b - D) / sigma),
  * with e_b = b * r_max / n_bins and Phi the standard normal distribution
  * function (evaluated from the tail that does not cancel).
- *   sigma        > 0, at most (1021 bin widths) / 12
+ *   sigma        > 0, at most (1020 bin widths) / 12
  *   z_scale      device double [1] (s), or NULL for s = 1
  *   h            [bins.n_bins] FP64, device, overwritten
  * bins.n_bins <= 4096.  Arithmetic after an FP32 culling test is FP64; the

@@ -836,8 +836,8 @@ static apt_status run_smooth(bool bwd, const apt_cloud* cl, apt_query q, apt_bin
     const double cut = (double)rb.r_max + 6.0 * sig;
     const double width = (double)rb.r_max / rb.n_bins;
     const double mw = floor(2.0 * w6 / width) + 3.0;     // most bins one window meets, with a margin
-    if (!(mw <= (double)kSmoothTerms))
-        return fail(APT_E_UNSUPPORTED, "sigma spans more than 1021 bins (12 sigma / bin width)");
+    if (!(mw + 1.0 <= (double)kSmoothTerms))             // its edges are buffered
+        return fail(APT_E_UNSUPPORTED, "sigma spans more than 1020 bins (12 sigma / bin width)");
     if (!((float)(cut * (1.0 + 2e-5)) < 1e30f)) return fail(APT_E_ARG, "r_max + 6 sigma is too large");
     SmoothWs w = carve_smooth(ws, cl->n);
     if ((s = check_ws(ws, ws_bytes, w.bytes)) != APT_OK) return s;
@@ -878,7 +878,7 @@ static apt_status run_smooth(bool bwd, const apt_cloud* cl, apt_query q, apt_bin
     sa.d_srf = q.d_srf;
     sa.uni = bwd ? 1 : 0;
     sa.n_bins = rb.n_bins;
-    sa.hcap = (int)fmin(64.0, floor((double)kSmoothTerms / mw));
+    sa.hcap = (int)fmin(64.0, floor((double)kSmoothTerms / (mw + 1.0)));
     sa.r_pre = r_pre;
     sa.sigma = sig;
     sa.cut = cut;
@@ -895,7 +895,8 @@ static apt_status run_smooth(bool bwd, const apt_cloud* cl, apt_query q, apt_bin
         TraceSpan span("smooth", st);
         hipLaunchKernelGGL(k_smooth_fwd, dim3(W), dim3(kWave), smooth_lds_bytes(true, rb.n_bins), st, sa);
         SmoothReduceArgs ra{w.part, W, rb.n_bins, h};
-        hipLaunchKernelGGL(k_smooth_reduce, dim3((rb.n_bins + 255) / 256), dim3(256), 0, st, ra);
+        hipLaunchKernelGGL(k_smooth_reduce, dim3((rb.n_bins + kWave - 1) / kWave), dim3(kWave * kReduceGroups), 0,
+                           st, ra);
     } else {
         sa.W = kSmoothWaves;
         TraceSpan span("smooth", st);
@@ -903,7 +904,7 @@ static apt_status run_smooth(bool bwd, const apt_cloud* cl, apt_query q, apt_bin
                            sa);
         if (grad_s) {
             SmoothReduceArgs ra{w.part, kSmoothWaves, 1, grad_s};
-            hipLaunchKernelGGL(k_smooth_reduce, dim3(1), dim3(64), 0, st, ra);
+            hipLaunchKernelGGL(k_smooth_reduce, dim3(1), dim3(kWave * kReduceGroups), 0, st, ra);
         }
     }
     return hip_check("smoothed RDF launch");

@@ -11,10 +11,12 @@
 //
 // Both kernels assign ions to wavefronts statically and sum in a fixed
 // order, so results are reproducible bit for bit:
-//  * forward: one wavefront per target; its pairs are collected, then each
-//    (pair, bin) term is computed on its own lane and added pair by pair to
+//  * forward: one wavefront per target; its pairs are collected, then the
+//    Gaussian tail at each (pair, bin edge) is computed on its own lane, and
+//    the bin terms (differences of adjacent edges) are added pair by pair to
 //    the wavefront's FP64 LDS histogram; a reduction kernel sums the
-//    per-wavefront rows in wavefront order;
+//    per-wavefront rows in a fixed order (consecutive row ranges in row
+//    order, then the range sums in range order);
 //  * adjoint: pair lists are recomputed, not stored.  Every ion that takes
 //    part in a pair (target or neighbour) gathers the derivative of L with
 //    respect to its own position over its pairs in both roles, so no two
@@ -102,43 +104,42 @@ __device__ __forceinline__ void smooth_body(const SmoothArgs& a) {
 
         auto flush = [&]() {
             wave_sync();
-            int b0 = 0, mh = 0;
+            // per pair: its window's bins b0 .. b0 + mh - 1 and their mh + 1
+            // edges; the Gaussian tail (forward) or density (adjoint) is
+            // evaluated once per edge, on its own lane, and shared by the
+            // two bins that meet there
+            int b0 = 0, mh = 0, me = 0;
             if (l < nh) {
                 int b1;
                 smooth_window(a, s_D[l], &b0, &b1);
                 mh = b1 - b0 + 1;
+                me = mh + 1;
             }
-            const uint32_t inc = wave_incl_scan((uint32_t)mh);
+            const uint32_t inc = wave_incl_scan((uint32_t)me);
             const uint32_t tot = readlane(inc, kWave - 1);
-            const uint32_t off = inc - (uint32_t)mh;
+            const uint32_t off = inc - (uint32_t)me;
             for (uint32_t c0 = 0; c0 < tot; c0 += kWave) {
                 const uint32_t v = c0 + (uint32_t)l;
-                int h = -1, bv = 0;
+                int h = -1, ev = 0;
                 const int r0 = __popcll(__ballot(inc <= c0));   // first pair ending after c0
                 for (int rr = r0; rr < nh; ++rr) {
                     const uint32_t o = readlane(off, rr);
                     if (o >= c0 + kWave) break;
-                    const uint32_t ln = (uint32_t)readlane(mh, rr);
+                    const uint32_t ln = (uint32_t)readlane(me, rr);
                     if (v >= o && v < o + ln) {
                         h = rr;
-                        bv = readlane(b0, rr) + (int)(v - o);
+                        ev = readlane(b0, rr) + (int)(v - o);
                     }
                 }
                 if (h >= 0) {
-                    const double Dh = s_D[h];
-                    const double tlo = (a.E[bv] - Dh) / a.sigma;
-                    const double thi = (a.E[bv + 1] - Dh) / a.sigma;
-                    double term;
+                    const double t = (a.E[ev] - s_D[h]) / a.sigma;
                     if (!BWD) {
-                        const double vlo = 0.5 * erfc(fabs(tlo) / M_SQRT2);
-                        const double vhi = 0.5 * erfc(fabs(thi) / M_SQRT2);
-                        term = tlo >= 0.0 ? vlo - vhi : (thi <= 0.0 ? vhi - vlo : (1.0 - vhi) - vlo);
+                        // the tail 0.5 erfc(|t| / sqrt 2) > 0, negated when t < 0
+                        const double u = 0.5 * erfc(fabs(t) / M_SQRT2);
+                        s_term[v] = t >= 0.0 ? u : -u;
                     } else {
-                        const double plo = exp(-0.5 * tlo * tlo) / sqrt(2.0 * M_PI);
-                        const double phi = exp(-0.5 * thi * thi) / sqrt(2.0 * M_PI);
-                        term = a.grad_h[bv] * (-(phi - plo) / a.sigma);
+                        s_term[v] = exp(-0.5 * t * t) / sqrt(2.0 * M_PI);
                     }
-                    s_term[v] = term;
                 }
             }
             wave_sync();
@@ -147,12 +148,22 @@ __device__ __forceinline__ void smooth_body(const SmoothArgs& a) {
                 for (int h = 0; h < nh; ++h) {
                     const uint32_t o = readlane(off, h);
                     const int ln = readlane(mh, h), bb = readlane(b0, h);
-                    for (int q = l; q < ln; q += kWave) s_hist[bb + q] += s_term[o + q];
+                    for (int q = l; q < ln; q += kWave) {
+                        // bin mass from the tails at its edges: both edges above
+                        // D, both below, or D inside the bin (an edge exactly at
+                        // D falls to the last case with the same value)
+                        const double slo = s_term[o + q], shi = s_term[o + q + 1];
+                        const double vlo = fabs(slo), vhi = fabs(shi);
+                        s_hist[bb + q] += slo > 0.0 ? vlo - vhi : (shi < 0.0 ? vhi - vlo : (1.0 - vhi) - vlo);
+                    }
                     wave_sync();
                 }
             } else if (l < nh) {
                 double g = 0.0;
-                for (int q = 0; q < mh; ++q) g += s_term[off + (uint32_t)q];
+                for (int q = 0; q < mh; ++q) {
+                    const double plo = s_term[off + (uint32_t)q], phi = s_term[off + (uint32_t)q + 1];
+                    g += a.grad_h[b0 + q] * (-(phi - plo) / a.sigma);
+                }
                 const double D = s_D[l];
                 if (D != 0.0) {
                     const int mul = s_mul[l];
@@ -248,12 +259,34 @@ __device__ __forceinline__ void smooth_body(const SmoothArgs& a) {
 __global__ __launch_bounds__(kWave) void k_smooth_fwd(SmoothArgs a) { smooth_body<false>(a); }
 __global__ __launch_bounds__(kWave) void k_smooth_bwd(SmoothArgs a) { smooth_body<true>(a); }
 
-// out[b] = sum over w of part[w][b], in wavefront order.
-__global__ void k_smooth_reduce(SmoothReduceArgs a) {
-    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < a.n_bins; b += gridDim.x * blockDim.x) {
-        double acc = 0.0;
-        for (int w = 0; w < a.W; ++w) acc += a.part[(size_t)w * (size_t)a.n_bins + (size_t)b];
-        a.out[b] = acc;
+// out[b] = sum over the W per-wavefront rows of part[w][b], in a fixed
+// order: kReduceGroups consecutive row ranges, each summed in row order,
+// then the range sums in range order (the same result on every run).
+// Workgroup: 64 bins x kReduceGroups ranges; grid: ceil(n_bins / 64).
+__global__ __launch_bounds__(kWave * kReduceGroups) void k_smooth_reduce(SmoothReduceArgs a) {
+    __shared__ double s_p[kReduceGroups][kWave];
+    const int tb = threadIdx.x % kWave, g = threadIdx.x / kWave;
+    const int b = blockIdx.x * kWave + tb;
+    const int w0 = (int)((int64_t)a.W * g / kReduceGroups), w1 = (int)((int64_t)a.W * (g + 1) / kReduceGroups);
+    double acc = 0.0;
+    if (b < a.n_bins) {
+        const double* col = a.part + (size_t)b;
+        int w = w0;
+        for (; w + 8 <= w1; w += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = col[(size_t)(w + u) * (size_t)a.n_bins];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u];
+        }
+        for (; w < w1; ++w) acc += col[(size_t)w * (size_t)a.n_bins];
+    }
+    s_p[g][tb] = acc;
+    __syncthreads();
+    if (g == 0 && b < a.n_bins) {
+        double t = 0.0;
+        for (int q = 0; q < kReduceGroups; ++q) t += s_p[q][tb];
+        a.out[b] = t;
     }
 }
 

@@ -9,9 +9,10 @@
 
 namespace apt {
 
-constexpr int kSmoothTerms = 1024;     // bin terms buffered per wavefront
+constexpr int kSmoothTerms = 1024;     // window edge values buffered per wavefront
 constexpr int kSmoothMaxBins = 4096;   // forward histogram held in LDS
-constexpr int kSmoothWaves = 2048;     // adjoint: wavefronts of the launch
+constexpr int kSmoothWaves = 8192;     // wavefronts of the launch (forward: at most this many)
+constexpr int kReduceGroups = 16;      // row ranges of the fixed-order reduction
 
 struct SmoothArgs {
     const GridPlan* plan;
@@ -26,7 +27,7 @@ struct SmoothArgs {
     float d_srf;
     int32_t uni;                 // adjoint: outer ions and candidates are the union of both roles
     int32_t n_bins;
-    int32_t hcap;                // pairs buffered per flush (hcap * widest window <= kSmoothTerms)
+    int32_t hcap;                // pairs buffered per flush (hcap * (widest window + 1) <= kSmoothTerms)
     int32_t W;                   // wavefronts of the launch (static assignment of outer ions)
     float r_pre;                 // FP32 culling radius (covers the FP64 cut)
     double sigma;

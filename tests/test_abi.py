@@ -144,3 +144,20 @@ def test_trace_enable_modes(aptstat):
             assert "apt_trace_enable" in _err(aptstat)
     finally:
         assert L.apt_trace_enable(0) == 0
+
+
+def test_smooth_window_limit(aptstat):
+    """sigma is limited by the edges one window buffers: 12 sigma may span
+    up to 1020 bin widths; beyond, APT_E_UNSUPPORTED before any GPU work."""
+    L = aptstat.lib()
+    q = aptstat._query(1, 1, 0.0)
+    bins = aptstat._bins(2.0, 200)                 # bin width 0.01 nm
+    p = ctypes.c_void_p(0x5000)
+    ws, big = ctypes.c_void_p(0x100000), 1 << 40
+    # 12 sigma = 1030 widths: refused
+    assert L.apt_rdf_smooth_fwd(_cloud(aptstat), q, bins, ctypes.c_float(0.01 * 1030 / 12), None, p, p, ws, big,
+                                None) == -3
+    assert "1020 bins" in _err(aptstat)
+    # sigma <= 0 and NaN: invalid
+    for bad in (0.0, -1.0, math.nan):
+        assert L.apt_rdf_smooth_fwd(_cloud(aptstat), q, bins, ctypes.c_float(bad), None, p, p, ws, big, None) == -1
