@@ -94,6 +94,10 @@ PROBLEMS = [
     ("sc_sc", 120_000, 16.0, 11, (SC, SC, False, 0.0), 2.0, 200, 0.02),
     ("sc_any_dbnd", 30_000, 10.0, 12, (SC, ANY, True, 1.0), 2.0, 200, 0.02),
     ("al_sc_coarse", 30_000, 10.0, 13, (AL, SC, True, 0.5), 1.5, 37, 0.045),
+    # windows wider than a wavefront (120 bins), histogram in registers
+    ("sc_sc_wide", 30_000, 10.0, 14, (SC, SC, False, 0.0), 2.0, 200, 0.1),
+    # more than 256 bins: histogram in LDS, windows of 180 bins
+    ("sc_sc_fine_lds", 30_000, 10.0, 15, (SC, SC, False, 0.0), 2.0, 1000, 0.03),
 ]
 
 
