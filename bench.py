@@ -287,7 +287,7 @@ def main():
 
         csrc = os.path.join(ROOT, "paper_2004_05188_amd", "csrc")
         blob = b"".join(open(os.path.join(csrc, f), "rb").read()
-                        for f in ("apt_pair.hip", "apt_pair.hpp", "apt_internal.hpp"))
+                        for f in ("apt_pair.hip", "apt_pair.hpp", "apt_pairdev.hpp", "apt_internal.hpp"))
         sha = hashlib.sha256(blob).hexdigest()[:16]
         if sha == PAIR_TRAFFIC[args.workload][1]:
             traffic = PAIR_TRAFFIC[args.workload][0]

@@ -10,10 +10,26 @@ namespace apt {
 __device__ __forceinline__ uint32_t f2u(float f) { return __builtin_bit_cast(uint32_t, f); }
 __device__ __forceinline__ float u2f(uint32_t u) { return __builtin_bit_cast(float, u); }
 
-// Ascending bitonic sort of buf[0..c) (padded to a power of two >= 64 with
-// all-ones keys) by one wavefront; c <= kKnnCap.
+// Ascending sort of buf[0..c) by one wavefront; c <= kKnnCap.  Up to 64
+// keys: each lane takes one key and counts the smaller ones (equal ones by
+// position), broadcast lane by lane (no LDS round trips); beyond: a bitonic
+// network over buf padded to a power of two with all-ones keys.
 __device__ inline void wave_sort_keys(uint64_t* buf, int c) {
     const int l = lane_id();
+    if (c <= kWave) {
+        wave_sync();
+        const uint64_t mine = l < c ? buf[l] : ~0ull;
+        const uint32_t lo = (uint32_t)mine, hi = (uint32_t)(mine >> 32);
+        int rank = 0;
+        for (int j = 0; j < c; ++j) {
+            const uint64_t kj = ((uint64_t)readlane(hi, j) << 32) | (uint64_t)readlane(lo, j);
+            rank += (kj < mine || (kj == mine && j < l)) ? 1 : 0;
+        }
+        wave_sync();
+        if (l < c) buf[rank] = mine;
+        wave_sync();
+        return;
+    }
     int N = kWave;
     while (N < c) N <<= 1;
     for (int i = c + l; i < N; i += kWave) buf[i] = ~0ull;
