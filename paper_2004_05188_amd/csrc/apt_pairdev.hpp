@@ -59,10 +59,11 @@ __device__ inline void wave_sort_keys(uint64_t* buf, int c) {
 constexpr int kUnroll = 4;
 
 // The i-th of L rows centre-out (middle of the range first, then
-// alternately below and above; a permutation of [0, L)): the nearest
-// candidates come first, so that a k-smallest list fills early and later,
-// farther candidates seldom change it (the visiting order never changes a
-// result).
+// alternately below and above; a permutation of [0, L)): enumerations that
+// feed a k-smallest list visit rows in this order, so that the list fills
+// with the nearest candidates early and later, farther candidates seldom
+// change it; others keep raster order, which walks memory in sequence (the
+// visiting order never changes a result).
 __device__ __forceinline__ int centre_out(int i, int L) {
     return L / 2 + ((i & 1) ? -((i + 1) >> 1) : (i >> 1));
 }
@@ -70,7 +71,7 @@ __device__ __forceinline__ int centre_out(int i, int L) {
 template <class F>
 __device__ __forceinline__ void enumerate_box(const GridPlan& P, const uint32_t* __restrict__ cell_start,
                                               const float4* __restrict__ bpos, float x0, float y0, float z0,
-                                              float x1, float y1, float z1, float R, F&& f) {
+                                              float x1, float y1, float z1, float R, F&& f, bool centre = false) {
     // neighbours within R of the box [x0,x1] x [y0,y1] x [z0,z1]
     const int l = lane_id();
     const float Re = R + P.eps;
@@ -83,7 +84,8 @@ __device__ __forceinline__ void enumerate_box(const GridPlan& P, const uint32_t*
         const int r = rb + l;
         uint32_t st = 0, len = 0;
         if (r < nrows) {
-            const int cz = cz0 + centre_out(r / ny, nz), cy = cy0 + centre_out(r % ny, ny);
+            const int iz = r / ny, iy = r % ny;
+            const int cz = cz0 + (centre ? centre_out(iz, nz) : iz), cy = cy0 + (centre ? centre_out(iy, ny) : iy);
             const float ya = P.lo[1] + (float)cy * P.h - P.eps, yb = P.lo[1] + (float)(cy + 1) * P.h + P.eps;
             const float za = P.lo[2] + (float)cz * P.h - P.eps, zb = P.lo[2] + (float)(cz + 1) * P.h + P.eps;
             const float dy = fmaxf(0.0f, fmaxf(ya - y1, y0 - yb));
@@ -138,8 +140,8 @@ __device__ __forceinline__ void enumerate_box(const GridPlan& P, const uint32_t*
 template <class F>
 __device__ __forceinline__ void enumerate(const GridPlan& P, const uint32_t* __restrict__ cell_start,
                                           const float4* __restrict__ bpos, float px, float py, float pz,
-                                          float R, F&& f) {
-    enumerate_box(P, cell_start, bpos, px, py, pz, px, py, pz, R, f);
+                                          float R, F&& f, bool centre = false) {
+    enumerate_box(P, cell_start, bpos, px, py, pz, px, py, pz, R, f, centre);
 }
 
 // Everything one target needs besides its position and index.
@@ -231,17 +233,17 @@ __device__ __forceinline__ int run_target(const GridPlan& P, const PairTask& T, 
                       [&](bool v, float4 c) { rdf_one(v, c, dist2(c)); });
             if (KNN)
                 enumerate(P, T.cell_start, T.bpos, px, py, pz, rk * 1.000001f,
-                          [&](bool v, float4 c) { knn_one(v, c, dist2(c)); });
+                          [&](bool v, float4 c) { knn_one(v, c, dist2(c)); }, true);
         } else if (RDF) {
             // the first kNN radius covers r_max: one enumeration for both
             enumerate(P, T.cell_start, T.bpos, px, py, pz, rk * 1.000001f, [&](bool v, float4 c) {
                 const float d2 = dist2(c);
                 rdf_one(v, c, d2);
                 knn_one(v, c, d2);
-            });
+            }, true);
         } else if (KNN) {
             enumerate(P, T.cell_start, T.bpos, px, py, pz, rk * 1.000001f,
-                      [&](bool v, float4 c) { knn_one(v, c, dist2(c)); });
+                      [&](bool v, float4 c) { knn_one(v, c, dist2(c)); }, true);
         }
         if (KNN) {
             // grow the radius until k keys are certain (or everything was seen)
@@ -252,7 +254,7 @@ __device__ __forceinline__ int run_target(const GridPlan& P, const PairTask& T, 
                 rk = fminf(rk * g, fminf(T.rknn, P.r_all));
                 rk2 = rk >= T.rknn ? T.rknn2 : rk * rk;
                 enumerate(P, T.cell_start, T.bpos, px, py, pz, rk * 1.000001f,
-                          [&](bool v, float4 c) { knn_one(v, c, dist2(c)); });
+                          [&](bool v, float4 c) { knn_one(v, c, dist2(c)); }, true);
             }
         }
     }
@@ -352,7 +354,7 @@ __device__ __forceinline__ void run_tile(const GridPlan& P, const PairTask& T, b
         }
         if (v) stage[m + __popcll(bal & lanemask_lt())] = c;
         m += nn;
-    });
+    }, KMAX > 0);
     if (m > 0) scan(m);
     (void)l;
 }
@@ -527,7 +529,7 @@ __device__ __forceinline__ uint64_t run_tile_kth(const GridPlan& P, const PairTa
             m += nn;
         };
     };
-    enumerate_box(P, T.cell_start, T.bpos, x0, y0, z0, x1, y1, z1, R, stage_one(scan));
+    enumerate_box(P, T.cell_start, T.bpos, x0, y0, z0, x1, y1, z1, R, stage_one(scan), true);
     if (m > 0) scan(m);
 
     // the k-th distance and how many of the k nearest lie strictly nearer
