@@ -458,22 +458,19 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
     KeyArgs kt{w.plan, cl->xyz, w.tid, zscale, 1, 1, w.K[0], w.V[0]};
     hipLaunchKernelGGL(k_keys, dim3(Gk), dim3(kBlock), 0, st, kt);
     sort(1);
-    OrderArgs oa{w.plan, cl->xyz, w.tid, {w.V[0], w.V[1]}, w.t_rank, w.t_id, w.tx, w.ty, w.tz};
+    // occupied cells (distinct sorted keys) feed the kNN radii
+    const bool occ = pp.k > 0 && !zscale;
+    OrderArgs oa{w.plan, cl->xyz, w.tid, {w.V[0], w.V[1]}, w.t_rank, w.t_id, w.tx, w.ty, w.tz,
+                 {w.K[0], w.K[1]}, occ ? w.strag_count + 1 : nullptr};
     hipLaunchKernelGGL(k_take_order, dim3(Gk), dim3(kBlock), 0, st, oa);
-    if (pp.k > 0 && !zscale)   // occupied target cells (the sorted keys are overwritten next)
-        hipLaunchKernelGGL(k_target_cells, dim3(cus * 2), dim3(kBlock), 0, st, w.plan, w.K[0], w.K[1],
-                           w.strag_count + 1);
     // neighbours in cell order
     KeyArgs kb{w.plan, cl->xyz, all_b ? nullptr : w.bsel, zscale, 0, 0, w.K[0], w.V[0]};
     hipLaunchKernelGGL(k_keys, dim3(Gk), dim3(kBlock), 0, st, kb);
     sort(0);
-    GatherArgs ga{w.plan, cl->xyz, zscale, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.bpos, w.cell_start};
+    GatherArgs ga{w.plan, cl->xyz, zscale, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.bpos, w.cell_start,
+                  occ ? w.strag_count + 2 : nullptr};
     hipLaunchKernelGGL(k_gather, dim3(Gk), dim3(kBlock), 0, st, ga);
-    if (pp.k > 0 && !zscale) {
-        hipLaunchKernelGGL(k_neighbour_cells, dim3(cus * 2), dim3(kBlock), 0, st, w.plan, w.cell_start,
-                           w.strag_count + 1);
-        hipLaunchKernelGGL(k_refine_radii, dim3(1), dim3(64), 0, st, w.plan, w.strag_count + 1, pp.k);
-    }
+    if (occ) hipLaunchKernelGGL(k_refine_radii, dim3(1), dim3(64), 0, st, w.plan, w.strag_count + 1, pp.k);
     return hip_check("binning launch");
 }
 
@@ -692,7 +689,8 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
             hipLaunchKernelGGL(k_rs_scan, dim3(256), dim3(kBlock), 0, st, sa);
             hipLaunchKernelGGL(k_rs_downsweep, dim3(kSortBlocks), dim3(kBlock), 0, st, sa);
         }
-        GatherArgs ga{pw.plan, cl->xyz, nullptr, {pw.K[0], pw.K[1]}, {pw.V[0], pw.V[1]}, pw.bpos, pw.cell_start};
+        GatherArgs ga{pw.plan, cl->xyz, nullptr, {pw.K[0], pw.K[1]}, {pw.V[0], pw.V[1]}, pw.bpos, pw.cell_start,
+                      nullptr};
         hipLaunchKernelGGL(k_gather, dim3(Gk), dim3(kBlock), 0, st, ga);
     }
 

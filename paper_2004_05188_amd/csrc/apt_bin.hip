@@ -546,7 +546,9 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortArgs a) {
 __global__ __launch_bounds__(kBlock) void k_take_order(OrderArgs a) {
     const GridPlan P = *a.plan;
     const uint32_t* __restrict__ v = a.vals[P.passes_T & 1];
+    const uint32_t* __restrict__ sk = a.keys[P.passes_T & 1];   // sorted target keys
     const uint64_t nT = P.nT, stride = (uint64_t)gridDim.x * kBlock;
+    uint32_t distinct = 0;
     // kGatherItems targets per thread in flight: the position reads are random
     for (uint64_t t0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t0 < nT; t0 += stride * kGatherItems) {
         uint32_t rank[kGatherItems], id[kGatherItems];
@@ -575,8 +577,13 @@ __global__ __launch_bounds__(kBlock) void k_take_order(OrderArgs a) {
                 a.tx[t] = x[u];
                 a.ty[t] = y[u];
                 a.tz[t] = z[u];
+                if (a.distinct) distinct += (t == 0 || sk[t] != sk[t - 1]) ? 1u : 0u;
             }
         }
+    }
+    if (a.distinct) {
+        distinct = wave_sum(distinct);
+        if (lane_id() == 0 && distinct) atomicAdd(a.distinct, distinct);
     }
 }
 
@@ -596,6 +603,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
     }
     // kGatherItems ions per thread in flight: the position reads are random
     const uint64_t st64 = stride;
+    uint32_t distinct = 0;
     for (uint64_t p0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p0 < nB; p0 += st64 * kGatherItems) {
         uint32_t id[kGatherItems];
         float x[kGatherItems], y[kGatherItems], z[kGatherItems];
@@ -619,9 +627,14 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
             const uint32_t c = key[p];
             const uint32_t cprev = p == 0 ? 0u : key[p - 1] + 1u;
             for (uint32_t q = cprev; q <= c; ++q) a.cell_start[q] = p;
+            distinct += cprev <= c ? 1u : 0u;   // the first record of its cell
             if (p == nB - 1)
                 for (uint32_t q = c + 1; q <= nc; ++q) a.cell_start[q] = nB;
         }
+    }
+    if (a.distinct) {
+        distinct = wave_sum(distinct);
+        if (lane_id() == 0 && distinct) atomicAdd(a.distinct, distinct);
     }
 }
 
@@ -629,30 +642,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
 // 8. the kNN radii from the volume the ions occupy.  The plan's first
 //    guesses use the bounding box, which a needle fills less than half;
 //    once the cells are known, the occupied cells of the denser set
-//    (distinct target cells, or non-empty neighbour cells) measure the
-//    specimen's volume.  occ[0] / occ[1] must be zero on entry.
+//    (distinct target cells, counted by k_take_order, or non-empty
+//    neighbour cells, counted by k_gather) measure the specimen's volume.
+//    occ[0] / occ[1] must be zero before those kernels run.
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_target_cells(const GridPlan* plan, const uint32_t* keys0,
-                                                         const uint32_t* keys1, uint32_t* occ) {
-    const GridPlan& P = *plan;
-    const uint32_t* __restrict__ key = (P.passes_T & 1) ? keys1 : keys0;   // sorted target keys
-    uint32_t c = 0;
-    for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < P.nT; t += gridDim.x * kBlock)
-        c += (t == 0 || key[t] != key[t - 1]);
-    c = wave_sum(c);
-    if (lane_id() == 0 && c) atomicAdd(&occ[0], c);
-}
-
-__global__ __launch_bounds__(kBlock) void k_neighbour_cells(const GridPlan* plan, const uint32_t* cell_start,
-                                                            uint32_t* occ) {
-    const uint32_t nc = plan->n_cells;
-    uint32_t c = 0;
-    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < nc; q += gridDim.x * kBlock)
-        c += cell_start[q + 1] > cell_start[q];
-    c = wave_sum(c);
-    if (lane_id() == 0 && c) atomicAdd(&occ[1], c);
-}
-
 __global__ void k_refine_radii(GridPlan* plan, const uint32_t* occ, int32_t k) {
     if (threadIdx.x != 0 || blockIdx.x != 0 || k <= 0) return;
     GridPlan& P = *plan;

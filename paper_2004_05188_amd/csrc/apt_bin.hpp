@@ -76,6 +76,8 @@ struct OrderArgs {
     float* tx;
     float* ty;
     float* tz;
+    const uint32_t* keys[2];   // sorted target keys
+    uint32_t* distinct;     // may be NULL: += number of distinct target cells
 };
 
 struct GatherArgs {
@@ -86,6 +88,7 @@ struct GatherArgs {
     uint32_t* vals[2];
     float4* bpos;           // [nB] (x, y, z, ion index as bits) in cell order
     uint32_t* cell_start;   // [n_cells + 1]
+    uint32_t* distinct;     // may be NULL: += number of non-empty neighbour cells
 };
 
 // Target / neighbour membership of ion i.  In union mode both are the ions
@@ -113,8 +116,6 @@ __global__ void k_rs_downsweep(SortArgs a);
 __global__ void k_take_order(OrderArgs a);
 __global__ void k_gather(GatherArgs a);
 __global__ void k_edges(double* E2, float r_max, int n_bins);
-__global__ void k_target_cells(const GridPlan* plan, const uint32_t* keys0, const uint32_t* keys1, uint32_t* occ);
-__global__ void k_neighbour_cells(const GridPlan* plan, const uint32_t* cell_start, uint32_t* occ);
 __global__ void k_refine_radii(GridPlan* plan, const uint32_t* occ, int32_t k);
 
 }  // namespace apt
