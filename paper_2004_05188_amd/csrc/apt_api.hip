@@ -163,7 +163,11 @@ static int sort_passes_max(uint32_t cap) {
     while (p < 4 && ((cap - 1u) >> (8 * p)) != 0u) ++p;
     return p;
 }
-constexpr int kSortBlocks = 1024;
+constexpr int kSortBlocks = 1024;   // most workgroups of a radix pass (the counts matrix is sized for it)
+// Workgroups of a radix pass over at most n keys: fewer, fuller ones for
+// small clouds (their fixed per-workgroup work dominates there; on the
+// 7.7 M-ion needle 512 bin 2 % faster than 1024, on 2e8 ions 1024 win).
+static int sort_blocks(int64_t n) { return n <= ((int64_t)1 << 25) ? 512 : kSortBlocks; }
 
 // Workspace of the plain path (rdf / knn / knn_rdf).
 struct PlainWs {
@@ -445,13 +449,14 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
     const int passes = sort_passes_max(pp.cell_cap);
     const int passes_T = passes < 4 ? passes + 1 : 4;
     const int Gk = cus * 8;
+    const int Gs = sort_blocks(n);
     auto sort = [&](int is_T) {
         for (int p = 0; p < (is_T ? passes_T : passes); ++p) {
-            SortArgs sa{w.plan, is_T, p, kSortBlocks, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.rs_counts,
+            SortArgs sa{w.plan, is_T, p, Gs, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.rs_counts,
                         w.rs_totals};
-            hipLaunchKernelGGL(k_rs_upsweep, dim3(kSortBlocks), dim3(kBlock), 0, st, sa);
+            hipLaunchKernelGGL(k_rs_upsweep, dim3(Gs), dim3(kBlock), 0, st, sa);
             hipLaunchKernelGGL(k_rs_scan, dim3(256), dim3(kBlock), 0, st, sa);
-            hipLaunchKernelGGL(k_rs_downsweep, dim3(kSortBlocks), dim3(kBlock), 0, st, sa);
+            hipLaunchKernelGGL(k_rs_downsweep, dim3(Gs), dim3(kBlock), 0, st, sa);
         }
     };
     // targets in cell order
@@ -680,14 +685,15 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
         PlanArgs pa{G, pw.part_cnt, pw.part_bbox, pw.part_nf, pw.part_off, pp, nullptr, pw.plan, status};
         hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, pa);
         const int Gk = cus * 8;
+        const int Gs = sort_blocks(n);
         KeyArgs kk{pw.plan, cl->xyz, nullptr, nullptr, 0, 0, pw.K[0], pw.V[0]};
         hipLaunchKernelGGL(k_keys, dim3(Gk), dim3(kBlock), 0, st, kk);
         for (int p = 0; p < sort_passes_max(pp.cell_cap); ++p) {
-            SortArgs sa{pw.plan, 0, p, kSortBlocks, {pw.K[0], pw.K[1]}, {pw.V[0], pw.V[1]}, pw.rs_counts,
+            SortArgs sa{pw.plan, 0, p, Gs, {pw.K[0], pw.K[1]}, {pw.V[0], pw.V[1]}, pw.rs_counts,
                         pw.rs_totals};
-            hipLaunchKernelGGL(k_rs_upsweep, dim3(kSortBlocks), dim3(kBlock), 0, st, sa);
+            hipLaunchKernelGGL(k_rs_upsweep, dim3(Gs), dim3(kBlock), 0, st, sa);
             hipLaunchKernelGGL(k_rs_scan, dim3(256), dim3(kBlock), 0, st, sa);
-            hipLaunchKernelGGL(k_rs_downsweep, dim3(kSortBlocks), dim3(kBlock), 0, st, sa);
+            hipLaunchKernelGGL(k_rs_downsweep, dim3(Gs), dim3(kBlock), 0, st, sa);
         }
         GatherArgs ga{pw.plan, cl->xyz, nullptr, {pw.K[0], pw.K[1]}, {pw.V[0], pw.V[1]}, pw.bpos, pw.cell_start,
                       nullptr};
