@@ -276,6 +276,16 @@ def test_frustum7m_queries(gpu, orc, needle7m, A, B):
     check_against_oracle(orc, g, xyz, lab, d, A, B, 1.0, k=10)
 
 
+@pytest.mark.parametrize("A,B", [(SC, SC), (SC, AL), (SI, SC)])
+def test_frustum7m_rdf_only(gpu, orc, needle7m, A, B):
+    """apt_rdf alone (no kNN: its rows are walked in raster order)."""
+    _say(f"case frustum7m rdf-only A={A} B={B} d_srf=1")
+    xyz, lab, d = needle7m
+    g = run_gpu(gpu, xyz, lab, d, A, B, 1.0, k_on=False)
+    assert g["status"] == 0
+    check_against_oracle(orc, g, xyz, lab, d, A, B, 1.0, k_on=False)
+
+
 # ---------------------------------------------------------------------------
 # label permutation (null model)
 # ---------------------------------------------------------------------------
