@@ -36,9 +36,12 @@ K, R_MAX, N_BINS, KB_RMAX, KB_NBINS = 10, 2.0, 200, 5.0, 5000
 # HBM bytes per k_pair launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
 # scaled by a plain-copy calibration; valid only for the kernel source they
 # were taken on (profiles/k_pair_frustum7m_hbm_counters.md)
-PAIR_TRAFFIC = {"frustum7m": (109.3e6, "91ab0e6180df92ff")}
+PAIR_TRAFFIC = {"frustum7m": (109.4e6, "d6307daf309b67d0")}
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk (packed FMA)
 FLOP_PER_PAIR = 8                 # 3 sub, 1 mul, 2 fma per pair distance
+# candidate pair-evaluations per second the FP32 vector units allow: 256 CU x
+# 64 lanes x 2 (packed) x 2.4 GHz over 6 instructions per candidate
+R_PAIR = 256 * 64 * 2 * 2.4e9 / 6
 
 
 def log(msg):
@@ -274,6 +277,11 @@ def main():
     tile_ms, _ = aptstat.trace_read("tile")
     bin_ms, bin_n = aptstat.trace_read("binning")
 
+    # culling: the neighbour records the pair kernel's first enumeration
+    # visits (outside the timed region), against the in-range pairs
+    cand = sum(int(aptstat.count_candidates(cloud, A, B, d_srf, R_MAX, N_BINS, k=K, ws=ws).item())
+               for A, B in queries)
+
     ms_per_step = 1e3 * dt / args.steps
     value = total_targets * args.steps / dt
     # roofline of the pair kernel: algorithmic FLOPs of the in-range pairs of
@@ -306,6 +314,9 @@ def main():
                                "tile": tile_ms / stage_steps},
         "in_range_pairs_per_step": pairs,
         "in_range_pairs_per_s": pairs * stage_steps / ((pair2_ms + tile_ms) / 1e3),
+        "culling": {"candidates_per_step": cand, "ratio": cand / max(pairs, 1),
+                    "candidate_evals_per_s": cand * stage_steps / (pair2_ms / 1e3) if pair2_ms > 0 else None,
+                    "frac_of_r_pair": (cand * stage_steps / (pair2_ms / 1e3)) / R_PAIR if pair2_ms > 0 else None},
         "status": status,
     }
     if args.batched_reps > 0 and args.workload == "frustum7m":

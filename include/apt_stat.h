@@ -211,6 +211,20 @@ apt_status apt_rdf_smooth_bwd(const apt_cloud* cloud, apt_query q, apt_bins bins
 apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_targets, void* ws,
                              size_t ws_bytes, void* stream);
 
+/* Diagnostic, not part of any statistic: bins the cloud exactly as
+ * apt_knn_rdf(q, bins, k, ...) would (k = 0: as apt_rdf), then sets
+ * candidates[0] (uint64, device; overwritten) to the number of neighbour
+ * records that the one-target-per-wavefront pair kernel's first enumeration
+ * visits, summed over the eligible targets: the cell rows within bins.r_max
+ * (or within the first kNN radius, when k > 0 and that is larger), each row
+ * trimmed to the x-range the sphere reaches.  Divided by the in-range pair
+ * count it gives the culling ratio of the grid (paper, Supplementary,
+ * "Effectiveness of the spatial splitting").  Errors as
+ * apt_knn_rdf; k < 0 or candidates NULL return APT_E_ARG.  Workspace as
+ * APT_OP_KNN_RDF. */
+apt_status apt_count_candidates(const apt_cloud* cloud, apt_query q, apt_bins bins, int32_t k,
+                                uint64_t* candidates, int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
 /* Process-wide tuning of the plain entry points (host only; results do not
  * depend on it, only speed):
  *   tile_policy  0 automatic, 1 one target per wavefront, 2 64 targets per

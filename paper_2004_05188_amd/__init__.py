@@ -64,6 +64,8 @@ _SIGS = {
     "apt_trace_read": ([ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
                        ctypes.c_int),
     "apt_count_targets": ([ctypes.POINTER(_Cloud), _Query, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "apt_count_candidates": ([ctypes.POINTER(_Cloud), _Query, _Bins, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t,
+                              _P], ctypes.c_int),
     "apt_permute_labels": ([_P, ctypes.c_int64, ctypes.c_uint64, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_rdf_batched": ([ctypes.POINTER(_Cloud), _P, ctypes.c_int32, _P, ctypes.c_int32, _Bins, ctypes.c_int32,
                          _Bins, _P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
@@ -229,6 +231,19 @@ def count_targets(cloud: Cloud, target: int, d_srf: float = 0.0, ws: Workspace |
     out = out if out is not None else torch.empty(1, dtype=torch.int64, device=cloud.device)
     _check(lib().apt_count_targets(cloud.c(), _query(target, ANY, d_srf), _ptr(out), _ptr(buf), nb,
                                    _stream(cloud.xyz)), "apt_count_targets")
+    return out
+
+
+def count_candidates(cloud: Cloud, target: int, neighbor: int, d_srf: float, r_max: float = 2.0, n_bins: int = 200,
+                     k: int = 0, ws: Workspace | None = None) -> torch.Tensor:
+    """Diagnostic: neighbour records the pair kernel's first enumeration visits
+    over all eligible targets (int64 tensor [1]); see apt_count_candidates."""
+    buf, nb = _ws(ws, OP_KNN_RDF, cloud)
+    out = torch.empty(1, dtype=torch.int64, device=cloud.device)
+    status = torch.empty(1, dtype=torch.int32, device=cloud.device)
+    _check(lib().apt_count_candidates(cloud.c(), _query(target, neighbor, d_srf), _bins(r_max, n_bins), int(k),
+                                      _ptr(out), _ptr(status), _ptr(buf), nb, _stream(cloud.xyz)),
+           "apt_count_candidates")
     return out
 
 

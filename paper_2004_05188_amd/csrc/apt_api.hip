@@ -480,11 +480,13 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
 }
 
 // The whole plain path.  rdf_hist / knn outputs may be absent.
+// cand (diagnostic, device u64): bin as the call would, then count the RDF
+// stencil's candidates into *cand instead of running the pair kernels.
 static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb, uint64_t* rdf_hist,
                             int32_t k, float r_knn_max, int64_t capacity, int64_t* target_id,
                             float* dist, int64_t* nbr_id, const apt_bins* kb, uint64_t* knn_hist,
                             int64_t* n_targets, int32_t* status, void* ws, size_t ws_bytes,
-                            void* stream) {
+                            void* stream, uint64_t* cand = nullptr) {
     apt_status s;
     if ((s = check_cloud(cl)) != APT_OK) return s;
     if ((s = check_query(q)) != APT_OK) return s;
@@ -492,14 +494,16 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     const bool do_rdf = rb != nullptr, do_knn = k > 0;
     if (do_rdf) {
         if ((s = check_bins(*rb, "rdf_bins")) != APT_OK) return s;
-        if (!rdf_hist) return fail(APT_E_ARG, "rdf histogram output is NULL");
+        if (!rdf_hist && !cand) return fail(APT_E_ARG, "rdf histogram output is NULL");
     }
     if (do_knn) {
         if (k > APT_MAX_K) return fail(APT_E_UNSUPPORTED, "k must be in [1, 256]");
         if (!(r_knn_max > 0.0f)) return fail(APT_E_ARG, "r_knn_max must be > 0 (or +inf)");
         if (capacity < 0) return fail(APT_E_ARG, "capacity is negative");
-        if (capacity > 0 && (!target_id || !dist || !nbr_id)) return fail(APT_E_ARG, "kNN row output is NULL");
-        if (!n_targets) return fail(APT_E_ARG, "n_targets is NULL");
+        if (!cand) {
+            if (capacity > 0 && (!target_id || !dist || !nbr_id)) return fail(APT_E_ARG, "kNN row output is NULL");
+            if (!n_targets) return fail(APT_E_ARG, "n_targets is NULL");
+        }
         if (knn_hist && (s = check_bins(*kb, "knn_bins")) != APT_OK) return s;
     }
     PlainWs w = carve_plain(ws, cl->n);
@@ -507,8 +511,8 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     (void)hipGetLastError();
 
-    InitArgs ia{status, rdf_hist, do_rdf ? rb->n_bins : 0, knn_hist, knn_hist ? kb->n_bins + 1 : 0, n_targets,
-                w.strag_count};
+    InitArgs ia{status, cand ? cand : rdf_hist, cand ? 1 : (do_rdf ? rb->n_bins : 0), knn_hist,
+                knn_hist ? kb->n_bins + 1 : 0, n_targets, w.strag_count};
     hipLaunchKernelGGL(k_init, dim3(64), dim3(256), 0, st, ia);
     if (do_rdf) hipLaunchKernelGGL(k_edges, dim3(64), dim3(256), 0, st, w.E2, rb->r_max, rb->n_bins);
     if (knn_hist) hipLaunchKernelGGL(k_edges, dim3(64), dim3(256), 0, st, w.KE2, kb->r_max, kb->n_bins);
@@ -528,6 +532,12 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     {
         TraceSpan span("binning", st);
         if ((s = run_binning(cl, q, pp, w, status, st)) != APT_OK) return s;
+    }
+    if (cand) {
+        hipLaunchKernelGGL(k_count_candidates, dim3(device_info().cus * 8), dim3(kBlock), 0, st, w.plan,
+                           w.cell_start, w.tx, w.ty, w.tz, rb->r_max, do_knn ? 1 : 0,
+                           reinterpret_cast<unsigned long long*>(cand));
+        return hip_check("candidate count launch");
     }
 
     PairArgs pa{};
@@ -1070,6 +1080,14 @@ apt_status apt_knn_rdf(const apt_cloud* cloud, apt_query q, apt_bins rdf_bins, u
     if (k < 1) return fail(APT_E_ARG, "k must be >= 1");
     return run_plain(cloud, q, &rdf_bins, rdf_hist, k, r_knn_max, capacity, target_id, dist, nbr_id,
                      &knn_bins, knn_hist, n_targets, status, ws, ws_bytes, stream);
+}
+
+apt_status apt_count_candidates(const apt_cloud* cloud, apt_query q, apt_bins bins, int32_t k,
+                                uint64_t* candidates, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+    if (k < 0) return fail(APT_E_ARG, "k must be >= 0");
+    if (!candidates) return fail(APT_E_ARG, "candidates is NULL");
+    return run_plain(cloud, q, &bins, nullptr, k, INFINITY, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                     nullptr, status, ws, ws_bytes, stream, candidates);
 }
 
 apt_status apt_rdf_smooth_fwd(const apt_cloud* cloud, apt_query q, apt_bins bins, float sigma, const double* z_scale,

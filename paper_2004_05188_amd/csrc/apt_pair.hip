@@ -146,6 +146,36 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
     if (LDS_HIST) flush_hist(T.hist_l, a.hist, a.n_bins);
 }
 
+// Diagnostic: the neighbour records in the cell rows of the first
+// enumeration of every eligible target in the one-target-per-wavefront
+// kernel (radius r_enum, or the first kNN radius when that is larger),
+// summed into *out.  One target per thread.
+__global__ __launch_bounds__(kBlock) void k_count_candidates(const GridPlan* plan, const uint32_t* cell_start,
+                                                             const float* tx, const float* ty, const float* tz,
+                                                             float r_enum, int knn, unsigned long long* out) {
+    const GridPlan P = *plan;
+    const float rk = P.rk0 * 1.000001f;
+    const float R = (knn && !(rk < r_enum)) ? rk : r_enum;
+    const float Re = R + P.eps;
+    const float R2 = Re * Re;
+    unsigned long long acc = 0;
+    for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < P.nT; t += (uint64_t)gridDim.x * kBlock) {
+        const float px = tx[t], py = ty[t], pz = tz[t];
+        if (!(isfinite(px) && isfinite(py) && isfinite(pz))) continue;
+        const int cy0 = cell_axis(P, 1, py - Re), cy1 = cell_axis(P, 1, py + Re);
+        const int cz0 = cell_axis(P, 2, pz - Re), cz1 = cell_axis(P, 2, pz + Re);
+        for (int cz = cz0; cz <= cz1; ++cz)
+            for (int cy = cy0; cy <= cy1; ++cy) {
+                uint32_t st, len;
+                row_span(P, cell_start, cy, cz, px, py, pz, px, py, pz, R2, st, len);
+                acc += len;
+            }
+    }
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, kWave);
+    if (lane_id() == 0 && acc) atomicAdd(out, acc);
+}
+
 size_t tile_lds_bytes(bool rdf, int n_bins) {
     size_t b = rdf ? (size_t)kWavesPerBlock * (size_t)hist_stride(n_bins) * 4u : 0;
     b = (b + 15) & ~size_t(15);

@@ -59,5 +59,7 @@ size_t pair_lds_bytes(bool rdf, bool knn, int n_bins, bool hist_in_lds);
 template <int FLAGS, int KMAX>
 __global__ void k_pair_tile(PairArgs a);
 size_t tile_lds_bytes(bool rdf, int n_bins);
+__global__ void k_count_candidates(const GridPlan* plan, const uint32_t* cell_start, const float* tx,
+                                   const float* ty, const float* tz, float r_enum, int knn, unsigned long long* out);
 
 }  // namespace apt

@@ -68,6 +68,29 @@ __device__ __forceinline__ int centre_out(int i, int L) {
     return L / 2 + ((i & 1) ? -((i + 1) >> 1) : (i >> 1));
 }
 
+// Records [st, st + len) of the cell row (cy, cz) that can lie within R of
+// the box [x0,x1] x [y0,y1] x [z0,z1] (R2 = (R + eps)^2): the row's cells
+// trimmed to the x-range the sphere reaches at the row's distance from the
+// box; len = 0 for a row beyond R.
+__device__ __forceinline__ void row_span(const GridPlan& P, const uint32_t* __restrict__ cell_start, int cy, int cz,
+                                         float x0, float y0, float z0, float x1, float y1, float z1, float R2,
+                                         uint32_t& st, uint32_t& len) {
+    const float ya = P.lo[1] + (float)cy * P.h - P.eps, yb = P.lo[1] + (float)(cy + 1) * P.h + P.eps;
+    const float za = P.lo[2] + (float)cz * P.h - P.eps, zb = P.lo[2] + (float)(cz + 1) * P.h + P.eps;
+    const float dy = fmaxf(0.0f, fmaxf(ya - y1, y0 - yb));
+    const float dz = fmaxf(0.0f, fmaxf(za - z1, z0 - zb));
+    const float d2 = dy * dy + dz * dz;
+    st = 0;
+    len = 0;
+    if (d2 <= R2) {
+        const float ex = sqrtf(R2 - d2) + P.eps;
+        const int cx0 = cell_axis(P, 0, x0 - ex), cx1 = cell_axis(P, 0, x1 + ex);
+        const uint32_t base = ((uint32_t)cz * (uint32_t)P.dim[1] + (uint32_t)cy) * (uint32_t)P.dim[0];
+        st = cell_start[base + (uint32_t)cx0];
+        len = cell_start[base + (uint32_t)cx1 + 1u] - st;
+    }
+}
+
 template <class F>
 __device__ __forceinline__ void enumerate_box(const GridPlan& P, const uint32_t* __restrict__ cell_start,
                                               const float4* __restrict__ bpos, float x0, float y0, float z0,
@@ -86,18 +109,7 @@ __device__ __forceinline__ void enumerate_box(const GridPlan& P, const uint32_t*
         if (r < nrows) {
             const int iz = r / ny, iy = r % ny;
             const int cz = cz0 + (centre ? centre_out(iz, nz) : iz), cy = cy0 + (centre ? centre_out(iy, ny) : iy);
-            const float ya = P.lo[1] + (float)cy * P.h - P.eps, yb = P.lo[1] + (float)(cy + 1) * P.h + P.eps;
-            const float za = P.lo[2] + (float)cz * P.h - P.eps, zb = P.lo[2] + (float)(cz + 1) * P.h + P.eps;
-            const float dy = fmaxf(0.0f, fmaxf(ya - y1, y0 - yb));
-            const float dz = fmaxf(0.0f, fmaxf(za - z1, z0 - zb));
-            const float d2 = dy * dy + dz * dz;
-            if (d2 <= R2) {
-                const float ex = sqrtf(R2 - d2) + P.eps;
-                const int cx0 = cell_axis(P, 0, x0 - ex), cx1 = cell_axis(P, 0, x1 + ex);
-                const uint32_t base = ((uint32_t)cz * (uint32_t)P.dim[1] + (uint32_t)cy) * (uint32_t)P.dim[0];
-                st = cell_start[base + (uint32_t)cx0];
-                len = cell_start[base + (uint32_t)cx1 + 1u] - st;
-            }
+            row_span(P, cell_start, cy, cz, x0, y0, z0, x1, y1, z1, R2, st, len);
         }
         const uint32_t inc = wave_incl_scan(len);
         const uint32_t tot = readlane(inc, kWave - 1);
@@ -392,17 +404,11 @@ __device__ __forceinline__ void run_lane(const GridPlan& P, const PairTask& T, b
         while (j >= j1 && r < nrows) {
             const int cz = cz0 + centre_out(r / ny, nz), cy = cy0 + centre_out(r % ny, ny);
             ++r;
-            const float ya = P.lo[1] + (float)cy * P.h - P.eps, yb = P.lo[1] + (float)(cy + 1) * P.h + P.eps;
-            const float za = P.lo[2] + (float)cz * P.h - P.eps, zb = P.lo[2] + (float)(cz + 1) * P.h + P.eps;
-            const float dy = fmaxf(0.0f, fmaxf(ya - py, py - yb));
-            const float dz = fmaxf(0.0f, fmaxf(za - pz, pz - zb));
-            const float d2r = dy * dy + dz * dz;
-            if (d2r <= R2) {
-                const float ex = sqrtf(R2 - d2r) + P.eps;
-                const int cx0 = cell_axis(P, 0, px - ex), cx1 = cell_axis(P, 0, px + ex);
-                const uint32_t base = ((uint32_t)cz * (uint32_t)P.dim[1] + (uint32_t)cy) * (uint32_t)P.dim[0];
-                j = T.cell_start[base + (uint32_t)cx0];
-                j1 = T.cell_start[base + (uint32_t)cx1 + 1u];
+            uint32_t st, len;
+            row_span(P, T.cell_start, cy, cz, px, py, pz, px, py, pz, R2, st, len);
+            if (len) {
+                j = st;
+                j1 = st + len;
             }
         }
         if (j >= j1) break;

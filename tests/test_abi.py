@@ -113,6 +113,19 @@ def test_knn_argument_validation(aptstat):
     assert L.apt_knn(*args(10, math.inf, 10, None)) == -1      # NULL rows
 
 
+def test_count_candidates_validation(aptstat):
+    L = aptstat.lib()
+    q = aptstat._query(1, 1, 0.0)
+    p = ctypes.c_void_p(0x5000)
+    ws, big = ctypes.c_void_p(0x100000), 1 << 40
+    good = aptstat._bins(2.0, 200)
+    assert L.apt_count_candidates(_cloud(aptstat), q, good, -1, p, p, ws, big, None) == -1
+    assert L.apt_count_candidates(_cloud(aptstat), q, good, 0, None, p, ws, big, None) == -1
+    assert "candidates" in _err(aptstat)
+    assert L.apt_count_candidates(_cloud(aptstat), q, aptstat._bins(0.0, 200), 0, p, p, ws, big, None) == -1
+    assert L.apt_count_candidates(_cloud(aptstat), q, good, 257, p, p, ws, big, None) == -3
+
+
 def test_tuning_round_trip_and_validation(aptstat):
     """The tuning is host state: set, read back, rejected when out of range
     (unchanged then), and NULL restores the defaults."""

@@ -127,6 +127,25 @@ def test_large_bin_count_uses_global_histogram(gpu, orc, small_needle):
     check_against_oracle(orc, g, xyz, lab, d, SC, ANY, 1.0, r_max=2.5, n_bins=5000, k_on=False)
 
 
+def test_candidate_count_bounds(gpu, orc, small_needle):
+    """The diagnostic candidate count lies between the in-range pair count
+    (every pair the RDF counts must be visited) and targets x neighbours and
+    repeats exactly; no eligible target gives zero."""
+    _say("case needle candidate counts")
+    aptstat, torch, ws = gpu
+    xyz, lab, d = small_needle
+    cloud = aptstat.Cloud(*_to_dev(torch, xyz, lab, d))
+    for A, B in ((SC, ANY), (SC, SC), (AL, SI)):
+        n_t = len(orc.knn(xyz, lab, d, A, B, 1.0, 1, math.inf, 5.0, 10)[0])
+        n_b = int(np.count_nonzero(lab == B)) if B != ANY else len(lab)
+        for r_max, k in ((2.0, 0), (1.0, 0), (1.0, 10)):
+            hits = int(orc.rdf(xyz, lab, d, A, B, 1.0, r_max, 200).sum())
+            c = int(aptstat.count_candidates(cloud, A, B, 1.0, r_max, 200, k=k, ws=ws).item())
+            assert hits <= c <= n_t * n_b, (A, B, r_max, k, hits, c, n_t * n_b)
+            assert int(aptstat.count_candidates(cloud, A, B, 1.0, r_max, 200, k=k, ws=ws).item()) == c
+    assert int(aptstat.count_candidates(cloud, SC, ANY, 1e6, ws=ws).item()) == 0
+
+
 def test_deterministic_repeat(gpu, small_needle):
     _say("case needle repeat determinism")
     xyz, lab, d = small_needle
