@@ -151,6 +151,24 @@ def batched_vs_looped(aptstat, torch, cloud, ws, n_rep, n_loop):
     tb = time.perf_counter() - t0
     aptstat.trace_enable(False)
     stages = {s_: aptstat.trace_read(s_)[0] for s_ in ("pair", "tile", "binning", "permute", "partition")}
+    # the same call captured once in a HIP graph and replayed (its outputs
+    # must equal the eager call's)
+    want = (rh.clone(), kh.clone())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph, stream=side):
+            aptstat.rdf_batched(cloud, pairs, seeds, r_max=R_MAX, n_bins=N_BINS, k=K, kb_rmax=KB_RMAX,
+                                kb_nbins=KB_NBINS, ws=ws, out=(rh, kh, st))
+    torch.cuda.synchronize()
+    log(f"[bench] batched: graph replay")
+    t0 = time.perf_counter()
+    graph.replay()
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    graph_equal = bool(torch.equal(want[0], rh) and torch.equal(want[1], kh))
+    del graph
     # looped: the definition of the batched result, call by call
     lab_r = torch.empty_like(cloud.lab)
     outs = (torch.empty(1, dtype=torch.int64, device=dev), torch.empty((1, K), dtype=torch.float32, device=dev),
@@ -176,6 +194,7 @@ def batched_vs_looped(aptstat, torch, cloud, ws, n_rep, n_loop):
     return {"replicates": n_rep, "pairs": [f"{NAMES[a]}->{NAMES[b]}" for a, b, _ in pairs],
             "batched_replicates_per_s": n_rep / tb, "batched_s": tb,
             "batched_stage_ms": stages,
+            "graph_replicates_per_s": n_rep / tg, "graph_equals_eager": graph_equal,
             "looped_replicates_per_s": n_loop / tl, "looped_replicates_timed": n_loop,
             "looped_calls_timed": n_loop * (1 + len(pairs)),
             "speedup": (n_rep / tb) / (n_loop / tl), "status": int(st.item())}
