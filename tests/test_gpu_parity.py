@@ -103,6 +103,7 @@ def small_needle(synth):
     (SC, SC, 10, 1.0, math.inf), (SC, AL, 10, 1.0, math.inf), (SI, SC, 10, 1.0, math.inf),
     (AL, SC, 10, 1.0, math.inf), (SC, ANY, 1, 2.0, math.inf), (ANY, SI, 3, 0.5, math.inf),
     (SC, SI, 37, 1.0, math.inf), (SC, SC, 10, 1.0, 1.3), (SI, AL, 64, 0.0, math.inf),
+    (SC, ANY, 100, 1.0, math.inf), (SI, SC, 100, 1.0, math.inf),
 ])
 def test_needle_queries(gpu, orc, small_needle, A, B, k, d_srf, r_knn_max):
     _say(f"case needle A={A} B={B} k={k} d_srf={d_srf} rknn={r_knn_max}")
