@@ -393,9 +393,18 @@ struct InitArgs {
     int32_t n2;
     int64_t* n_targets;
     uint32_t* counter;
+    // squared bin edges of the RDF and of the k-th distance histogram, or NULL
+    double* e2;
+    float e2_rmax;
+    int32_t e2_nbins;
+    double* ke2;
+    float ke2_rmax;
+    int32_t ke2_nbins;
 };
 __global__ void k_init(InitArgs a) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x, st = gridDim.x * blockDim.x;
+    if (a.e2) fill_edges(a.e2, a.e2_rmax, a.e2_nbins, t, st);
+    if (a.ke2) fill_edges(a.ke2, a.ke2_rmax, a.ke2_nbins, t, st);
     if (t == 0) {
         if (a.status) *a.status = 0;
         if (a.n_targets) *a.n_targets = 0;
@@ -475,7 +484,6 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
     GatherArgs ga{w.plan, cl->xyz, zscale, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.bpos, w.cell_start,
                   occ ? w.strag_count + 2 : nullptr};
     hipLaunchKernelGGL(k_gather, dim3(Gk), dim3(kBlock), 0, st, ga);
-    if (occ) hipLaunchKernelGGL(k_refine_radii, dim3(1), dim3(64), 0, st, w.plan, w.strag_count + 1, pp.k);
     return hip_check("binning launch");
 }
 
@@ -512,10 +520,10 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     (void)hipGetLastError();
 
     InitArgs ia{status, cand ? cand : rdf_hist, cand ? 1 : (do_rdf ? rb->n_bins : 0), knn_hist,
-                knn_hist ? kb->n_bins + 1 : 0, n_targets, w.strag_count};
+                knn_hist ? kb->n_bins + 1 : 0, n_targets, w.strag_count,
+                do_rdf ? w.E2 : nullptr, do_rdf ? rb->r_max : 0.0f, do_rdf ? rb->n_bins : 0,
+                knn_hist ? w.KE2 : nullptr, knn_hist ? kb->r_max : 0.0f, knn_hist ? kb->n_bins : 0};
     hipLaunchKernelGGL(k_init, dim3(64), dim3(256), 0, st, ia);
-    if (do_rdf) hipLaunchKernelGGL(k_edges, dim3(64), dim3(256), 0, st, w.E2, rb->r_max, rb->n_bins);
-    if (knn_hist) hipLaunchKernelGGL(k_edges, dim3(64), dim3(256), 0, st, w.KE2, kb->r_max, kb->n_bins);
 
     const apt_tuning tu = tuning();
     const bool rdf_lds = do_rdf && pair_lds_bytes(true, do_knn, rb->n_bins, true) <= kMaxLds;
@@ -535,8 +543,8 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     }
     if (cand) {
         hipLaunchKernelGGL(k_count_candidates, dim3(device_info().cus * 8), dim3(kBlock), 0, st, w.plan,
-                           w.cell_start, w.tx, w.ty, w.tz, rb->r_max, do_knn ? 1 : 0,
-                           reinterpret_cast<unsigned long long*>(cand));
+                           do_knn ? w.strag_count + 1 : nullptr, w.cell_start, w.tx, w.ty, w.tz, rb->r_max,
+                           do_knn ? k : 0, reinterpret_cast<unsigned long long*>(cand));
         return hip_check("candidate count launch");
     }
 
@@ -592,6 +600,10 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     }
     pa.strag = w.strag;
     pa.strag_count = w.strag_count;
+    // the kNN radii from the occupied cells that the binning counted
+    pa.occ = do_knn ? w.strag_count + 1 : nullptr;
+    pa.n_targets = do_knn ? n_targets : nullptr;
+    pa.status = status;
     const size_t lds = pair_lds_bytes(do_rdf, do_knn, n_bins, in_lds);
     if (pp.tile_policy != 1) {
         // 64 targets per wavefront when the plan chooses it (exits otherwise)
@@ -627,8 +639,6 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
             self ? go(k_pair<kSelf, true>) : go(k_pair<0, true>);
         }
     }
-    FinishArgs fa{w.plan, do_knn ? capacity : -1, n_targets, status};
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, st, fa);
     return hip_check("pair launch");
 }
 
@@ -677,10 +687,9 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
     // zero the outputs and the status word, edge tables
     const int64_t nh = (int64_t)n_rep * n_pairs * rb.n_bins;
     const int64_t nk = knn_hist ? (int64_t)n_rep * n_pairs * (kb.n_bins + 1) : 0;
-    InitArgs ia{status, rdf_hist, (int32_t)nh, knn_hist, (int32_t)nk, nullptr, nullptr};
+    InitArgs ia{status, rdf_hist, (int32_t)nh, knn_hist, (int32_t)nk, nullptr, nullptr,
+                w.plain.E2, rb.r_max, rb.n_bins, knn_hist ? w.plain.KE2 : nullptr, kb.r_max, kb.n_bins};
     hipLaunchKernelGGL(k_init, dim3(cus * 4), dim3(256), 0, st, ia);
-    hipLaunchKernelGGL(k_edges, dim3(64), dim3(256), 0, st, w.plain.E2, rb.r_max, rb.n_bins);
-    if (knn_hist) hipLaunchKernelGGL(k_edges, dim3(64), dim3(256), 0, st, w.plain.KE2, kb.r_max, kb.n_bins);
 
     // all ions binned once: records in cell order (w.plain.bpos), cell ids
     {

@@ -638,40 +638,5 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
     }
 }
 
-// ------------------------------------------------------------------------
-// 8. the kNN radii from the volume the ions occupy.  The plan's first
-//    guesses use the bounding box, which a needle fills less than half;
-//    once the cells are known, the occupied cells of the denser set
-//    (distinct target cells, counted by k_take_order, or non-empty
-//    neighbour cells, counted by k_gather) measure the specimen's volume.
-//    occ[0] / occ[1] must be zero before those kernels run.
-// ------------------------------------------------------------------------
-__global__ void k_refine_radii(GridPlan* plan, const uint32_t* occ, int32_t k) {
-    if (threadIdx.x != 0 || blockIdx.x != 0 || k <= 0) return;
-    GridPlan& P = *plan;
-    double box = 1.0;
-    for (int ax = 0; ax < 3; ++ax) box *= fmax((double)P.hi[ax] - (double)P.lo[ax], 1e-3);
-    const double h = (double)P.h;
-    double vol = (double)max(occ[0], occ[1]) * h * h * h;
-    if (!(vol > 0.0) || vol > box) vol = box;
-    const double rho = (double)(P.nB > 0 ? P.nB : 1) / vol;
-    const double r = 1.15 * cbrt(3.0 * ((double)k + 0.5) / (4.0 * M_PI * rho));
-    P.rk0 = (float)fmin(r, (double)P.r_all);
-    // tiles: certified within 1.6x the Poisson mean k-th distance (species
-    // that cluster leave the matrix poorer than the mean: a tighter radius
-    // sends too many targets to the one-by-one search)
-    P.rk_tile = (float)fmin(1.6 / 1.15 * (double)P.rk0, (double)P.r_all);
-}
-
-// ------------------------------------------------------------------------
-// 9. squared bin edges, e_b = b * r_max / n_bins in FP64
-// ------------------------------------------------------------------------
-__global__ void k_edges(double* E2, float r_max, int n_bins) {
-#pragma clang fp contract(off)
-    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b <= n_bins; b += gridDim.x * blockDim.x) {
-        const double e = ((double)b * (double)r_max) / (double)n_bins;
-        E2[b] = e * e;
-    }
-}
 
 }  // namespace apt

@@ -106,6 +106,38 @@ __device__ __forceinline__ void select_ion(uint8_t l, const float* d_bnd, int64_
     }
 }
 
+// The kNN radii from the volume the ions occupy.  The plan's first guesses
+// use the bounding box, which a needle fills less than half; once the cells
+// are known, the occupied cells of the denser set (occ[0]: distinct target
+// cells, counted by k_take_order; occ[1]: non-empty neighbour cells, counted
+// by k_gather, both zero before those kernels run) measure the specimen's
+// volume.  The kernels that search apply this to their own copy of the plan.
+__device__ inline void refine_radii(GridPlan& P, const uint32_t* occ, int32_t k) {
+    if (!occ || k <= 0) return;
+    double box = 1.0;
+    for (int ax = 0; ax < 3; ++ax) box *= fmax((double)P.hi[ax] - (double)P.lo[ax], 1e-3);
+    const double h = (double)P.h;
+    double vol = (double)max(occ[0], occ[1]) * h * h * h;
+    if (!(vol > 0.0) || vol > box) vol = box;
+    const double rho = (double)(P.nB > 0 ? P.nB : 1) / vol;
+    const double r = 1.15 * cbrt(3.0 * ((double)k + 0.5) / (4.0 * M_PI * rho));
+    P.rk0 = (float)fmin(r, (double)P.r_all);
+    // tiles: certified within 1.6x the Poisson mean k-th distance (species
+    // that cluster leave the matrix poorer than the mean: a tighter radius
+    // sends too many targets to the one-by-one search)
+    P.rk_tile = (float)fmin(1.6 / 1.15 * (double)P.rk0, (double)P.r_all);
+}
+
+// Squared bin edges e_b^2, e_b = b * r_max / n_bins in FP64, b = 0..n_bins,
+// written by the threads [t, n_bins] in steps of `stride`.
+__device__ inline void fill_edges(double* E2, float r_max, int n_bins, int t, int stride) {
+#pragma clang fp contract(off)
+    for (int b = t; b <= n_bins; b += stride) {
+        const double e = ((double)b * (double)r_max) / (double)n_bins;
+        E2[b] = e * e;
+    }
+}
+
 __global__ void k_count(CountArgs a);
 __global__ void k_plan(PlanArgs a);
 __global__ void k_compact(CompactArgs a);
@@ -115,7 +147,5 @@ __global__ void k_rs_scan(SortArgs a);
 __global__ void k_rs_downsweep(SortArgs a);
 __global__ void k_take_order(OrderArgs a);
 __global__ void k_gather(GatherArgs a);
-__global__ void k_edges(double* E2, float r_max, int n_bins);
-__global__ void k_refine_radii(GridPlan* plan, const uint32_t* occ, int32_t k);
 
 }  // namespace apt

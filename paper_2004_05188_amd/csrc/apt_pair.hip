@@ -20,6 +20,7 @@
 //    the search unbounded;
 //  * targets are processed in cell order and dealt out so that each XCD
 //    (and its L2) works on one contiguous slab of space.
+#include "apt_bin.hpp"
 #include "apt_pairdev.hpp"
 
 namespace apt {
@@ -36,7 +37,12 @@ template <int FLAGS, bool KNN>
 __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
     constexpr bool LDS_HIST = (FLAGS & kRdfLds) != 0;
     extern __shared__ __align__(16) uint8_t smem[];
-    const GridPlan P = *a.plan;
+    GridPlan P = *a.plan;
+    refine_radii(P, a.occ, a.k);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (a.n_targets) *a.n_targets = (int64_t)P.nT;
+        if (a.k > 0 && a.status && (int64_t)P.nT > a.capacity) atomicOr(a.status, APT_STATUS_CAPACITY);
+    }
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int l = lane_id();
     PairTask T;
@@ -150,12 +156,14 @@ __global__ __launch_bounds__(kBlock) void k_pair(PairArgs a) {
 // enumeration of every eligible target in the one-target-per-wavefront
 // kernel (radius r_enum, or the first kNN radius when that is larger),
 // summed into *out.  One target per thread.
-__global__ __launch_bounds__(kBlock) void k_count_candidates(const GridPlan* plan, const uint32_t* cell_start,
-                                                             const float* tx, const float* ty, const float* tz,
-                                                             float r_enum, int knn, unsigned long long* out) {
-    const GridPlan P = *plan;
+__global__ __launch_bounds__(kBlock) void k_count_candidates(const GridPlan* plan, const uint32_t* occ,
+                                                             const uint32_t* cell_start, const float* tx,
+                                                             const float* ty, const float* tz, float r_enum,
+                                                             int32_t k, unsigned long long* out) {
+    GridPlan P = *plan;
+    refine_radii(P, occ, k);
     const float rk = P.rk0 * 1.000001f;
-    const float R = (knn && !(rk < r_enum)) ? rk : r_enum;
+    const float R = (k > 0 && !(rk < r_enum)) ? rk : r_enum;
     const float Re = R + P.eps;
     const float R2 = Re * Re;
     unsigned long long acc = 0;
@@ -185,8 +193,9 @@ size_t tile_lds_bytes(bool rdf, int n_bins) {
 template <int FLAGS, int KMAX>
 __global__ __launch_bounds__(kBlock) void k_pair_tile(PairArgs a) {
     constexpr bool LDS_HIST = (FLAGS & kRdfLds) != 0;
-    const GridPlan P = *a.plan;
+    GridPlan P = *a.plan;
     if (!P.tile_mode) return;
+    refine_radii(P, a.occ, a.k);
     extern __shared__ __align__(16) uint8_t smem[];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int l = lane_id();

@@ -42,6 +42,11 @@ struct PairArgs {
     // tile mode: targets left for the one-per-wavefront pass
     uint32_t* strag;             // [nT] target slots (cell order)
     uint32_t* strag_count;       // [1], zeroed before the tile pass
+    const uint32_t* occ;         // [2] occupied-cell counts for refine_radii, or NULL
+    // written once per call by k_pair (workgroup 0): the eligible target
+    // count, and APT_STATUS_CAPACITY when k > 0 and it exceeds capacity
+    int64_t* n_targets;
+    int32_t* status;
 };
 
 // grid: multiple of 8 workgroups of kBlock threads; dynamic LDS per block:
@@ -59,7 +64,8 @@ size_t pair_lds_bytes(bool rdf, bool knn, int n_bins, bool hist_in_lds);
 template <int FLAGS, int KMAX>
 __global__ void k_pair_tile(PairArgs a);
 size_t tile_lds_bytes(bool rdf, int n_bins);
-__global__ void k_count_candidates(const GridPlan* plan, const uint32_t* cell_start, const float* tx,
-                                   const float* ty, const float* tz, float r_enum, int knn, unsigned long long* out);
+__global__ void k_count_candidates(const GridPlan* plan, const uint32_t* occ, const uint32_t* cell_start,
+                                   const float* tx, const float* ty, const float* tz, float r_enum, int32_t k,
+                                   unsigned long long* out);
 
 }  // namespace apt
