@@ -180,8 +180,10 @@ struct PlainWs {
     double* KE2;
     uint32_t* tid;
     uint32_t* bsel;
-    uint32_t* K[2];
+    uint32_t* K[2];         // target sort keys and values (ping-pong)
     uint32_t* V[2];
+    uint32_t* KB[2];        // neighbour sort keys and values (ping-pong)
+    uint32_t* VB[2];
     uint32_t* t_rank;
     uint32_t* t_id;
     float* tx;
@@ -207,14 +209,18 @@ static PlainWs carve_plain(void* base, int64_t n) {
     w.part_off = c.take<uint32_t>(2 * kMaxCountBlocks);
     w.E2 = c.take<double>(APT_MAX_BINS + 1);
     w.KE2 = c.take<double>(APT_MAX_BINS + 1);
-    w.rs_counts = c.take<uint32_t>(256 * kSortBlocks);
-    w.rs_totals = c.take<uint32_t>(256);
+    w.rs_counts = c.take<uint32_t>(2 * 256 * kSortBlocks);   // [sort][256][G]
+    w.rs_totals = c.take<uint32_t>(2 * 256);
     w.tid = c.take<uint32_t>(N);
     w.bsel = c.take<uint32_t>(N);
     w.K[0] = c.take<uint32_t>(N);
     w.V[0] = c.take<uint32_t>(N);
     w.K[1] = c.take<uint32_t>(N);
     w.V[1] = c.take<uint32_t>(N);
+    w.KB[0] = c.take<uint32_t>(N);
+    w.VB[0] = c.take<uint32_t>(N);
+    w.KB[1] = c.take<uint32_t>(N);
+    w.VB[1] = c.take<uint32_t>(N);
     w.t_rank = c.take<uint32_t>(N);
     w.t_id = c.take<uint32_t>(N);
     w.tx = c.take<float>(N);
@@ -450,40 +456,36 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
     PlanArgs pa{G, w.part_cnt, w.part_bbox, w.part_nf, w.part_off, pp, zscale, w.plan, status};
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, pa);
     const bool all_b = q.neighbor == APT_ANY;
+    // the compaction writes both key lists (the plan is known by then)
     CompactArgs cm{cl->lab, cl->d_bnd, n, chunk, q.target, q.neighbor, q.d_srf, w.part_off, w.tid,
-                   all_b ? nullptr : w.bsel, sel_union};
+                   all_b ? nullptr : w.bsel, sel_union, w.plan, cl->xyz, zscale, w.K[0], w.V[0], w.KB[0],
+                   w.VB[0]};
     hipLaunchKernelGGL(k_compact, dim3(G), dim3(kBlock), 0, st, cm);
 
-    // target keys (block-raster order) may need one byte more than cell ids
+    // both sorts share each pass's launches; target keys (block-raster
+    // order) may need one byte more than cell ids
     const int passes = sort_passes_max(pp.cell_cap);
     const int passes_T = passes < 4 ? passes + 1 : 4;
     const int Gk = cus * 8;
     const int Gs = sort_blocks(n);
-    auto sort = [&](int is_T) {
-        for (int p = 0; p < (is_T ? passes_T : passes); ++p) {
-            SortArgs sa{w.plan, is_T, p, Gs, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.rs_counts,
-                        w.rs_totals};
-            hipLaunchKernelGGL(k_rs_upsweep, dim3(Gs), dim3(kBlock), 0, st, sa);
-            hipLaunchKernelGGL(k_rs_scan, dim3(256), dim3(kBlock), 0, st, sa);
-            hipLaunchKernelGGL(k_rs_downsweep, dim3(Gs), dim3(kBlock), 0, st, sa);
-        }
-    };
-    // targets in cell order
-    KeyArgs kt{w.plan, cl->xyz, w.tid, zscale, 1, 1, w.K[0], w.V[0]};
-    hipLaunchKernelGGL(k_keys, dim3(Gk), dim3(kBlock), 0, st, kt);
-    sort(1);
+    for (int p = 0; p < passes_T; ++p) {
+        SortSet ss{};
+        ss.s[0] = SortArgs{w.plan, 1, p, Gs, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.rs_counts, w.rs_totals};
+        ss.s[1] = SortArgs{w.plan, 0, p, Gs, {w.KB[0], w.KB[1]}, {w.VB[0], w.VB[1]},
+                           w.rs_counts + (size_t)256 * kSortBlocks, w.rs_totals + 256};
+        ss.n = p < passes ? 2 : 1;
+        hipLaunchKernelGGL(k_rs_upsweep, dim3(Gs * ss.n), dim3(kBlock), 0, st, ss);
+        hipLaunchKernelGGL(k_rs_scan, dim3(256 * ss.n), dim3(kBlock), 0, st, ss);
+        hipLaunchKernelGGL(k_rs_downsweep, dim3(Gs * ss.n), dim3(kBlock), 0, st, ss);
+    }
+    // targets in cell order and the neighbour records, in one launch;
     // occupied cells (distinct sorted keys) feed the kNN radii
     const bool occ = pp.k > 0 && !zscale;
     OrderArgs oa{w.plan, cl->xyz, w.tid, {w.V[0], w.V[1]}, w.t_rank, w.t_id, w.tx, w.ty, w.tz,
                  {w.K[0], w.K[1]}, occ ? w.strag_count + 1 : nullptr};
-    hipLaunchKernelGGL(k_take_order, dim3(Gk), dim3(kBlock), 0, st, oa);
-    // neighbours in cell order
-    KeyArgs kb{w.plan, cl->xyz, all_b ? nullptr : w.bsel, zscale, 0, 0, w.K[0], w.V[0]};
-    hipLaunchKernelGGL(k_keys, dim3(Gk), dim3(kBlock), 0, st, kb);
-    sort(0);
-    GatherArgs ga{w.plan, cl->xyz, zscale, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.bpos, w.cell_start,
+    GatherArgs ga{w.plan, cl->xyz, zscale, {w.KB[0], w.KB[1]}, {w.VB[0], w.VB[1]}, w.bpos, w.cell_start,
                   occ ? w.strag_count + 2 : nullptr};
-    hipLaunchKernelGGL(k_gather, dim3(Gk), dim3(kBlock), 0, st, ga);
+    hipLaunchKernelGGL(k_order_gather, dim3(2 * Gk), dim3(kBlock), 0, st, oa, ga, Gk);
     return hip_check("binning launch");
 }
 
@@ -708,11 +710,13 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
         KeyArgs kk{pw.plan, cl->xyz, nullptr, nullptr, 0, 0, pw.K[0], pw.V[0]};
         hipLaunchKernelGGL(k_keys, dim3(Gk), dim3(kBlock), 0, st, kk);
         for (int p = 0; p < sort_passes_max(pp.cell_cap); ++p) {
-            SortArgs sa{pw.plan, 0, p, Gs, {pw.K[0], pw.K[1]}, {pw.V[0], pw.V[1]}, pw.rs_counts,
-                        pw.rs_totals};
-            hipLaunchKernelGGL(k_rs_upsweep, dim3(Gs), dim3(kBlock), 0, st, sa);
-            hipLaunchKernelGGL(k_rs_scan, dim3(256), dim3(kBlock), 0, st, sa);
-            hipLaunchKernelGGL(k_rs_downsweep, dim3(Gs), dim3(kBlock), 0, st, sa);
+            SortSet ss{};
+            ss.s[0] = SortArgs{pw.plan, 0, p, Gs, {pw.K[0], pw.K[1]}, {pw.V[0], pw.V[1]}, pw.rs_counts,
+                               pw.rs_totals};
+            ss.n = 1;
+            hipLaunchKernelGGL(k_rs_upsweep, dim3(Gs), dim3(kBlock), 0, st, ss);
+            hipLaunchKernelGGL(k_rs_scan, dim3(256), dim3(kBlock), 0, st, ss);
+            hipLaunchKernelGGL(k_rs_downsweep, dim3(Gs), dim3(kBlock), 0, st, ss);
         }
         GatherArgs ga{pw.plan, cl->xyz, nullptr, {pw.K[0], pw.K[1]}, {pw.V[0], pw.V[1]}, pw.bpos, pw.cell_start,
                       nullptr};

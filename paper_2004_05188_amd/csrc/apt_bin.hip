@@ -254,6 +254,55 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
 constexpr int kCompactItems = 16;
 constexpr int kCompactTile = kBlock * kCompactItems;
 
+// The sort keys of the ions one tile of k_compact selected: targets
+// [t0, t1) and neighbours [b0, b1) of the lists (contiguous: the compaction
+// is stable), or every ion of [i0, i1) when the neighbours are all ions.
+__device__ __forceinline__ void compact_keys(const CompactArgs& a, uint32_t t0, uint32_t t1, uint32_t b0, uint32_t b1,
+                                              int64_t i0, int64_t i1) {
+    const GridPlan P = *a.plan;
+    const double sd = a.zscale ? *a.zscale : 1.0;
+    constexpr int U = 4;   // list entries and positions in flight per thread
+    // ion ids of list entries [j0, j0 + U * kBlock) of `list` (NULL: the
+    // entries are the ions themselves), their positions, then f(j, id, x, y, z)
+    auto run = [&](const uint32_t* list, int64_t j0, int64_t j1, auto&& f) {
+        for (int64_t jb = j0 + threadIdx.x; jb < j1; jb += (int64_t)U * kBlock) {
+            uint32_t id[U];
+            float x[U], y[U], z[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t j = jb + (int64_t)u * kBlock;
+                id[u] = j < j1 ? (list ? list[j] : (uint32_t)j) : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (jb + (int64_t)u * kBlock < j1) {
+                    x[u] = a.xyz[3 * (size_t)id[u]];
+                    y[u] = a.xyz[3 * (size_t)id[u] + 1];
+                    z[u] = a.xyz[3 * (size_t)id[u] + 2];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t j = jb + (int64_t)u * kBlock;
+                if (j < j1) {
+                    const float zz = a.zscale ? (float)((double)z[u] * sd) : z[u];
+                    f((uint32_t)j, id[u], x[u], y[u], zz);
+                }
+            }
+        }
+    };
+    run(a.tid, t0, t1, [&](uint32_t j, uint32_t, float x, float y, float z) {
+        a.tkeys[j] = target_key(P, x, y, z);
+        a.tvals[j] = j;
+    });
+    auto bkey = [&](uint32_t j, uint32_t id, float x, float y, float z) {
+        a.bkeys[j] = cell_id(P, x, y, z);
+        a.bvals[j] = id;
+    };
+    if (a.bsel) run(a.bsel, b0, b1, bkey);
+    else run(nullptr, i0, i1, bkey);   // neighbours = every ion, in index order
+}
+
 __global__ __launch_bounds__(kBlock) void k_compact(CompactArgs a) {
     __shared__ uint32_t s_cnt[2][kCompactItems][kWavesPerBlock];
     __shared__ uint32_t s_base[2][kCompactItems][kWavesPerBlock];
@@ -305,7 +354,12 @@ __global__ __launch_bounds__(kBlock) void k_compact(CompactArgs a) {
             if (mt[it] & bit) a.tid[s_base[0][it][w] + __popcll(mt[it] & lanemask_lt())] = (uint32_t)i;
             if (mb[it] & bit) a.bsel[s_base[1][it][w] + __popcll(mb[it] & lanemask_lt())] = (uint32_t)i;
         }
-        __syncthreads();
+        __syncthreads();   // the tile's list entries are visible to the whole workgroup
+        if (a.tkeys) {
+            const int64_t te = tile + kCompactTile < end ? tile + kCompactTile : end;
+            compact_keys(a, s_base[0][0][0], s_run[0], s_base[1][0][0], s_run[1], tile, te);
+            __syncthreads();
+        }
     }
 }
 
@@ -336,6 +390,7 @@ constexpr int kRsTile = kBlock * kRsItems;   // 4096
 constexpr int kRadix = 256;
 constexpr int kRsUp = 8;                     // keys per thread in flight in the upsweep
 constexpr int kGatherItems = 4;              // random position reads per thread in flight
+constexpr int kOrderItems = 2;               // the same for the (fewer) targets
 
 __device__ __forceinline__ bool rs_active(const GridPlan& P, const SortArgs& a) {
     return (uint32_t)a.pass < (a.count_is_T ? P.passes_T : P.passes);
@@ -346,7 +401,11 @@ __device__ __forceinline__ void rs_chunk(uint32_t n, int G, uint32_t* chunk) {
     *chunk = (c + kRsTile - 1u) / kRsTile * kRsTile;
 }
 
-__global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortArgs a) {
+__global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortSet set) {
+    const int q = blockIdx.x / set.s[0].G;
+    if (q >= set.n) return;
+    const SortArgs a = set.s[q];
+    const uint32_t bid = blockIdx.x - (uint32_t)q * (uint32_t)a.G;
     const GridPlan P = *a.plan;
     if (!rs_active(P, a)) return;
     const uint32_t n = a.count_is_T ? P.nT : P.nB;
@@ -355,8 +414,8 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortArgs a) {
     for (int i = threadIdx.x; i < kWavesPerBlock * kRadix; i += kBlock) (&s_h[0][0])[i] = 0;
     __syncthreads();
     uint32_t chunk;
-    rs_chunk(n, gridDim.x, &chunk);
-    const uint64_t beg = (uint64_t)blockIdx.x * chunk;
+    rs_chunk(n, a.G, &chunk);
+    const uint64_t beg = (uint64_t)bid * chunk;
     uint64_t end = beg + chunk;
     if (end > n) end = n;
     const int w = threadIdx.x / kWave;
@@ -378,18 +437,21 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortArgs a) {
     for (int d = threadIdx.x; d < kRadix; d += kBlock) {
         uint32_t s = 0;
         for (int v = 0; v < kWavesPerBlock; ++v) s += s_h[v][d];
-        a.counts[(size_t)d * gridDim.x + blockIdx.x] = s;
+        a.counts[(size_t)d * a.G + bid] = s;
     }
 }
 
 // Row scan of the digit counts: workgroup d turns counts[d][0..G) into
 // exclusive prefixes within the row and writes the row total to totals[d].
 // The downsweep adds the digit bases (a scan of the 256 totals).
-__global__ __launch_bounds__(kBlock) void k_rs_scan(SortArgs a) {
+__global__ __launch_bounds__(kBlock) void k_rs_scan(SortSet set) {
+    const int q = blockIdx.x / kRadix;
+    if (q >= set.n) return;
+    const SortArgs a = set.s[q];
     const GridPlan P = *a.plan;
     if (!rs_active(P, a)) return;
     __shared__ uint32_t s_w[kWavesPerBlock];
-    const int d = blockIdx.x, t = threadIdx.x, w = t / kWave, l = lane_id();
+    const int d = blockIdx.x - q * kRadix, t = threadIdx.x, w = t / kWave, l = lane_id();
     const int G = a.G;
     const int per = (G + kBlock - 1) / kBlock;    // G <= 4096: at most 16 per thread
     uint32_t v[16];
@@ -414,7 +476,11 @@ __global__ __launch_bounds__(kBlock) void k_rs_scan(SortArgs a) {
     if (t == kBlock - 1) a.totals[d] = run;
 }
 
-__global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortArgs a) {
+__global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortSet set) {
+    const int q = blockIdx.x / set.s[0].G;
+    if (q >= set.n) return;
+    const SortArgs a = set.s[q];
+    const uint32_t bid = blockIdx.x - (uint32_t)q * (uint32_t)a.G;
     const GridPlan P = *a.plan;
     if (!rs_active(P, a)) return;
     const uint32_t n = a.count_is_T ? P.nT : P.nB;
@@ -433,8 +499,8 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortArgs a) {
     __shared__ uint32_t s_tmp[16];
 
     uint32_t chunk;
-    rs_chunk(n, gridDim.x, &chunk);
-    const uint64_t beg = (uint64_t)blockIdx.x * chunk;
+    rs_chunk(n, a.G, &chunk);
+    const uint64_t beg = (uint64_t)bid * chunk;
     uint64_t end = beg + chunk;
     if (end > n) end = n;
     const int t = threadIdx.x, w = t / kWave, l = lane_id();
@@ -446,7 +512,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortArgs a) {
         __syncthreads();
         uint32_t base = inc - tot_d;
         for (int v = 0; v < w; ++v) base += s_tmp[v];
-        s_run[t] = base + a.counts[(size_t)t * gridDim.x + blockIdx.x];
+        s_run[t] = base + a.counts[(size_t)t * a.G + bid];
     }
     __syncthreads();
 
@@ -543,25 +609,25 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortArgs a) {
 // ------------------------------------------------------------------------
 // 6. targets in cell order as SoA: rank, ion index, position
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_take_order(OrderArgs a) {
+__device__ __forceinline__ void take_order(const OrderArgs& a, uint32_t bid, uint32_t nblk) {
     const GridPlan P = *a.plan;
     const uint32_t* __restrict__ v = a.vals[P.passes_T & 1];
     const uint32_t* __restrict__ sk = a.keys[P.passes_T & 1];   // sorted target keys
-    const uint64_t nT = P.nT, stride = (uint64_t)gridDim.x * kBlock;
+    const uint64_t nT = P.nT, stride = (uint64_t)nblk * kBlock;
     uint32_t distinct = 0;
-    // kGatherItems targets per thread in flight: the position reads are random
-    for (uint64_t t0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t0 < nT; t0 += stride * kGatherItems) {
-        uint32_t rank[kGatherItems], id[kGatherItems];
-        float x[kGatherItems], y[kGatherItems], z[kGatherItems];
+    // kOrderItems targets per thread in flight: the position reads are random
+    for (uint64_t t0 = (uint64_t)bid * kBlock + threadIdx.x; t0 < nT; t0 += stride * kOrderItems) {
+        uint32_t rank[kOrderItems], id[kOrderItems];
+        float x[kOrderItems], y[kOrderItems], z[kOrderItems];
 #pragma unroll
-        for (int u = 0; u < kGatherItems; ++u) {
+        for (int u = 0; u < kOrderItems; ++u) {
             const uint64_t t = t0 + (uint64_t)u * stride;
             rank[u] = t < nT ? v[t] : 0u;
         }
 #pragma unroll
-        for (int u = 0; u < kGatherItems; ++u) id[u] = t0 + (uint64_t)u * stride < nT ? a.tid[rank[u]] : 0u;
+        for (int u = 0; u < kOrderItems; ++u) id[u] = t0 + (uint64_t)u * stride < nT ? a.tid[rank[u]] : 0u;
 #pragma unroll
-        for (int u = 0; u < kGatherItems; ++u) {
+        for (int u = 0; u < kOrderItems; ++u) {
             if (t0 + (uint64_t)u * stride < nT) {
                 x[u] = a.xyz[3 * (size_t)id[u]];
                 y[u] = a.xyz[3 * (size_t)id[u] + 1];
@@ -569,7 +635,7 @@ __global__ __launch_bounds__(kBlock) void k_take_order(OrderArgs a) {
             }
         }
 #pragma unroll
-        for (int u = 0; u < kGatherItems; ++u) {
+        for (int u = 0; u < kOrderItems; ++u) {
             const uint64_t t = t0 + (uint64_t)u * stride;
             if (t < nT) {
                 a.t_rank[t] = rank[u];
@@ -590,21 +656,21 @@ __global__ __launch_bounds__(kBlock) void k_take_order(OrderArgs a) {
 // ------------------------------------------------------------------------
 // 7. gather into 16-byte records (x, y, z, index) and cell start offsets
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
+__device__ __forceinline__ void gather(const GatherArgs& a, uint32_t bid, uint32_t nblk) {
     const GridPlan P = *a.plan;
     const uint32_t* __restrict__ key = a.keys[P.passes & 1];
     const uint32_t* __restrict__ val = a.vals[P.passes & 1];
     const uint32_t nB = P.nB, nc = P.n_cells;
     const double sd = a.zscale ? *a.zscale : 1.0;
-    const uint32_t stride = gridDim.x * kBlock;
+    const uint32_t stride = nblk * kBlock;
     if (nB == 0) {
-        for (uint32_t c = blockIdx.x * kBlock + threadIdx.x; c <= nc; c += stride) a.cell_start[c] = 0;
+        for (uint32_t c = bid * kBlock + threadIdx.x; c <= nc; c += stride) a.cell_start[c] = 0;
         return;
     }
     // kGatherItems ions per thread in flight: the position reads are random
     const uint64_t st64 = stride;
     uint32_t distinct = 0;
-    for (uint64_t p0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x; p0 < nB; p0 += st64 * kGatherItems) {
+    for (uint64_t p0 = (uint64_t)bid * kBlock + threadIdx.x; p0 < nB; p0 += st64 * kGatherItems) {
         uint32_t id[kGatherItems];
         float x[kGatherItems], y[kGatherItems], z[kGatherItems];
 #pragma unroll
@@ -636,6 +702,13 @@ __global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) {
         distinct = wave_sum(distinct);
         if (lane_id() == 0 && distinct) atomicAdd(a.distinct, distinct);
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather(GatherArgs a) { gather(a, blockIdx.x, gridDim.x); }
+
+__global__ __launch_bounds__(kBlock) void k_order_gather(OrderArgs oa, GatherArgs ga, int32_t g_order) {
+    if ((int32_t)blockIdx.x < g_order) take_order(oa, blockIdx.x, (uint32_t)g_order);
+    else gather(ga, blockIdx.x - (uint32_t)g_order, gridDim.x - (uint32_t)g_order);
 }
 
 

@@ -42,6 +42,15 @@ struct CompactArgs {
     uint32_t* tid;          // [nT]
     uint32_t* bsel;         // [nB] or NULL (neighbours = all ions)
     int32_t sel_union;      // as CountArgs::sel_union
+    // sort keys written with the lists (plan from k_plan; NULL keys: none):
+    // targets (block-raster key, list position), neighbours (cell id, ion index)
+    const GridPlan* plan;
+    const float* xyz;
+    const double* zscale;   // NULL: unscaled
+    uint32_t* tkeys;
+    uint32_t* tvals;
+    uint32_t* bkeys;
+    uint32_t* bvals;
 };
 
 struct KeyArgs {
@@ -64,6 +73,14 @@ struct SortArgs {
     uint32_t* vals[2];
     uint32_t* counts;       // [256][G]
     uint32_t* totals;       // [256]
+};
+
+// One radix pass of up to two independent sorts in the same launches: the
+// grid holds n * G workgroups (n * 256 for the scan), sort s taking the s-th
+// block of them.
+struct SortSet {
+    SortArgs s[2];
+    int32_t n;
 };
 
 struct OrderArgs {
@@ -142,10 +159,12 @@ __global__ void k_count(CountArgs a);
 __global__ void k_plan(PlanArgs a);
 __global__ void k_compact(CompactArgs a);
 __global__ void k_keys(KeyArgs a);
-__global__ void k_rs_upsweep(SortArgs a);
-__global__ void k_rs_scan(SortArgs a);
-__global__ void k_rs_downsweep(SortArgs a);
-__global__ void k_take_order(OrderArgs a);
+__global__ void k_rs_upsweep(SortSet a);
+__global__ void k_rs_scan(SortSet a);
+__global__ void k_rs_downsweep(SortSet a);
 __global__ void k_gather(GatherArgs a);
+// the target order (first g_order workgroups) and the neighbour gather (the
+// rest) in one launch: they read and write disjoint arrays
+__global__ void k_order_gather(OrderArgs oa, GatherArgs ga, int32_t g_order);
 
 }  // namespace apt
