@@ -126,9 +126,10 @@ __device__ __forceinline__ void select_ion(uint8_t l, const float* d_bnd, int64_
 // The kNN radii from the volume the ions occupy.  The plan's first guesses
 // use the bounding box, which a needle fills less than half; once the cells
 // are known, the occupied cells of the denser set (occ[0]: distinct target
-// cells, counted by k_take_order; occ[1]: non-empty neighbour cells, counted
-// by k_gather, both zero before those kernels run) measure the specimen's
-// volume.  The kernels that search apply this to their own copy of the plan.
+// cells, counted while the targets are put in cell order; occ[1]: non-empty
+// neighbour cells, counted by the gather; both zero before k_order_gather
+// runs) measure the specimen's volume.  The kernels that search apply this
+// to their own copy of the plan.
 __device__ inline void refine_radii(GridPlan& P, const uint32_t* occ, int32_t k) {
     if (!occ || k <= 0) return;
     double box = 1.0;
