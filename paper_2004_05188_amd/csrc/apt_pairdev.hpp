@@ -129,12 +129,20 @@ __device__ __forceinline__ void enumerate_box(const GridPlan& P, const uint32_t*
                         // the whole step lies in row r0
                         idx[u] = readlane(st, r0) + (v - (e0 - readlane(len, r0)));
                     } else {
-                        for (int rr = r0; rr < kWave; ++rr) {
-                            const uint32_t o = readlane(off, rr);
-                            if (o >= b + kWave || o >= tot) break;
-                            const uint32_t s0 = readlane(st, rr), ln = readlane(len, rr);
-                            if (v >= o && v < o + ln) idx[u] = s0 + (v - o);
+                        // rows r0..r1 start before the step's end: each lane finds
+                        // the last of them starting at or before its slot (binary
+                        // lifting over the ascending row offsets, lane shuffles)
+                        const uint32_t lim = b + kWave < tot ? b + kWave : tot;
+                        const int r1 = __popcll(__ballot(off < lim)) - 1;
+                        int row = r0;
+                        for (int step = 32; step > 0; step >>= 1) {
+                            if (step > r1 - r0) continue;            // uniform
+                            const int c = row + step;
+                            const uint32_t oc = (uint32_t)__shfl((int)off, c < kWave ? c : kWave - 1, kWave);
+                            if (c <= r1 && oc <= v) row = c;
                         }
+                        const uint32_t base = (uint32_t)__shfl((int)(st - off), row, kWave);
+                        if (v < tot) idx[u] = base + v;
                     }
                 }
             }
