@@ -342,8 +342,9 @@ __global__ __launch_bounds__(kBlock, 5) void k_pair_batched(BatchPairArgs a) {  
 //         wavefront (RDF and kNN from LDS-staged neighbours); a target whose
 //         k-th neighbour lies beyond the tile's certified radius is finished
 //         by the one-target-per-wavefront search right away (kNN only)
+// (at most 128 VGPRs: four wavefronts per SIMD against three, for two small spills)
 template <int KMAX>
-__global__ __launch_bounds__(kBlock) void k_pair_batched_tile(BatchPairArgs a) {
+__global__ __launch_bounds__(kBlock, 4) void k_pair_batched_tile(BatchPairArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     const GridPlan P = *a.plan;
     const int RP = a.R * a.n_pairs;

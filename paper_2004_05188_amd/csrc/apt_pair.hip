@@ -192,8 +192,9 @@ size_t tile_lds_bytes(bool rdf, int n_bins) {
     return b + (size_t)kWavesPerBlock * kStage * sizeof(float4);
 }
 
+// (at most 128 VGPRs: four wavefronts per SIMD against three, for a few spills)
 template <int FLAGS, int KMAX>
-__global__ __launch_bounds__(kBlock) void k_pair_tile(PairArgs a) {
+__global__ __launch_bounds__(kBlock, 4) void k_pair_tile(PairArgs a) {
     constexpr bool LDS_HIST = (FLAGS & kRdfLds) != 0;
     GridPlan P = *a.plan;
     if (!P.tile_mode) return;
