@@ -33,10 +33,11 @@ size_t pair_lds_bytes(bool rdf, bool knn, int n_bins, bool hist_in_lds) {
     return b;
 }
 
-// (at most 96 VGPRs: five wavefronts per SIMD hide more of the candidate
-// loads' latency than the registers a sixth of them would need to save)
+// (at most 80 VGPRs, six wavefronts per SIMD: they hide more of the
+// candidate loads' latency than the few registers spilled outside the
+// candidate loop cost)
 template <int FLAGS, bool KNN>
-__global__ __launch_bounds__(kBlock, 5) void k_pair(PairArgs a) {
+__global__ __launch_bounds__(kBlock, 6) void k_pair(PairArgs a) {
     constexpr bool LDS_HIST = (FLAGS & kRdfLds) != 0;
     extern __shared__ __align__(16) uint8_t smem[];
     GridPlan P = *a.plan;
