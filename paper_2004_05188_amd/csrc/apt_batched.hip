@@ -240,7 +240,7 @@ __global__ void k_batch_items(BatchPairArgs a) {
 // ---- 5. the pair launch over (replicate, pair, target)
 constexpr uint64_t kChunk = 32;
 
-__global__ __launch_bounds__(kBlock, 5) void k_pair_batched(BatchPairArgs a) {   // 5 waves per SIMD (<= 96 VGPRs)
+__global__ __launch_bounds__(kBlock, 6) void k_pair_batched(BatchPairArgs a) {   // 6 waves per SIMD (<= 80 VGPRs)
     extern __shared__ __align__(16) uint8_t smem[];
     const GridPlan P = *a.plan;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
