@@ -303,7 +303,8 @@ __device__ __forceinline__ void compact_keys(const CompactArgs& a, uint32_t t0, 
     else run(nullptr, i0, i1, bkey);   // neighbours = every ion, in index order
 }
 
-__global__ __launch_bounds__(kBlock) void k_compact(CompactArgs a) {
+// (at most 64 VGPRs: eight wavefronts per SIMD for the streaming reads)
+__global__ __launch_bounds__(kBlock, 8) void k_compact(CompactArgs a) {
     __shared__ uint32_t s_cnt[2][kCompactItems][kWavesPerBlock];
     __shared__ uint32_t s_base[2][kCompactItems][kWavesPerBlock];
     __shared__ uint32_t s_run[2];
