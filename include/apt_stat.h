@@ -64,7 +64,8 @@ typedef enum {
 } apt_status;
 
 #define APT_ANY 255
-#define APT_STATUS_NONFINITE 1 /* a coordinate was NaN or infinite (such ions take part in no pair) */
+#define APT_STATUS_NONFINITE 1 /* a target or neighbour of the call had a NaN or infinite coordinate
+                                  (such ions take part in no pair) */
 #define APT_STATUS_CAPACITY 2  /* more eligible targets than the kNN row capacity */
 
 #define APT_MAX_BINS 65536     /* largest n_bins of any histogram */
@@ -187,8 +188,9 @@ apt_status apt_rdf_batched(const apt_cloud* cloud, const apt_query* pairs, int32
  *   z_scale      device double [1] (s), or NULL for s = 1
  *   h            [bins.n_bins] FP64, device, overwritten
  * bins.n_bins <= 4096.  Arithmetic after an FP32 culling test is FP64; the
- * result is reproducible bit for bit.  Ions with a non-finite (scaled)
- * position take part in no pair and set APT_STATUS_NONFINITE.
+ * result is reproducible bit for bit.  Targets and neighbours with a
+ * non-finite (scaled) position take part in no pair and set
+ * APT_STATUS_NONFINITE.
  * Workspace: APT_OP_SMOOTH. */
 apt_status apt_rdf_smooth_fwd(const apt_cloud* cloud, apt_query q, apt_bins bins, float sigma, const double* z_scale,
                               double* h, int32_t* status, void* ws, size_t ws_bytes, void* stream);

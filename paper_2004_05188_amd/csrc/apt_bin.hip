@@ -15,9 +15,12 @@
 namespace apt {
 
 // ------------------------------------------------------------------------
-// 1. counts and bounding box.  Block b owns ions [b*chunk, (b+1)*chunk),
-//    striped over threads for coalesced loads.
+// 1. counts and the bounding box of the targets and neighbours.  Block b
+//    owns ions [b*chunk, (b+1)*chunk), striped over threads for coalesced
+//    loads.
 // ------------------------------------------------------------------------
+constexpr int kCountItems = 8;
+
 __global__ __launch_bounds__(kBlock) void k_count(CountArgs a) {
     const int64_t beg = (int64_t)blockIdx.x * a.chunk;
     int64_t end = beg + a.chunk;
@@ -26,20 +29,36 @@ __global__ __launch_bounds__(kBlock) void k_count(CountArgs a) {
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     int nf = 0;
     const double sd = a.zscale ? *a.zscale : 1.0;
-    for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
-        bool isT, isB;
-        select_ion(a.lab[i], a.d_bnd, i, a.A, a.B, a.d_srf, a.sel_union, &isT, &isB);
-        nt += isT;
-        nb += isB;
-        float p[3] = {a.xyz[3 * i], a.xyz[3 * i + 1], a.xyz[3 * i + 2]};
-        if (a.zscale) p[2] = (float)((double)p[2] * sd);
+    // kCountItems labels per thread in flight (one at a time leaves the
+    // kernel latency-bound)
+    for (int64_t i0 = beg + threadIdx.x; i0 < end; i0 += (int64_t)kBlock * kCountItems) {
+        uint8_t lb[kCountItems];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            if (isfinite(p[c])) {
-                lo[c] = fminf(lo[c], p[c]);
-                hi[c] = fmaxf(hi[c], p[c]);
-            } else {
-                nf = 1;
+        for (int u = 0; u < kCountItems; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            lb[u] = i < end ? a.lab[i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kCountItems; ++u) {
+            const int64_t i = i0 + (int64_t)u * kBlock;
+            if (i >= end) continue;
+            bool isT, isB;
+            select_ion(lb[u], a.d_bnd, i, a.A, a.B, a.d_srf, a.sel_union, &isT, &isB);
+            nt += isT;
+            nb += isB;
+            // the box of the ions the call bins (targets and neighbours); the
+            // others' positions are never read
+            if (!(isT || isB)) continue;
+            float p[3] = {a.xyz[3 * i], a.xyz[3 * i + 1], a.xyz[3 * i + 2]};
+            if (a.zscale) p[2] = (float)((double)p[2] * sd);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (isfinite(p[c])) {
+                    lo[c] = fminf(lo[c], p[c]);
+                    hi[c] = fmaxf(hi[c], p[c]);
+                } else {
+                    nf = 1;
+                }
             }
         }
     }

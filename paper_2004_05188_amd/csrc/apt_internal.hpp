@@ -18,7 +18,7 @@ constexpr uint32_t kNone = 0xFFFFFFFFu;
 // Device-resident description of the cell grid of one call, written by
 // k_plan and read by every later kernel (launch grids do not depend on it).
 struct GridPlan {
-    float lo[3];        // bounding box of all finite positions
+    float lo[3];        // bounding box of the finite positions of the targets and neighbours
     float hi[3];
     float h;            // cell edge (nm)
     float inv_h;
