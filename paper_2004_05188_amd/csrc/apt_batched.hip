@@ -433,12 +433,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_pair_batched_tile(BatchPairArgs a
                                   : nullptr;
         if (kh && certified) {
             int b = a.kb_nbins;
-            if (kth != ~0ull) {
-                const uint32_t j = (uint32_t)kth;
-                b = exact_bin(exact_D2(px, py, pz, a.xyz[3 * (size_t)j], a.xyz[3 * (size_t)j + 1],
-                                       a.xyz[3 * (size_t)j + 2]),
-                              a.KE2, a.kb_nbins, a.kb_inv_w64);
-            }
+            if (kth != ~0ull) b = key_bin(kth, a.xyz, px, py, pz, a.KE2, a.kb_nbins, a.kb_inv_w64);
             atomicAdd((unsigned long long*)&kh[b], 1ull);
         }
         // the rest: one target at a time over the whole wavefront

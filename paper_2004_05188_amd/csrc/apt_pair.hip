@@ -289,12 +289,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_pair_tile(PairArgs a) {
                 }
                 if (a.knn_hist) {
                     int b = a.kb_nbins;
-                    if (found == a.k) {
-                        const uint32_t j = (uint32_t)kth;
-                        b = exact_bin(exact_D2(px, py, pz, a.xyz[3 * (size_t)j], a.xyz[3 * (size_t)j + 1],
-                                               a.xyz[3 * (size_t)j + 2]),
-                                      a.KE2, a.kb_nbins, a.kb_inv_w64);
-                    }
+                    if (found == a.k) b = key_bin(kth, a.xyz, px, py, pz, a.KE2, a.kb_nbins, a.kb_inv_w64);
                     atomicAdd((unsigned long long*)&a.knn_hist[b], 1ull);
                 }
             }

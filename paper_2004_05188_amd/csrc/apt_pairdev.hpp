@@ -591,13 +591,29 @@ __device__ __forceinline__ void flush_hist(uint32_t* hist_l, uint64_t* hist_g, i
     wave_sync();
 }
 
-// Bin of the k-th neighbour's FP64 distance (kb_nbins when missing).
+// Bin of the distance of a kNN key (bits(d2f) << 32 | index) in the k-th
+// distance histogram: the FP32 bin of the key's squared distance, exact
+// away from the edges (the same band as the RDF's fast path: the FP32
+// squared distance, root and scaling err by a few ulps); inside the band,
+// the FP64 distance of the stored positions decides.
+__device__ __forceinline__ int key_bin(uint64_t key, const float* xyz, float px, float py, float pz,
+                                       const double* KE2, int kb_nbins, double kb_inv_w64) {
+    const float t = __builtin_amdgcn_sqrtf(u2f((uint32_t)(key >> 32))) * (float)kb_inv_w64;
+    if (!(t < (float)kb_nbins + 2.0f)) return kb_nbins;
+    const float band = (float)fmin(0.25, fmax(1e-6 * kb_inv_w64, 4e-6 * (double)kb_nbins));
+    const int bf = (int)t;
+    const float fr = t - (float)bf;
+    if (fr > band && fr < 1.0f - band) return bf < kb_nbins ? bf : kb_nbins;
+    const uint32_t j = (uint32_t)key;
+    return exact_bin(exact_D2(px, py, pz, xyz[3 * (size_t)j], xyz[3 * (size_t)j + 1], xyz[3 * (size_t)j + 2]),
+                     KE2, kb_nbins, kb_inv_w64);
+}
+
+// Bin of the k-th neighbour's distance (kb_nbins when missing).
 __device__ __forceinline__ int kth_bin(int found, int k, const uint64_t* kbuf, const float* xyz, float px,
                                        float py, float pz, const double* KE2, int kb_nbins, double kb_inv_w64) {
     if (found < k) return kb_nbins;
-    const uint32_t j = (uint32_t)kbuf[k - 1];
-    return exact_bin(exact_D2(px, py, pz, xyz[3 * (size_t)j], xyz[3 * (size_t)j + 1], xyz[3 * (size_t)j + 2]),
-                     KE2, kb_nbins, kb_inv_w64);
+    return key_bin(kbuf[k - 1], xyz, px, py, pz, KE2, kb_nbins, kb_inv_w64);
 }
 
 }  // namespace apt
