@@ -7,7 +7,7 @@ RDF histogram and exact kNN rows plus the k-th distance histogram).
 Inputs are generated on the host (seeded, synthetic), copied to HBM once,
 and are resident when the timed region starts.
 
-Prints one JSON line (rank 0).  --gpus above 1 is refused: this build
+Prints one JSON line (rank 0).  --gpus above 1 is refused: the benchmark
 measures one GPU.
 """
 from __future__ import annotations
@@ -216,8 +216,8 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy 5 times (scale of the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              f"(the multi-GPU sharding is described in DESIGN.md but not run)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library runs on "
+              f"one GPU; how the path would shard over several is a design note, not code)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
