@@ -232,7 +232,10 @@ __device__ __forceinline__ int run_target(const GridPlan& P, const PairTask& T, 
         uint64_t m = __ballot(q);
         if (m) {
             int nn = __popcll(m);
-            if (cnt + nn > kKnnCap) {
+            // for small k the buffer is cut at 64 keys (once it holds k),
+            // so that cuts and the final sort stay within one wavefront's
+            // rank sort and later candidates meet the raised bar sooner
+            if (cnt + nn > (T.k <= 32 ? kWave : kKnnCap) && cnt >= T.k) {
                 // keep the k smallest keys, raise the bar to the k-th
                 wave_sort_keys(T.kbuf, cnt);
                 cnt = T.k;
