@@ -422,10 +422,13 @@ __device__ __forceinline__ void rs_chunk(uint32_t n, int G, uint32_t* chunk) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortSet set) {
-    const int q = blockIdx.x / set.s[0].G;
+    // sort 0 takes the first s[0].G workgroups, sort 1 the next s[1].G
+    const uint32_t g0 = (uint32_t)set.s[0].G;
+    const int q = blockIdx.x < g0 ? 0 : 1;
     if (q >= set.n) return;
     const SortArgs a = set.s[q];
-    const uint32_t bid = blockIdx.x - (uint32_t)q * (uint32_t)a.G;
+    const uint32_t bid = blockIdx.x - (q ? g0 : 0u);
+    if (bid >= (uint32_t)a.G) return;
     const GridPlan P = *a.plan;
     if (!rs_active(P, a)) return;
     const uint32_t n = a.count_is_T ? P.nT : P.nB;
@@ -497,10 +500,13 @@ __global__ __launch_bounds__(kBlock) void k_rs_scan(SortSet set) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortSet set) {
-    const int q = blockIdx.x / set.s[0].G;
+    // sort 0 takes the first s[0].G workgroups, sort 1 the next s[1].G
+    const uint32_t g0 = (uint32_t)set.s[0].G;
+    const int q = blockIdx.x < g0 ? 0 : 1;
     if (q >= set.n) return;
     const SortArgs a = set.s[q];
-    const uint32_t bid = blockIdx.x - (uint32_t)q * (uint32_t)a.G;
+    const uint32_t bid = blockIdx.x - (q ? g0 : 0u);
+    if (bid >= (uint32_t)a.G) return;
     const GridPlan P = *a.plan;
     if (!rs_active(P, a)) return;
     const uint32_t n = a.count_is_T ? P.nT : P.nB;

@@ -75,9 +75,9 @@ struct SortArgs {
     uint32_t* totals;       // [256]
 };
 
-// One radix pass of up to two independent sorts in the same launches: the
-// grid holds n * G workgroups (n * 256 for the scan), sort s taking the s-th
-// block of them.
+// One radix pass of up to two independent sorts in the same launches: sort
+// 0 takes the first s[0].G workgroups, sort 1 the next s[1].G (the scan: 256
+// each).
 struct SortSet {
     SortArgs s[2];
     int32_t n;
