@@ -391,36 +391,8 @@ static apt_status hip_check(const char* where) {
 }
 
 // ------------------------------------------------------- small kernels --
-struct InitArgs {
-    int32_t* status;
-    uint64_t* h1;
-    int32_t n1;
-    uint64_t* h2;
-    int32_t n2;
-    int64_t* n_targets;
-    uint32_t* counter;
-    // squared bin edges of the RDF and of the k-th distance histogram, or NULL
-    double* e2;
-    float e2_rmax;
-    int32_t e2_nbins;
-    double* ke2;
-    float ke2_rmax;
-    int32_t ke2_nbins;
-};
 __global__ void k_init(InitArgs a) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x, st = gridDim.x * blockDim.x;
-    if (a.e2) fill_edges(a.e2, a.e2_rmax, a.e2_nbins, t, st);
-    if (a.ke2) fill_edges(a.ke2, a.ke2_rmax, a.ke2_nbins, t, st);
-    if (t == 0) {
-        if (a.status) *a.status = 0;
-        if (a.n_targets) *a.n_targets = 0;
-        if (a.counter)
-            for (int c = 0; c < 4; ++c) a.counter[c] = 0;   // [0] stragglers, [1..2] occupied cells
-    }
-    if (a.h1)
-        for (int b = t; b < a.n1; b += st) a.h1[b] = 0;
-    if (a.h2)
-        for (int b = t; b < a.n2; b += st) a.h2[b] = 0;
+    init_body(a, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 struct FinishArgs {
@@ -444,7 +416,7 @@ __global__ void k_finish(FinishArgs a) {
 // role.
 static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams& pp, const PlainWs& w,
                               int32_t* status, hipStream_t st, const double* zscale = nullptr,
-                              int sel_union = 0) {
+                              int sel_union = 0, const InitArgs* init = nullptr) {
     const int64_t n = cl->n;
     const int G = count_blocks(n);
     const int64_t chunk = count_chunk(n, G);
@@ -452,6 +424,10 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
 
     CountArgs ca{cl->xyz, cl->lab, cl->d_bnd, n, chunk, q.target, q.neighbor, q.d_srf, zscale,
                  w.part_cnt, w.part_bbox, w.part_nf, sel_union};
+    if (init) {
+        ca.init = *init;
+        ca.do_init = 1;
+    }
     hipLaunchKernelGGL(k_count, dim3(G), dim3(kBlock), 0, st, ca);
     PlanArgs pa{G, w.part_cnt, w.part_bbox, w.part_nf, w.part_off, pp, zscale, w.plan, status};
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, pa);
@@ -529,7 +505,7 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
                 knn_hist ? kb->n_bins + 1 : 0, n_targets, w.strag_count,
                 do_rdf ? w.E2 : nullptr, do_rdf ? rb->r_max : 0.0f, do_rdf ? rb->n_bins : 0,
                 knn_hist ? w.KE2 : nullptr, knn_hist ? kb->r_max : 0.0f, knn_hist ? kb->n_bins : 0};
-    hipLaunchKernelGGL(k_init, dim3(64), dim3(256), 0, st, ia);
+    // (zeroed and filled by the binning's first kernel)
 
     const apt_tuning tu = tuning();
     const bool rdf_lds = do_rdf && pair_lds_bytes(true, do_knn, rb->n_bins, true) <= kMaxLds;
@@ -545,7 +521,7 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     pp.r_enum = do_rdf ? rb->r_max : 0.0f;
     {
         TraceSpan span("binning", st);
-        if ((s = run_binning(cl, q, pp, w, status, st)) != APT_OK) return s;
+        if ((s = run_binning(cl, q, pp, w, status, st, nullptr, 0, &ia)) != APT_OK) return s;
     }
     if (cand) {
         hipLaunchKernelGGL(k_count_candidates, dim3(device_info().cus * 8), dim3(kBlock), 0, st, w.plan,

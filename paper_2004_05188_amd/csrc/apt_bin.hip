@@ -22,6 +22,7 @@ namespace apt {
 constexpr int kCountItems = 8;
 
 __global__ __launch_bounds__(kBlock) void k_count(CountArgs a) {
+    if (a.do_init) init_body(a.init, blockIdx.x * kBlock + threadIdx.x, gridDim.x * kBlock);
     const int64_t beg = (int64_t)blockIdx.x * a.chunk;
     int64_t end = beg + a.chunk;
     if (end > a.n) end = a.n;

@@ -4,6 +4,43 @@
 
 namespace apt {
 
+// What a call zeroes or fills before its work: status word, output
+// histograms, target count, counters, squared bin edges (any may be NULL).
+struct InitArgs {
+    int32_t* status;
+    uint64_t* h1;
+    int32_t n1;
+    uint64_t* h2;
+    int32_t n2;
+    int64_t* n_targets;
+    uint32_t* counter;      // [4]: [0] stragglers, [1..2] occupied cells
+    // squared bin edges of the RDF and of the k-th distance histogram, or NULL
+    double* e2;
+    float e2_rmax;
+    int32_t e2_nbins;
+    double* ke2;
+    float ke2_rmax;
+    int32_t ke2_nbins;
+};
+
+__device__ inline void fill_edges(double* E2, float r_max, int n_bins, int t, int stride);
+
+// Threads t, t + stride, ... of a grid do the work of `a`.
+__device__ inline void init_body(const InitArgs& a, int t, int st) {
+    if (a.e2) fill_edges(a.e2, a.e2_rmax, a.e2_nbins, t, st);
+    if (a.ke2) fill_edges(a.ke2, a.ke2_rmax, a.ke2_nbins, t, st);
+    if (t == 0) {
+        if (a.status) *a.status = 0;
+        if (a.n_targets) *a.n_targets = 0;
+        if (a.counter)
+            for (int c = 0; c < 4; ++c) a.counter[c] = 0;
+    }
+    if (a.h1)
+        for (int b = t; b < a.n1; b += st) a.h1[b] = 0;
+    if (a.h2)
+        for (int b = t; b < a.n2; b += st) a.h2[b] = 0;
+}
+
 struct CountArgs {
     const float* xyz;
     const uint8_t* lab;
@@ -17,6 +54,9 @@ struct CountArgs {
     float* part_bbox;       // [G][6]
     int32_t* part_nf;       // [G]
     int32_t sel_union;      // 1: targets and neighbours are both (eligible A) or B
+    // the call's initial zeroing, done by the same launch (do_init = 1)
+    InitArgs init;
+    int32_t do_init;
 };
 
 struct PlanArgs {
