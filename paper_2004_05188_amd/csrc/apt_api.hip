@@ -438,22 +438,22 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
                    w.VB[0]};
     hipLaunchKernelGGL(k_compact, dim3(G), dim3(kBlock), 0, st, cm);
 
-    // both sorts share each pass's launches; target keys (block-raster
-    // order) may need one byte more than cell ids
+    // both sorts share each pass's launches; target keys never need more
+    // bytes than cell ids (the plan falls back to cell order when its
+    // block-raster keys would)
     const int passes = sort_passes_max(pp.cell_cap);
-    const int passes_T = passes < 4 ? passes + 1 : 4;
     const int Gk = cus * 8;
     // the target sort on half the workgroups: targets are usually the rarer
     // species (on the needle's queries binning −2 to −5.5 %; a query whose
     // targets are the majority species bins ≈ 5 % slower)
     const int Gs = sort_blocks(n), GsT = Gs / 2;
-    for (int p = 0; p < passes_T; ++p) {
+    for (int p = 0; p < passes; ++p) {
         SortSet ss{};
         ss.s[0] = SortArgs{w.plan, 1, p, GsT, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.rs_counts, w.rs_totals};
         ss.s[1] = SortArgs{w.plan, 0, p, Gs, {w.KB[0], w.KB[1]}, {w.VB[0], w.VB[1]},
                            w.rs_counts + (size_t)256 * kSortBlocks, w.rs_totals + 256};
-        ss.n = p < passes ? 2 : 1;
-        const int grid = GsT + (ss.n > 1 ? Gs : 0);
+        ss.n = 2;
+        const int grid = GsT + Gs;
         hipLaunchKernelGGL(k_rs_upsweep, dim3(grid), dim3(kBlock), 0, st, ss);
         hipLaunchKernelGGL(k_rs_scan, dim3(256 * ss.n), dim3(kBlock), 0, st, ss);
         hipLaunchKernelGGL(k_rs_downsweep, dim3(grid), dim3(kBlock), 0, st, ss);

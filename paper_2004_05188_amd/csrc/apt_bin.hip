@@ -235,12 +235,16 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
     uint32_t passes = 1;
     while (passes < 4 && ((P.n_cells - 1u) >> (8u * passes)) != 0u) ++passes;
     P.passes = passes;
-    // targets in block-raster order when its keys fit 32 bits
+    // targets in block-raster order when its keys need no more bytes than
+    // the largest cell id the workspace allows (the radix passes launched
+    // for both sorts), else in cell order
     {
         const uint64_t nbx = ((uint64_t)P.dim[0] + 7) / 8, nby = ((uint64_t)P.dim[1] + 7) / 8,
                        nbz = ((uint64_t)P.dim[2] + 7) / 8;
         const uint64_t kmax = nbx * nby * nbz * 512u - 1u;
-        if (kmax <= 0xFFFFFFFFull) {
+        uint32_t cap_bytes = 1;
+        while (cap_bytes < 4 && ((pp.cell_cap - 1u) >> (8u * cap_bytes)) != 0u) ++cap_bytes;
+        if (kmax < (1ull << (8u * cap_bytes))) {
             P.tblock = 8;
             P.nbx = (int32_t)nbx;
             P.nby = (int32_t)nby;
