@@ -519,6 +519,7 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     // tiles need an LDS histogram and at most 16 kNN keys per lane
     pp.tile_policy = (!tile_fits || (do_knn && k > 16)) ? 1 : tu.tile_policy;
     pp.r_enum = do_rdf ? rb->r_max : 0.0f;
+    pp.h_shrink = 0.7f;
     {
         TraceSpan span("binning", st);
         if ((s = run_binning(cl, q, pp, w, status, st, nullptr, 0, &ia)) != APT_OK) return s;

@@ -50,6 +50,9 @@ struct PlanParams {
                           // sharing staged candidates, 3: one target per lane
     float r_enum;       // RDF enumeration radius (0: no RDF)
     float tile_occ;     // aimed-for neighbours per cell with 64 targets per wavefront (<= 0: occ)
+    // > 0: one target per wavefront also tries the edge h_min * h_shrink and
+    // keeps it when the cell ids need no more bytes (no extra radix pass)
+    float h_shrink = 0.0f;
 };
 
 // ---------------------------------------------------------------- waves --
