@@ -465,9 +465,11 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
                  {w.K[0], w.K[1]}, occ ? w.strag_count + 1 : nullptr};
     GatherArgs ga{w.plan, cl->xyz, zscale, {w.KB[0], w.KB[1]}, {w.VB[0], w.VB[1]}, w.bpos, w.cell_start,
                   occ ? w.strag_count + 2 : nullptr};
-    // (half the usual grid per half: for the neighbour gather, more records
-    // per thread in flight beat more workgroups, −2 % on 7.5e6 records)
-    hipLaunchKernelGGL(k_order_gather, dim3(Gk), dim3(kBlock), 0, st, oa, ga, Gk / 2);
+    // (up to 2^25 ions half the usual grid per half: more records per thread
+    // beat more workgroups, −2 % on 7.5e6 records; beyond, the full grid:
+    // at 2e9 records the half grid's fewer loads in flight cost 2 %)
+    const int Go = n > ((int64_t)1 << 25) ? Gk : Gk / 2;
+    hipLaunchKernelGGL(k_order_gather, dim3(2 * Go), dim3(kBlock), 0, st, oa, ga, Go);
     return hip_check("binning launch");
 }
 
