@@ -36,7 +36,7 @@ K, R_MAX, N_BINS, KB_RMAX, KB_NBINS = 10, 2.0, 200, 5.0, 5000
 # HBM bytes per k_pair launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
 # scaled by a plain-copy calibration; valid only for the kernel source they
 # were taken on (profiles/k_pair_frustum7m_hbm_counters.md)
-PAIR_TRAFFIC = {"frustum7m": (200.1e6, "36fb0ed37bbd0285")}
+PAIR_TRAFFIC = {"frustum7m": (200.0e6, "36fb0ed37bbd0285")}
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk (packed FMA)
 FLOP_PER_PAIR = 8                 # 3 sub, 1 mul, 2 fma per pair distance
 # candidate pair-evaluations per second the FP32 vector units allow: 256 CU x
