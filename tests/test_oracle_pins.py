@@ -498,3 +498,133 @@ def test_smooth_local_fd_equals_full_recompute(orc, synth):
         g, _ = orc.smooth_bwd(xyz, lab, d, *args, sc, 2 * (h - target))
         gi = g[ions]
         assert np.abs(fd - gi).max() <= 2e-3 * np.abs(gi).max()
+
+
+# --------------------------------------------------------------------------
+# exact rounding: the fixed FP32 and FP64 distance expressions, bit for bit
+# --------------------------------------------------------------------------
+
+def _round_binary(x, mant_bits, emin):
+    """x (a Fraction) rounded to nearest, ties to even, in a binary format with
+    `mant_bits` significand bits and smallest normal exponent `emin`
+    (subnormals included; no overflow occurs for the values used here)."""
+    from fractions import Fraction
+
+    if x == 0:
+        return Fraction(0)
+    sign = -1 if x < 0 else 1
+    a = abs(x)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    e = max(e, emin)
+    q = Fraction(2) ** (e - (mant_bits - 1))
+    m = a / q
+    n = m.numerator // m.denominator
+    rem = m - n
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and n % 2 == 1):
+        n += 1
+    return sign * n * q
+
+
+def _rn32(x):
+    return _round_binary(x, 24, -126)
+
+
+def _rn64(x):
+    return _round_binary(x, 53, -1022)
+
+
+def _fr(v):
+    from fractions import Fraction
+
+    return Fraction(float(v))
+
+
+def _d2f_variants(a, b):
+    """Exact values of three FP32 evaluation orders of the squared distance:
+    the defined one fmaf(dz,dz,fmaf(dy,dy,dx*dx)), the unfused sum, and the
+    other nesting fmaf(dx,dx,fmaf(dy,dy,dz*dz))."""
+    dx, dy, dz = (_rn32(_fr(b[c]) - _fr(a[c])) for c in range(3))
+    defined = _rn32(dz * dz + _rn32(dy * dy + _rn32(dx * dx)))
+    unfused = _rn32(_rn32(_rn32(dx * dx) + _rn32(dy * dy)) + _rn32(dz * dz))
+    other = _rn32(dx * dx + _rn32(dy * dy + _rn32(dz * dz)))
+    return defined, unfused, other
+
+
+def test_d2f_fused_order_bit_exact(orc):
+    # Random FP32 pairs at the coordinate scales of the workloads; the
+    # expected bits come from exact rational arithmetic with one rounding to
+    # FP32 per step of the defined expression.  Cases where an unfused sum or
+    # the other nesting rounds differently must exist among them, so that a
+    # plausible slip in the oracle's expression fails here.
+    rng = np.random.default_rng(20040518)
+    discriminating = 0
+    for scale, spread in ((1.0, 2.0), (150.0, 2.0), (3000.0, 2.0), (20.0, 0.3)):
+        for _ in range(400):
+            a = (rng.uniform(0.0, scale, 3)).astype(np.float32)
+            b = (a.astype(np.float64) + rng.uniform(-spread, spread, 3)).astype(np.float32)
+            defined, unfused, other = _d2f_variants(a, b)
+            got = orc.d2f(a, b)
+            assert got == float(defined), (a, b, got, float(defined))
+            if defined != unfused and defined != other:
+                discriminating += 1
+    assert discriminating >= 20, discriminating
+
+
+def test_D2_association_order_bit_exact(orc):
+    # FP64 squared distance of the stored FP32 values, ((dx*dx + dy*dy) + dz*dz)
+    # with every operation rounded on its own.  The differences are exact in
+    # FP64 for FP32 inputs; a square or a sum rounds only when the
+    # differences span more than ~26 significant bits (at the workloads' large
+    # coordinates every step is exact).  Two families make the alternatives
+    # visible: coordinates of unlike magnitudes (inexact squares: a fused
+    # last step differs) and one long with two tiny differences (each tiny
+    # square below half an ulp of the first: the other association differs).
+    rng = np.random.default_rng(7)
+    other_differs = fused_differs = 0
+    for it in range(2000):
+        if it % 2:
+            a = rng.uniform(0.0, 0.1, 3).astype(np.float32)
+            b = rng.uniform(-1.0, 1.0, 3).astype(np.float32)
+        else:
+            a = np.zeros(3, np.float32)
+            tiny = rng.choice([-1.0, 1.0], 2) * rng.uniform(0.7, 1.0, 2) * 2.0 ** -26.5
+            b = np.array([rng.uniform(0.5, 1.0), *tiny], np.float32)
+        dx, dy, dz = (_fr(b[c]) - _fr(a[c]) for c in range(3))
+        sx, sy, sz = _rn64(dx * dx), _rn64(dy * dy), _rn64(dz * dz)
+        defined = _rn64(_rn64(sx + sy) + sz)
+        other = _rn64(sx + _rn64(sy + sz))
+        fused = _rn64(dz * dz + _rn64(sx + sy))
+        assert orc.D2(a, b) == float(defined), (a, b)
+        other_differs += defined != other
+        fused_differs += defined != fused
+    assert other_differs >= 100 and fused_differs >= 20, (other_differs, fused_differs)
+
+
+def test_splitmix64_seed_shift(orc):
+    # the state after m steps from seed 0 is m * golden gamma (mod 2^64): the
+    # stream of that seed is the seed-0 stream shifted by m
+    gamma = 0x9E3779B97F4A7C15
+    for m in (1, 2, 5, 1000):
+        s = (gamma * m) % (1 << 64)
+        for i in range(8):
+            assert orc.splitmix64(s, i) == orc.splitmix64(0, i + m)
+
+
+@pytest.mark.parametrize("n", [5, 9, 17, 33, 50])
+def test_permutation_direction_bit_exact(orc, n):
+    # out[i] = lab[pi(i)], pi = the indices sorted by (key(i), i): distinct
+    # labels make the direction visible (out[pi(i)] = lab[i] differs)
+    lab = np.arange(n, dtype=np.uint8)[::-1].copy()
+    inverse_differs = 0
+    for seed in (0, 1, 12345, 2**63 + 11):
+        keys = [orc.splitmix64(seed, i) for i in range(n)]
+        pi = sorted(range(n), key=lambda i: (keys[i], i))
+        expect = np.array([lab[j] for j in pi], dtype=np.uint8)
+        got = orc.permute_labels(lab, seed)
+        assert np.array_equal(got, expect), (seed, got, expect)
+        inv = np.empty_like(lab)
+        inv[np.array(pi)] = lab
+        inverse_differs += not np.array_equal(inv, expect)
+    assert inverse_differs >= 3
