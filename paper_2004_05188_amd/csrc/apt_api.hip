@@ -111,8 +111,8 @@ struct TraceSpan {
 
 // Grid of a one-target-per-wavefront kernel: exactly the workgroups that
 // fit on the device at once, so that the static deal of targets runs in a
-// single round (a second, partly filled round would leave CUs idle).  A
-// multiple of the CU count, hence of the XCD count.
+// single round (a second, partly filled round would leave CUs idle),
+// rounded down to a multiple of the XCD count.
 // The occupancy query is remembered per (device, kernel, LDS bytes): it
 // costs host time on every call otherwise.
 template <class K>
@@ -129,7 +129,10 @@ static int resident_grid(K kern, size_t lds) {
     }
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, kBlock, lds) != hipSuccess || nb < 1) nb = 2;
-    const int grid = device_info().cus * nb;
+    // the kernels deal items per XCD (workgroup b on XCD b mod 8, gridDim.x / 8
+    // workgroups each): a multiple of kXcd covers every item exactly once
+    int grid = device_info().cus * nb / kXcd * kXcd;
+    if (grid < kXcd) grid = kXcd;
     std::lock_guard<std::mutex> g(mu);
     cache[key] = grid;
     return grid;
@@ -645,6 +648,11 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
     if (!status) return fail(APT_E_ARG, "status is NULL");
     if (batched_lds_bytes(rb.n_bins) > kMaxLds)
         return fail(APT_E_UNSUPPORTED, "batched RDF supports at most 3072 bins");
+    // the output histograms are zeroed and indexed with 32-bit counts
+    const int64_t nh = (int64_t)n_rep * n_pairs * rb.n_bins;
+    const int64_t nk = knn_hist ? (int64_t)n_rep * n_pairs * ((int64_t)kb.n_bins + 1) : 0;
+    if (nh > (int64_t)INT32_MAX || nk > (int64_t)INT32_MAX)
+        return fail(APT_E_UNSUPPORTED, "n_rep * n_pairs * bins must stay below 2^31 for each histogram");
     // species -> class; every species of the pairs gets one class
     uint8_t slot[256];
     int C = 0;
@@ -672,8 +680,6 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
     const int cus = device_info().cus;
 
     // zero the outputs and the status word, edge tables
-    const int64_t nh = (int64_t)n_rep * n_pairs * rb.n_bins;
-    const int64_t nk = knn_hist ? (int64_t)n_rep * n_pairs * (kb.n_bins + 1) : 0;
     InitArgs ia{status, rdf_hist, (int32_t)nh, knn_hist, (int32_t)nk, nullptr, nullptr,
                 w.plain.E2, rb.r_max, rb.n_bins, knn_hist ? w.plain.KE2 : nullptr, kb.r_max, kb.n_bins};
     hipLaunchKernelGGL(k_init, dim3(cus * 4), dim3(256), 0, st, ia);

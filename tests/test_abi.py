@@ -174,3 +174,22 @@ def test_smooth_window_limit(aptstat):
     # sigma <= 0 and NaN: invalid
     for bad in (0.0, -1.0, math.nan):
         assert L.apt_rdf_smooth_fwd(_cloud(aptstat), q, bins, ctypes.c_float(bad), None, p, p, ws, big, None) == -1
+
+
+def test_batched_histogram_size_limit(aptstat):
+    # the batched histograms are zeroed and indexed with 32-bit counts: calls
+    # whose n_rep * n_pairs * bins reach 2^31 are rejected before GPU work
+    L = aptstat.lib()
+    p = ctypes.c_void_p(0x5000)
+    ws, big = ctypes.c_void_p(0x100000), 1 << 40
+    qs = (aptstat._Query * 16)(*[aptstat._query(a % 3, (a + 1) % 3, 1.0) for a in range(16)])
+    n_rep = 2048
+    seeds = (ctypes.c_uint64 * n_rep)(*range(1, n_rep + 1))
+    rb, kb = aptstat._bins(2.0, 200), aptstat._bins(5.0, 65536)
+    assert L.apt_rdf_batched(_cloud(aptstat), qs, 16, seeds, n_rep, rb, 10, kb, p, p, None, p, ws, big,
+                             None) == -3
+    assert "2^31" in _err(aptstat)
+    # the same call without the k-th histogram passes the size check (and
+    # stops at the workspace check instead)
+    assert L.apt_rdf_batched(_cloud(aptstat), qs, 16, seeds, n_rep, rb, 10, kb, p, None, None, p, None, big,
+                             None) == -2
