@@ -111,6 +111,21 @@ size_t apt_workspace_size(int32_t op, int64_t n, int32_t n_pairs, int32_t n_rep)
 apt_status apt_rdf(const apt_cloud* cloud, apt_query q, apt_bins bins, uint64_t* hist,
                    int32_t* status, void* ws, size_t ws_bytes, void* stream);
 
+/* apt_rdf without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the call's scratch is a static device
+ * array of 128 MiB (APT_NOALLOC_SCRATCH_BYTES) that each GPU the library runs
+ * on holds from the library's load until the process ends.  Arguments,
+ * results and errors as apt_rdf; clouds whose apt_rdf workspace exceeds the
+ * array (about 1.5 million ions) return APT_E_UNSUPPORTED before any GPU
+ * work.  The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine).  Every call on one GPU shares that GPU's array and
+ * leaves its contents behind: calls that overlap on one GPU (concurrent
+ * streams or host threads) race and must be ordered by the caller. */
+#define APT_NOALLOC_SCRATCH_BYTES (128u << 20)
+apt_status apt_rdf_noalloc(const apt_cloud* cloud, apt_query q, apt_bins bins, uint64_t* hist,
+                           int32_t* status, void* stream);
+
 /* kNN of one query (paper, Methods: kNN as the distribution of distances to
  * the k-th nearest neighbour of a given type).  Rows are for the eligible
  * targets in ascending ion index; the search radius is unbounded unless

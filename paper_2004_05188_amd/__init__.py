@@ -70,6 +70,7 @@ _SIGS = {
     "apt_rdf_batched": ([ctypes.POINTER(_Cloud), _P, ctypes.c_int32, _P, ctypes.c_int32, _Bins, ctypes.c_int32,
                          _Bins, _P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_rdf": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "apt_rdf_noalloc": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, _P, _P], ctypes.c_int),
     "apt_knn": ([ctypes.POINTER(_Cloud), _Query, ctypes.c_int32, ctypes.c_float, ctypes.c_int64, _P, _P, _P,
                  _Bins, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_knn_rdf": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, ctypes.c_int32, ctypes.c_float, ctypes.c_int64,

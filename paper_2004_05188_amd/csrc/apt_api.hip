@@ -928,6 +928,33 @@ static apt_status run_smooth(bool bwd, const apt_cloud* cl, apt_query q, apt_bin
     return hip_check("smoothed RDF launch");
 }
 
+// ------------------------------------------------------ static scratch --
+// The workspace of apt_rdf_noalloc: one array per device, held from the
+// library's load until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol): its device address, taken once per device with that device
+// current, is what the launches receive.
+constexpr size_t kStaticScratchBytes = (size_t)APT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];
+
+static apt_status static_scratch(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(APT_E_HIP, "hipGetDevice failed");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(APT_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return APT_OK;
+}
+
 }  // namespace apt
 
 using namespace apt;
@@ -1067,6 +1094,21 @@ apt_status apt_rdf(const apt_cloud* cloud, apt_query q, apt_bins bins, uint64_t*
                    void* ws, size_t ws_bytes, void* stream) {
     return run_plain(cloud, q, &bins, hist, 0, INFINITY, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
                      nullptr, status, ws, ws_bytes, stream);
+}
+
+apt_status apt_rdf_noalloc(const apt_cloud* cloud, apt_query q, apt_bins bins, uint64_t* hist, int32_t* status,
+                           void* stream) {
+    apt_status s;
+    if ((s = check_cloud(cloud)) != APT_OK) return s;
+    const size_t need = carve_plain(nullptr, cloud->n).bytes;
+    if (need > kStaticScratchBytes)
+        return fail(APT_E_UNSUPPORTED, "apt_rdf_noalloc: " + std::to_string(cloud->n) + " ions need " +
+                                           std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                                           std::to_string(kStaticScratchBytes));
+    void* ws = nullptr;
+    if ((s = static_scratch(&ws)) != APT_OK) return s;
+    return run_plain(cloud, q, &bins, hist, 0, INFINITY, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                     status, ws, kStaticScratchBytes, stream);
 }
 
 apt_status apt_knn(const apt_cloud* cloud, apt_query q, int32_t k, float r_knn_max, int64_t capacity,
