@@ -2,10 +2,15 @@
 
 A step is one pass of the whole plain path over the workload: for each
 query of the workload, one apt_knn_rdf call (bounding box, target and
-neighbour selection, cell binning by radix sort, pair enumeration with
-RDF histogram and exact kNN rows plus the k-th distance histogram).
-Inputs are generated on the host (seeded, synthetic), copied to HBM once,
-and are resident when the timed region starts.
+neighbour selection, cell binning, pair enumeration with RDF histogram and
+exact kNN rows plus the k-th distance histogram).  Inputs are generated on
+the host (seeded, synthetic), copied to HBM once, and are resident when the
+timed region starts.
+
+The headline workload is the full-scale needle: 2e9 ions, Sc -> any
+species, d_srf = 2 nm.  Beside it the line carries the 7.7e6-ion needle's
+three queries, the batched null-model replicates against looped plain calls
+on that needle, and the smoothed RDF on the 1e6-ion box.
 
 Prints one JSON line (rank 0).  --gpus above 1 is refused: the benchmark
 measures one GPU.
@@ -37,7 +42,9 @@ K, R_MAX, N_BINS, KB_RMAX, KB_NBINS = 10, 2.0, 200, 5.0, 5000
 # scaled by a plain-copy calibration; valid only for the kernel source they
 # were taken on (profiles/k_pair_frustum7m_hbm_counters.md)
 PAIR_TRAFFIC = {"frustum7m": (200.0e6, "36fb0ed37bbd0285")}
-FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk (packed FMA)
+PAIR_SOURCES = ("apt_pair.hip", "apt_pair.hpp", "apt_pairdev.hpp", "apt_internal.hpp", "apt_bin.hpp")
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBPS = 8000.0            # MI355X HBM3E   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk (packed FMA)
 FLOP_PER_PAIR = 8                 # 3 sub, 1 mul, 2 fma per pair distance
 # candidate pair-evaluations per second the FP32 vector units allow: 256 CU x
 # 64 lanes x 2 (packed) x 2.4 GHz over 6 instructions per candidate
@@ -48,8 +55,9 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(spec_name, queries, d_srf, use_d, seconds_budget=25.0):
-    """The oracle (grid kNN + grid RDF, OpenMP) on a bounded sample of the workload."""
+def cpu_baseline(spec_name, queries, d_srf, use_d, repeats=3):
+    """The oracle (grid kNN + grid RDF, OpenMP) on a bounded sample of the
+    workload: median of `repeats` runs on all host threads and on one."""
     import numpy as np
 
     import aptsynth
@@ -58,8 +66,6 @@ def cpu_baseline(spec_name, queries, d_srf, use_d, seconds_budget=25.0):
     spec = aptsynth.WORKLOADS[spec_name]()
     n = spec.n
     if n <= 8_000_000:
-        # the whole cloud (frustum7m: a few seconds)
-        m = n
         xyz, lab, d = spec.generate()
         what = f"the whole {n}-ion cloud"
     else:
@@ -68,23 +74,56 @@ def cpu_baseline(spec_name, queries, d_srf, use_d, seconds_budget=25.0):
         # same density, composition and cluster density, hence the same
         # per-target work
         sub = aptsynth.WORKLOADS[spec_name](n=8_000_000)
-        m = sub.n
         xyz, lab, d = sub.generate()
-        what = f"the same needle scaled to {m} ions (same density, composition and clusters; the full cloud has {n})"
+        what = (f"the same needle scaled to {sub.n} ions (same density, composition and clusters; "
+                f"the full cloud has {n})")
     d = d if use_d else None
-    targets = 0
-    t0 = time.perf_counter()
-    for A, B in queries:
-        oracle.rdf(xyz, lab, d, A, B, d_srf, R_MAX, N_BINS)
-        tid, _, _, _ = oracle.knn(xyz, lab, d, A, B, d_srf, K, kb_rmax=KB_RMAX, kb_nbins=KB_NBINS)
-        targets += len(tid)
-        if time.perf_counter() - t0 > seconds_budget:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": targets / dt, "unit": "target ions/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{what}, queries "
-                      f"{', '.join(NAMES[a] + '->' + NAMES[b] for a, b in queries)}, grid oracle "
-                      f"(RDF + kNN k={K} + k-th histogram), {dt:.1f} s"}
+
+    def run(dd):
+        targets = 0
+        t0 = time.perf_counter()
+        for A, B in queries:
+            oracle.rdf(xyz, lab, dd, A, B, d_srf, R_MAX, N_BINS)
+            tid, _, _, _ = oracle.knn(xyz, lab, dd, A, B, d_srf, K, kb_rmax=KB_RMAX, kb_nbins=KB_NBINS)
+            targets += len(tid)
+        return targets, time.perf_counter() - t0
+
+    all_threads = oracle.threads()
+    rates, secs = [], []
+    for _ in range(repeats):
+        t, dt = run(d)
+        rates.append(t / dt)
+        secs.append(dt)
+    # one core: the whole of a smaller cloud of the same kind (the same
+    # needle scaled to 2e6 ions: same density and chemistry, a quarter of
+    # the targets), so that three runs stay within ~15 s
+    if n > 2_000_000:
+        sub1 = aptsynth.WORKLOADS[spec_name](n=2_000_000) if n > 8_000_000 else None
+        if sub1 is not None:
+            xyz, lab, d1 = sub1.generate()
+            d1 = d1 if use_d else None
+            what1 = f"the same needle scaled to {sub1.n} ions, the whole cloud"
+        else:
+            d1, what1 = d, what
+    else:
+        d1, what1 = d, what
+    # (a whole cloud of more than 2e6 ions is timed once on one core)
+    reps1 = 1 if (d1 is d and n > 2_000_000) else repeats
+    oracle.set_threads(1)
+    rates1, secs1 = [], []
+    try:
+        for _ in range(reps1):
+            t, dt = run(d1)
+            rates1.append(t / dt)
+            secs1.append(dt)
+    finally:
+        oracle.set_threads(all_threads)
+    qs = ", ".join(NAMES[a] + "->" + NAMES[b] for a, b in queries)
+    return {"value": float(np.median(rates)), "unit": "target ions/s", "cores": all_threads, "kind": "oracle",
+            "sample": f"{what}, queries {qs}, grid oracle (RDF + kNN k={K} + k-th histogram), median of "
+                      f"{repeats} runs of {np.median(secs):.1f} s on {all_threads} threads",
+            "one_core": {"value": float(np.median(rates1)), "unit": "target ions/s", "cores": 1,
+                         "sample": f"{what1}, median of {reps1} runs of {np.median(secs1):.1f} s on 1 thread"}}
 
 
 def smooth_timing(aptstat, torch, reps=10):
@@ -200,51 +239,41 @@ def batched_vs_looped(aptstat, torch, cloud, ws, n_rep, n_loop):
             "speedup": (n_rep / tb) / (n_loop / tl), "status": int(st.item())}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="frustum7m", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-smooth", action="store_true", help="skip the smoothed-RDF timing")
-    ap.add_argument("--batched-reps", type=int, default=256,
-                    help="replicates of the batched null-model measurement (0 = skip)")
-    ap.add_argument("--looped-reps", type=int, default=16,
-                    help="replicates timed for the looped baseline (its rate is replicates/s)")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain 1 GiB device-to-device copy 5 times (scale of the HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library runs on "
-              f"one GPU; how the path would shard over several is a design note, not code)", file=sys.stderr)
-        sys.exit(2)
+def traffic_for(workload):
+    """HBM bytes per pair launch from committed counter runs, if the pair
+    kernel's sources still hash to the ones measured (else None)."""
+    if workload not in PAIR_TRAFFIC:
+        return None
+    import hashlib
 
-    import numpy as np
-    import torch
+    csrc = os.path.join(ROOT, "paper_2004_05188_amd", "csrc")
+    blob = b"".join(open(os.path.join(csrc, f), "rb").read() for f in PAIR_SOURCES)
+    sha = hashlib.sha256(blob).hexdigest()[:16]
+    return PAIR_TRAFFIC[workload][0] if sha == PAIR_TRAFFIC[workload][1] else None
 
+
+def binning_bytes(n_ions, n_target_species, n_targets, n_neighbours):
+    """Algorithmic HBM bytes of one call's binning: labels read (1 B/ion),
+    d_bnd of the target species (4 B), positions of targets and neighbours
+    (12 B), the neighbour records written (16 B) and the target order
+    written (rank, index, position: 20 B).  The cell offsets, whose size is
+    a choice of the index, are not counted."""
+    return n_ions + 4 * n_target_species + 12 * (n_targets + n_neighbours) + 16 * n_neighbours + 20 * n_targets
+
+
+def measure_plain(aptstat, torch, workload, steps, warmup, ws, with_candidates=True):
+    """Target ions/s of the plain path on one workload, stage times, the pair
+    kernel's roofline figures and the culling ratio."""
     import aptsynth
-    import paper_2004_05188_amd as aptstat
 
-    if args.copy_calibration:
-        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
-        b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4, "copy_calibration_bytes_written":
-                          b.numel() * 4, "launches": 5}), flush=True)
-        return
-
-    gen_name, queries, d_srf, use_d = WORKLOADS[args.workload]
+    gen_name, queries, d_srf, use_d = WORKLOADS[workload]
     spec = aptsynth.WORKLOADS[gen_name]()
     dev = torch.device("cuda:0")
-    log(f"[bench] generating {args.workload}: {spec.n} ions into HBM")
+    log(f"[bench] generating {workload}: {spec.n} ions into HBM")
     t = time.perf_counter()
     xyz_d, lab_d, d_d = aptsynth.to_device(spec, torch, dev, with_d_bnd=use_d, log=lambda m: log(f"[bench] {m}"))
     log(f"[bench] generated in {time.perf_counter() - t:.1f} s")
     cloud = aptstat.Cloud(xyz_d, lab_d, d_d)
-    ws = aptstat.Workspace()
     # outputs sized once from the exact target counts (outside the timed region)
     outs = []
     total_targets = 0
@@ -264,8 +293,8 @@ def main():
             aptstat.knn_rdf(cloud, A, B, d_srf, K, r_max=R_MAX, n_bins=N_BINS, capacity=o[7],
                             kb_rmax=KB_RMAX, kb_nbins=KB_NBINS, ws=ws, outputs=o[:7])
 
-    log(f"[bench] warmup {args.warmup}")
-    for _ in range(args.warmup):
+    log(f"[bench] {workload}: warmup {warmup}")
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     # in-range pairs per step (the algorithmic unit of the pair kernel)
@@ -277,16 +306,16 @@ def main():
     # is a GPU command of its own); the stage breakdown comes from a second,
     # separately traced run of the same steps
     aptstat.trace_enable(True, pair_only=True)
-    log(f"[bench] timing {args.steps} steps")
+    log(f"[bench] {workload}: timing {steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     aptstat.trace_enable(False)
     pair_ms, pair_n = aptstat.trace_read("pair")
-    stage_steps = min(args.steps, 10)
+    stage_steps = min(steps, 10)
     aptstat.trace_enable(True)
     for _ in range(stage_steps):
         step()
@@ -296,53 +325,119 @@ def main():
     tile_ms, _ = aptstat.trace_read("tile")
     bin_ms, bin_n = aptstat.trace_read("binning")
 
-    # culling: the neighbour records the pair kernel's first enumeration
-    # visits (outside the timed region), against the in-range pairs
-    cand = sum(int(aptstat.count_candidates(cloud, A, B, d_srf, R_MAX, N_BINS, k=K, ws=ws).item())
-               for A, B in queries)
+    # binning's algorithmic bytes: species counts and cells from the inputs
+    # (host reductions outside the timed region)
+    n_ions = spec.n
+    bbytes = 0
+    for (A, B), o in zip(queries, outs):
+        n_a = n_ions if A == ANY else int((lab_d == A).sum().item())
+        n_b = n_ions if B == ANY else int((lab_d == B).sum().item())
+        bbytes += binning_bytes(n_ions, n_a, o[7], n_b)
 
-    ms_per_step = 1e3 * dt / args.steps
-    value = total_targets * args.steps / dt
-    # roofline of the pair kernel: algorithmic FLOPs of the in-range pairs of
-    # one launch over its average duration
+    cand = None
+    if with_candidates:
+        # culling: the neighbour records the pair kernel's first enumeration
+        # visits (outside the timed region), against the in-range pairs
+        cand = sum(int(aptstat.count_candidates(cloud, A, B, d_srf, R_MAX, N_BINS, k=K, ws=ws).item())
+                   for A, B in queries)
+    del cloud, xyz_d, lab_d, d_d, outs
+    torch.cuda.empty_cache()
+
     flop_per_launch = FLOP_PER_PAIR * pairs / len(queries)
     pair_avg_s = (pair_ms / max(pair_n, 1)) / 1e3
     achieved = flop_per_launch / pair_avg_s / 1e12
-    traffic = None
-    if args.workload in PAIR_TRAFFIC:
-        import hashlib
-
-        csrc = os.path.join(ROOT, "paper_2004_05188_amd", "csrc")
-        blob = b"".join(open(os.path.join(csrc, f), "rb").read()
-                        for f in ("apt_pair.hip", "apt_pair.hpp", "apt_pairdev.hpp", "apt_internal.hpp", "apt_bin.hpp"))
-        sha = hashlib.sha256(blob).hexdigest()[:16]
-        if sha == PAIR_TRAFFIC[args.workload][1]:
-            traffic = PAIR_TRAFFIC[args.workload][0]
-    line = {
-        "metric": METRIC, "value": value, "unit": "target ions/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": args.workload, "ions": spec.n,
-                   "queries": [f"{NAMES[a]}->{NAMES[b]}" for a, b in queries], "k": K, "r_max_nm": R_MAX,
-                   "n_bins": N_BINS, "d_srf_nm": d_srf if use_d else None,
-                   "knn_hist": [0.0, KB_RMAX / KB_NBINS, KB_RMAX], "targets_per_step": total_targets},
-        "roofline": {"bound": "alu", "kernel": "k_pair", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
-                     "pairs_per_launch": pairs / len(queries), "avg_launch_ms": pair_ms / max(pair_n, 1)},
+    bin_s = bin_ms / stage_steps / 1e3
+    res = {
+        "workload": workload, "ions": spec.n, "queries": [f"{NAMES[a]}->{NAMES[b]}" for a, b in queries],
+        "d_srf_nm": d_srf if use_d else None, "targets_per_step": total_targets,
+        "ms_per_step": 1e3 * dt / steps, "target_ions_per_s": total_targets * steps / dt,
+        "roofline": {"bound": "alu", "kernel": "pair stage (k_pair)", "achieved": achieved,
+                     "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": traffic_for(workload), "pairs_per_launch": pairs / len(queries),
+                     "avg_launch_ms": pair_ms / max(pair_n, 1)},
         "stages_ms_per_step": {"binning": bin_ms / stage_steps, "pair": pair2_ms / stage_steps,
                                "tile": tile_ms / stage_steps},
+        "binning_hbm": {"algorithmic_bytes_per_step": bbytes, "achieved_GBps": bbytes / bin_s / 1e9 if bin_s else None,
+                        "peak_GBps": HBM_PEAK_GBPS,
+                        "frac": (bbytes / bin_s / 1e9) / HBM_PEAK_GBPS if bin_s else None},
         "in_range_pairs_per_step": pairs,
         "in_range_pairs_per_s": pairs * stage_steps / ((pair2_ms + tile_ms) / 1e3),
-        "culling": {"candidates_per_step": cand, "ratio": cand / max(pairs, 1),
-                    "candidate_evals_per_s": cand * stage_steps / (pair2_ms / 1e3) if pair2_ms > 0 else None,
-                    "frac_of_r_pair": (cand * stage_steps / (pair2_ms / 1e3)) / R_PAIR if pair2_ms > 0 else None},
         "status": status,
     }
-    if args.batched_reps > 0 and args.workload == "frustum7m":
-        line["batched"] = batched_vs_looped(aptstat, torch, cloud, ws, args.batched_reps, args.looped_reps)
-    if args.workload == "frustum7m" and not args.no_smooth:
-        log("[bench] smoothed RDF on box1m")
-        line["smooth"] = smooth_timing(aptstat, torch)
+    if cand is not None:
+        res["culling"] = {"candidates_per_step": cand, "ratio": cand / max(pairs, 1),
+                          "candidate_evals_per_s": cand * stage_steps / (pair2_ms / 1e3) if pair2_ms > 0 else None,
+                          "frac_of_r_pair": (cand * stage_steps / (pair2_ms / 1e3)) / R_PAIR if pair2_ms > 0 else None}
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="frustum2g", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 7.7e6-ion needle, batched and smoothed-RDF measurements")
+    ap.add_argument("--no-smooth", action="store_true", help="skip the smoothed-RDF timing")
+    ap.add_argument("--batched-reps", type=int, default=256,
+                    help="replicates of the batched null-model measurement (0 = skip)")
+    ap.add_argument("--looped-reps", type=int, default=256,
+                    help="replicates timed for the looped baseline (its rate is replicates/s)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (scale of the HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the library runs on "
+              f"one GPU; how the path would shard over several is a design note, not code)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2004_05188_amd as aptstat
+
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4, "copy_calibration_bytes_written":
+                          b.numel() * 4, "launches": 5}), flush=True)
+        return
+
+    ws = aptstat.Workspace()
+    head = measure_plain(aptstat, torch, args.workload, args.steps, args.warmup, ws)
+    gen_name, queries, d_srf, use_d = WORKLOADS[args.workload]
+    line = {
+        "metric": METRIC, "value": head["target_ions_per_s"], "unit": "target ions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "ions": head["ions"], "queries": head["queries"], "k": K,
+                   "r_max_nm": R_MAX, "n_bins": N_BINS, "d_srf_nm": head["d_srf_nm"],
+                   "knn_hist": [0.0, KB_RMAX / KB_NBINS, KB_RMAX], "targets_per_step": head["targets_per_step"]},
+        "roofline": head["roofline"],
+        "stages_ms_per_step": head["stages_ms_per_step"], "binning_hbm": head["binning_hbm"],
+        "in_range_pairs_per_step": head["in_range_pairs_per_step"],
+        "in_range_pairs_per_s": head["in_range_pairs_per_s"], "culling": head.get("culling"),
+        "status": head["status"],
+    }
+    if not args.no_extra:
+        if args.workload != "frustum7m":
+            line["needle7m"] = measure_plain(aptstat, torch, "frustum7m", args.steps, args.warmup, ws)
+        if args.batched_reps > 0:
+            import aptsynth
+
+            spec = aptsynth.frustum7m()
+            xyz_d, lab_d, d_d = aptsynth.to_device(spec, torch, torch.device("cuda:0"), with_d_bnd=True)
+            cloud = aptstat.Cloud(xyz_d, lab_d, d_d)
+            line["batched"] = batched_vs_looped(aptstat, torch, cloud, ws, args.batched_reps,
+                                                min(args.looped_reps, args.batched_reps))
+            del cloud, xyz_d, lab_d, d_d
+        if not args.no_smooth:
+            log("[bench] smoothed RDF on box1m")
+            line["smooth"] = smooth_timing(aptstat, torch)
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host")
         line["cpu_baseline"] = cpu_baseline(gen_name, queries, d_srf, use_d)

@@ -41,6 +41,7 @@ def _load():
         L = ctypes.CDLL(_SO)
         sig = {
             "orc_threads": ([], _i32),
+            "orc_set_threads": ([_i32], None),
             "orc_d2f": ([_p, _p], _f32),
             "orc_D2": ([_p, _p], _f64),
             "orc_edges2": ([_f32, _i32, _p], None),
@@ -81,6 +82,11 @@ def _cloud(xyz, lab, d_bnd):
 
 def threads() -> int:
     return int(_load().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads the oracle's OpenMP loops use from now on."""
+    _load().orc_set_threads(int(n))
 
 
 def d2f(a, b) -> float:

@@ -744,3 +744,12 @@ void orc_smooth_fd(const float* xyz, const uint8_t* lab, const float* d_bnd, int
     free((void*)st.e);
 }
 
+
+/* Threads the OpenMP loops of the oracle use from now on (n >= 1). */
+void orc_set_threads(int32_t n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

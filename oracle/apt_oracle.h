@@ -20,6 +20,7 @@ extern "C" {
 
 /* Number of OpenMP threads the oracle's loops use. */
 int32_t orc_threads(void);
+void orc_set_threads(int32_t n);
 
 /* Canonical distances between two stored FP32 positions. */
 float orc_d2f(const float* a, const float* b);   /* FP32, fixed evaluation order */
