@@ -203,7 +203,14 @@ def frustum2g(seed: int = 1, n: int = 2_000_000_000) -> Specimen:
     return scaled_needle(n, 2000.0, 60.0, 30.0, seed=seed)
 
 
-WORKLOADS = {"box240k": box240k, "frustum7m": frustum7m, "box1m": box1m, "frustum2g": frustum2g}
+def frustum200m(seed: int = 1) -> Specimen:
+    """The full-scale needle's shape and chemistry at a tenth of its ions (same
+    density: the same per-target work, for profiling runs)."""
+    return frustum2g(seed=seed, n=200_000_000)
+
+
+WORKLOADS = {"box240k": box240k, "frustum7m": frustum7m, "box1m": box1m, "frustum2g": frustum2g,
+             "frustum200m": frustum200m}
 
 
 def to_device(spec: Specimen, torch, device, with_d_bnd: bool = True, chunk: int = 1 << 25, on_chunk=None,

@@ -36,12 +36,14 @@ WORKLOADS = {
     "frustum7m": ("frustum7m", [(SC, SC), (SC, AL), (SI, SC)], 1.0, True),
     "box240k": ("box240k", [(SC, SC)], 0.0, False),
     "frustum2g": ("frustum2g", [(SC, ANY)], 2.0, True),
+    "frustum200m": ("frustum200m", [(SC, ANY)], 2.0, True),
 }
 K, R_MAX, N_BINS, KB_RMAX, KB_NBINS = 10, 2.0, 200, 5.0, 5000
-# HBM bytes per k_pair launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs,
-# scaled by a plain-copy calibration; valid only for the kernel source they
-# were taken on (profiles/k_pair_frustum7m_hbm_counters.md)
-PAIR_TRAFFIC = {"frustum7m": (200.0e6, "36fb0ed37bbd0285")}
+# HBM bytes per launch of the roofline kernel, (workload, kernel) -> (bytes,
+# source hash), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a
+# plain-copy calibration; valid only for the kernel sources they were taken
+# on (the summaries under profiles/)
+PAIR_TRAFFIC = {}
 PAIR_SOURCES = ("apt_pair.hip", "apt_pair.hpp", "apt_pairdev.hpp", "apt_internal.hpp", "apt_bin.hpp")
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBPS = 8000.0            # MI355X HBM3E   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk (packed FMA)
@@ -239,17 +241,17 @@ def batched_vs_looped(aptstat, torch, cloud, ws, n_rep, n_loop):
             "speedup": (n_rep / tb) / (n_loop / tl), "status": int(st.item())}
 
 
-def traffic_for(workload):
-    """HBM bytes per pair launch from committed counter runs, if the pair
-    kernel's sources still hash to the ones measured (else None)."""
-    if workload not in PAIR_TRAFFIC:
+def traffic_for(workload, kernel):
+    """HBM bytes per launch of the roofline kernel from committed counter
+    runs, if the kernel sources still hash to the ones measured (else None)."""
+    if (workload, kernel) not in PAIR_TRAFFIC:
         return None
     import hashlib
 
     csrc = os.path.join(ROOT, "paper_2004_05188_amd", "csrc")
     blob = b"".join(open(os.path.join(csrc, f), "rb").read() for f in PAIR_SOURCES)
     sha = hashlib.sha256(blob).hexdigest()[:16]
-    return PAIR_TRAFFIC[workload][0] if sha == PAIR_TRAFFIC[workload][1] else None
+    return PAIR_TRAFFIC[(workload, kernel)][0] if sha == PAIR_TRAFFIC[(workload, kernel)][1] else None
 
 
 def binning_bytes(n_ions, n_target_species, n_targets, n_neighbours):
@@ -300,7 +302,7 @@ def measure_plain(aptstat, torch, workload, steps, warmup, ws, with_candidates=T
     # in-range pairs per step (the algorithmic unit of the pair kernel)
     pairs = sum(int(o[6].sum().item()) for o in outs)
     status = [int(o[5].item()) for o in outs]
-    for stage in ("pair", "tile", "binning"):
+    for stage in ("pair", "tile", "nbr", "binning"):
         aptstat.trace_read(stage)
     # the timed steps record events around the pair kernel only (each event
     # is a GPU command of its own); the stage breakdown comes from a second,
@@ -315,6 +317,7 @@ def measure_plain(aptstat, torch, workload, steps, warmup, ws, with_candidates=T
     dt = time.perf_counter() - t0
     aptstat.trace_enable(False)
     pair_ms, pair_n = aptstat.trace_read("pair")
+    nbr_ms, nbr_n = aptstat.trace_read("nbr")
     stage_steps = min(steps, 10)
     aptstat.trace_enable(True)
     for _ in range(stage_steps):
@@ -323,6 +326,7 @@ def measure_plain(aptstat, torch, workload, steps, warmup, ws, with_candidates=T
     aptstat.trace_enable(False)
     pair2_ms, _ = aptstat.trace_read("pair")
     tile_ms, _ = aptstat.trace_read("tile")
+    nbr2_ms, _ = aptstat.trace_read("nbr")
     bin_ms, bin_n = aptstat.trace_read("binning")
 
     # binning's algorithmic bytes: species counts and cells from the inputs
@@ -343,31 +347,40 @@ def measure_plain(aptstat, torch, workload, steps, warmup, ws, with_candidates=T
     del cloud, xyz_d, lab_d, d_d, outs
     torch.cuda.empty_cache()
 
+    # the RDF's pairs are counted by the neighbour-major kernel (dense
+    # neighbours) or by the one-target-per-wavefront pair kernel: the
+    # dominant of the two is the roofline kernel (on a mix of queries the
+    # per-launch pair count is the mean over all queries)
+    if nbr_ms > pair_ms:
+        kname, k_ms, k_n = "k_rdf_nbr", nbr_ms, nbr_n
+    else:
+        kname, k_ms, k_n = "k_pair", pair_ms, pair_n
     flop_per_launch = FLOP_PER_PAIR * pairs / len(queries)
-    pair_avg_s = (pair_ms / max(pair_n, 1)) / 1e3
-    achieved = flop_per_launch / pair_avg_s / 1e12
+    k_avg_s = (k_ms / max(k_n, 1)) / 1e3
+    achieved = flop_per_launch / k_avg_s / 1e12
     bin_s = bin_ms / stage_steps / 1e3
     res = {
         "workload": workload, "ions": spec.n, "queries": [f"{NAMES[a]}->{NAMES[b]}" for a, b in queries],
         "d_srf_nm": d_srf if use_d else None, "targets_per_step": total_targets,
         "ms_per_step": 1e3 * dt / steps, "target_ions_per_s": total_targets * steps / dt,
-        "roofline": {"bound": "alu", "kernel": "pair stage (k_pair)", "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": kname, "achieved": achieved,
                      "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": traffic_for(workload), "pairs_per_launch": pairs / len(queries),
-                     "avg_launch_ms": pair_ms / max(pair_n, 1)},
+                     "traffic": traffic_for(workload, kname), "pairs_per_launch": pairs / len(queries),
+                     "avg_launch_ms": k_ms / max(k_n, 1)},
         "stages_ms_per_step": {"binning": bin_ms / stage_steps, "pair": pair2_ms / stage_steps,
-                               "tile": tile_ms / stage_steps},
+                               "tile": tile_ms / stage_steps, "nbr": nbr2_ms / stage_steps},
         "binning_hbm": {"algorithmic_bytes_per_step": bbytes, "achieved_GBps": bbytes / bin_s / 1e9 if bin_s else None,
                         "peak_GBps": HBM_PEAK_GBPS,
                         "frac": (bbytes / bin_s / 1e9) / HBM_PEAK_GBPS if bin_s else None},
         "in_range_pairs_per_step": pairs,
-        "in_range_pairs_per_s": pairs * stage_steps / ((pair2_ms + tile_ms) / 1e3),
+        "in_range_pairs_per_s": pairs * stage_steps / ((pair2_ms + tile_ms + nbr2_ms) / 1e3),
         "status": status,
     }
     if cand is not None:
+        eval_ms = pair2_ms + nbr2_ms
         res["culling"] = {"candidates_per_step": cand, "ratio": cand / max(pairs, 1),
-                          "candidate_evals_per_s": cand * stage_steps / (pair2_ms / 1e3) if pair2_ms > 0 else None,
-                          "frac_of_r_pair": (cand * stage_steps / (pair2_ms / 1e3)) / R_PAIR if pair2_ms > 0 else None}
+                          "candidate_evals_per_s": cand * stage_steps / (eval_ms / 1e3) if eval_ms > 0 else None,
+                          "frac_of_r_pair": (cand * stage_steps / (eval_ms / 1e3)) / R_PAIR if eval_ms > 0 else None}
     return res
 
 
@@ -385,6 +398,8 @@ def main():
                     help="replicates of the batched null-model measurement (0 = skip)")
     ap.add_argument("--looped-reps", type=int, default=256,
                     help="replicates timed for the looped baseline (its rate is replicates/s)")
+    ap.add_argument("--tile-policy", type=int, default=0,
+                    help="pair mode (apt_set_tuning tile_policy; 0 = automatic) for profiling runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (scale of the HBM byte counters)")
     args = ap.parse_args()
@@ -407,6 +422,8 @@ def main():
                           b.numel() * 4, "launches": 5}), flush=True)
         return
 
+    if args.tile_policy:
+        aptstat.set_tuning(tile_policy=args.tile_policy)
     ws = aptstat.Workspace()
     head = measure_plain(aptstat, torch, args.workload, args.steps, args.warmup, ws)
     gen_name, queries, d_srf, use_d = WORKLOADS[args.workload]

@@ -230,11 +230,14 @@ apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_tar
 
 /* Diagnostic, not part of any statistic: bins the cloud exactly as
  * apt_knn_rdf(q, bins, k, ...) would (k = 0: as apt_rdf), then sets
- * candidates[0] (uint64, device; overwritten) to the number of neighbour
- * records that the one-target-per-wavefront pair kernel's first enumeration
- * visits, summed over the eligible targets: the cell rows within bins.r_max
- * (or within the first kNN radius, when k > 0 and that is larger), each row
- * trimmed to the x-range the sphere reaches.  Divided by the in-range pair
+ * candidates[0] (uint64, device; overwritten) to the number of pair
+ * evaluations of the kernel that counts the RDF: for the one-target-per-
+ * wavefront pair kernel, the neighbour records its first enumeration visits,
+ * summed over the eligible targets (the cell rows within bins.r_max, or
+ * within the first kNN radius when k > 0 and that is larger, each row
+ * trimmed to the x-range the sphere reaches); for the neighbour-major kernel
+ * (dense neighbours), the records of each 64-record run times the targets
+ * staged for it.  Divided by the in-range pair
  * count it gives the culling ratio of the grid (paper, Supplementary,
  * "Effectiveness of the spatial splitting").  Errors as
  * apt_knn_rdf; k < 0 or candidates NULL return APT_E_ARG.  Workspace as
@@ -247,14 +250,16 @@ apt_status apt_count_candidates(const apt_cloud* cloud, apt_query q, apt_bins bi
  *   tile_policy  0 automatic, 1 one target per wavefront, 2 64 targets per
  *                wavefront with LDS-staged neighbours and a register kNN list,
  *                3 one target per lane, each lane walking its own cells with a
- *                register kNN list (2 and 3 only when k <= 16 and
- *                n_bins <= 2048)
+ *                register kNN list, 4 the kNN one target per lane (register
+ *                list within a certified radius) and the RDF one target per
+ *                wavefront (2, 3 and 4 only when k <= 16 and n_bins <= 2048;
+ *                4 also needs k >= 1)
  *   cell_occ     neighbours per grid cell aimed at with one target per
  *                wavefront (default 4)
  *   h_min_frac   smallest cell edge as a fraction of r_max (default 0.5)
  *   tile_occ     neighbours per grid cell aimed at with 64 targets per
  *                wavefront or one per lane (default 1; 0 selects the default)
- * Out-of-range values (tile_policy outside 0..3, cell_occ or h_min_frac not
+ * Out-of-range values (tile_policy outside 0..4, cell_occ or h_min_frac not
  * finite and > 0, tile_occ not finite and >= 0) return APT_E_ARG and leave
  * the tuning unchanged.  apt_set_tuning(NULL) restores the defaults. */
 typedef struct {
@@ -268,11 +273,13 @@ apt_status apt_get_tuning(apt_tuning* t);
 
 /* Tracing: while enabled, every call records HIP events on its stream
  * around its stages (on = 1) or around the one-target-per-wavefront pair
- * kernel only (on = 2: fewer events, each of which the GPU executes as a
- * command of its own); on = 0 disables it, other values return APT_E_ARG.
+ * kernel and the neighbour-major RDF kernel only (on = 2: fewer events, each
+ * of which the GPU executes as a command of its own); on = 0 disables it,
+ * other values return APT_E_ARG.
  * apt_trace_read waits for the recorded events, returns the summed time
  * (ms) and number of launches of one stage ("binning" = bounding box to
- * sorted records, "pair" = the pair kernel, "tile" = the 64-target kernel,
+ * sorted records, "pair" = the pair kernel, "tile" = the 64-target kernel
+ * (and the per-lane kNN of mode 4), "nbr" = the neighbour-major RDF kernel,
  * "permute" and "partition" = the batched replicates' label permutation and
  * class split) and forgets that stage's records.  Host only; off by
  * default. */

@@ -174,7 +174,8 @@ def set_tuning(tile_policy: int = 0, cell_occ: float = 4.0, h_min_frac: float = 
     """Process-wide speed knobs (results do not depend on them).
 
     tile_policy: 0 automatic, 1 one target per wavefront, 2 64 targets per
-    wavefront sharing staged candidates, 3 one target per lane."""
+    wavefront sharing staged candidates, 3 one target per lane, 4 the kNN one
+    target per lane and the RDF one target per wavefront."""
     t = _Tuning(int(tile_policy), float(cell_occ), float(h_min_frac), float(tile_occ))
     _check(lib().apt_set_tuning(ctypes.byref(t)), "apt_set_tuning")
 

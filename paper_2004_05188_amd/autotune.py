@@ -17,7 +17,7 @@ from . import Cloud, Workspace, count_targets, get_tuning, knn_rdf, set_tuning, 
 STAGES = ("binning", "pair", "tile")
 
 DEFAULT_GRID = {
-    "tile_policy": (1, 2, 3),
+    "tile_policy": (1, 2, 3, 4),
     "cell_occ": (2.0, 4.0, 8.0),
     "h_min_frac": (0.35, 0.5, 0.7),
     "tile_occ": (0.5, 1.0, 2.0),

@@ -89,7 +89,7 @@ struct TraceSpan {
     int dev = 0;
     TraceSpan(const char* s, hipStream_t stream) : stage(s), st(stream) {
         const int on = g_trace_on.load();
-        if (!on || (on == 2 && strcmp(s, "pair") != 0)) return;
+        if (!on || (on == 2 && strcmp(s, "pair") != 0 && strcmp(s, "nbr") != 0)) return;
         if (hipGetDevice(&dev) != hipSuccess) return;
         a = take_event(dev);
         b = take_event(dev);
@@ -198,6 +198,7 @@ struct PlainWs {
     uint32_t* rs_totals;
     uint32_t* strag;
     uint32_t* strag_count;
+    uint32_t* t_cell_start;
     size_t bytes;
 };
 
@@ -233,6 +234,7 @@ static PlainWs carve_plain(void* base, int64_t n) {
     w.cell_start = c.take<uint32_t>((size_t)cell_cap_for(n) + 1);
     w.strag = c.take<uint32_t>(N);
     w.strag_count = c.take<uint32_t>(64);
+    w.t_cell_start = c.take<uint32_t>((size_t)cell_cap_for(n) + 1);
     w.bytes = c.off;
     return w;
 }
@@ -465,7 +467,7 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
     // occupied cells (distinct sorted keys) feed the kNN radii
     const bool occ = pp.k > 0 && !zscale;
     OrderArgs oa{w.plan, cl->xyz, w.tid, {w.V[0], w.V[1]}, w.t_rank, w.t_id, w.tx, w.ty, w.tz,
-                 {w.K[0], w.K[1]}, occ ? w.strag_count + 1 : nullptr};
+                 {w.K[0], w.K[1]}, occ ? w.strag_count + 1 : nullptr, w.t_cell_start};
     GatherArgs ga{w.plan, cl->xyz, zscale, {w.KB[0], w.KB[1]}, {w.VB[0], w.VB[1]}, w.bpos, w.cell_start,
                   occ ? w.strag_count + 2 : nullptr};
     // (up to 2^25 ions half the usual grid per half: more records per thread
@@ -535,6 +537,23 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
         hipLaunchKernelGGL(k_count_candidates, dim3(device_info().cus * 8), dim3(kBlock), 0, st, w.plan,
                            do_knn ? w.strag_count + 1 : nullptr, w.cell_start, w.tx, w.ty, w.tz, rb->r_max,
                            do_knn ? k : 0, reinterpret_cast<unsigned long long*>(cand));
+        if (pp.tile_policy != 1) {
+            // mode 3: the neighbour-major kernel's pair evaluations instead
+            PairArgs ca{};
+            ca.plan = w.plan;
+            ca.tx = w.tx;
+            ca.ty = w.ty;
+            ca.tz = w.tz;
+            ca.t_id = w.t_id;
+            ca.bpos = w.bpos;
+            ca.t_cell_start = w.t_cell_start;
+            ca.r_enum = (float)((double)rb->r_max * (1.0 + 4e-5));
+            ca.hist = cand;
+            ca.n_bins = 1;
+            const size_t nl = nbr_lds_bytes(1, false);
+            auto kern = k_rdf_nbr<kRdfGlobal | kCountEvals>;
+            hipLaunchKernelGGL(kern, dim3(resident_grid(kern, nl)), dim3(kBlock), nl, st, ca);
+        }
         return hip_check("candidate count launch");
     }
 
@@ -590,11 +609,21 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     }
     pa.strag = w.strag;
     pa.strag_count = w.strag_count;
+    pa.t_cell_start = w.t_cell_start;
     // the kNN radii from the occupied cells that the binning counted
     pa.occ = do_knn ? w.strag_count + 1 : nullptr;
     pa.n_targets = do_knn ? n_targets : nullptr;
     pa.status = status;
     const size_t lds = pair_lds_bytes(do_rdf, do_knn, n_bins, in_lds);
+    if (pp.tile_policy != 1 && do_rdf) {
+        // the RDF neighbour-major when the plan chooses mode 3 (exits otherwise)
+        TraceSpan span("nbr", st);
+        const bool self = pa.self_possible != 0;
+        const size_t nl = nbr_lds_bytes(n_bins, in_lds);
+        auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(resident_grid(kern, nl)), dim3(kBlock), nl, st, pa); };
+        if (in_lds) self ? go(k_rdf_nbr<kRdfLds | kSelf>) : go(k_rdf_nbr<kRdfLds>);
+        else self ? go(k_rdf_nbr<kRdfGlobal | kSelf>) : go(k_rdf_nbr<kRdfGlobal>);
+    }
     if (pp.tile_policy != 1) {
         // 64 targets per wavefront when the plan chooses it (exits otherwise)
         TraceSpan span("tile", st);
@@ -966,7 +995,7 @@ const char* apt_last_error(void) { return g_err.c_str(); }
 apt_status apt_set_tuning(const apt_tuning* t) {
     apt_tuning v = {0, 4.0f, 0.5f, 1.0f};
     if (t) {
-        if (t->tile_policy < 0 || t->tile_policy > 3) return fail(APT_E_ARG, "tile_policy must be 0, 1, 2 or 3");
+        if (t->tile_policy < 0 || t->tile_policy > 4) return fail(APT_E_ARG, "tile_policy must be 0, 1, 2, 3 or 4");
         if (!(t->cell_occ > 0.0f) || !(t->h_min_frac > 0.0f) || !isfinite(t->cell_occ) || !isfinite(t->h_min_frac))
             return fail(APT_E_ARG, "cell_occ and h_min_frac must be finite and > 0");
         if (!(t->tile_occ >= 0.0f) || !isfinite(t->tile_occ))

@@ -200,16 +200,27 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
     if (pp.tile_policy == 1) P.tile_mode = 0;
     else if (pp.tile_policy == 2) P.tile_mode = pp.k <= 16 ? 1 : 0;
     else if (pp.tile_policy == 3) P.tile_mode = pp.k <= 16 ? 2 : 0;
+    else if (pp.tile_policy == 4) P.tile_mode = (pp.k <= 16 && (pp.k >= 1 || pp.r_enum > 0.0f)) ? 3 : 0;
     else {
         // a tile pays when its 64 targets fill a region no larger than the
         // search reach, so that they share most of their candidates
         const double R = fmax((double)pp.r_enum, 1.6 / 1.15 * rk_raw);
         const double v64 = 64.0 * vol / (double)(totT > 0 ? totT : 1);
         P.tile_mode = (pp.k <= 16 && totT >= totB && totT >= 4096 && v64 <= R * R * R) ? 1 : 0;
+        // neighbours so dense that 64 of them span well under r_max: the RDF
+        // runs neighbour-major (64 records per wavefront against every target
+        // within reach), and the kNN, whose radius is then well below r_max,
+        // one target per lane among a few dozen records
+        const double a64 = cbrt(64.0 / rho);
+        if (!P.tile_mode && pp.k <= 16 && pp.r_enum > 0.0f && a64 <= (double)pp.r_enum &&
+            (pp.k == 0 || rk_raw <= 0.5 * (double)pp.r_enum))
+            P.tile_mode = 3;
     }
     // cell edge: at least h_min, and large enough to hold ~occ neighbours
-    // (tiles gather every candidate of their 64 targets: smaller cells pay)
-    const double occ = (P.tile_mode && pp.tile_occ > 0.0f) ? (double)pp.tile_occ : (double)pp.occ;
+    // (tiles gather every candidate of their 64 targets: smaller cells pay;
+    // in mode 3 the RDF enumeration sets the cell size)
+    const bool tiles = P.tile_mode == 1 || P.tile_mode == 2;
+    const double occ = (tiles && pp.tile_occ > 0.0f) ? (double)pp.tile_occ : (double)pp.occ;
     double h = fmax((double)pp.h_min, cbrt(occ / rho));
     if (totB == 0 || !(h > 0.0)) h = emax + 1.0;
     if (h < 1e-6 * (emax + 1.0)) h = 1e-6 * (emax + 1.0);
@@ -228,7 +239,7 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
     // binning cost more than it saved: +2 % on the 7.7e6-ion needle) when
     // its cell ids fit the same number of bytes, so that the binning runs
     // no extra radix pass (at 2e8 ions the extra pass cost more)
-    if (pp.h_shrink > 0.0f && !P.tile_mode && totB >= (1u << 25) && h < 3.0e38) {
+    if (pp.h_shrink > 0.0f && !tiles && totB >= (1u << 25) && h < 3.0e38) {
         const double h2 = fmax((double)pp.h_min * (double)pp.h_shrink, cbrt(occ / rho));
         if (h2 < h && h2 >= 1e-6 * (emax + 1.0)) {
             auto cells_of = [&](double hh) {
@@ -268,7 +279,8 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
         const uint64_t kmax = nbx * nby * nbz * 512u - 1u;
         uint32_t cap_bytes = 1;
         while (cap_bytes < 4 && ((pp.cell_cap - 1u) >> (8u * cap_bytes)) != 0u) ++cap_bytes;
-        if (kmax < (1ull << (8u * cap_bytes))) {
+        // (mode 3 looks targets up by cell: plain cell order)
+        if (P.tile_mode != 3 && kmax < (1ull << (8u * cap_bytes))) {
             P.tblock = 8;
             P.nbx = (int32_t)nbx;
             P.nby = (int32_t)nby;
@@ -670,6 +682,9 @@ __device__ __forceinline__ void take_order(const OrderArgs& a, uint32_t bid, uin
     const uint32_t* __restrict__ sk = a.keys[P.passes_T & 1];   // sorted target keys
     const uint64_t nT = P.nT, stride = (uint64_t)nblk * kBlock;
     uint32_t distinct = 0;
+    uint32_t* tcs = P.tile_mode == 3 ? a.t_cell_start : nullptr;
+    if (tcs && nT == 0)
+        for (uint64_t c = (uint64_t)bid * kBlock + threadIdx.x; c <= P.n_cells; c += stride) tcs[c] = 0;
     // kOrderItems targets per thread in flight: the position reads are random
     for (uint64_t t0 = (uint64_t)bid * kBlock + threadIdx.x; t0 < nT; t0 += stride * kOrderItems) {
         uint32_t rank[kOrderItems], id[kOrderItems];
@@ -699,6 +714,45 @@ __device__ __forceinline__ void take_order(const OrderArgs& a, uint32_t bid, uin
                 a.ty[t] = y[u];
                 a.tz[t] = z[u];
                 if (a.distinct) distinct += (t == 0 || sk[t] != sk[t - 1]) ? 1u : 0u;
+            }
+            if (tcs) {
+                // plain cell order (the key is the cell id): target t starts
+                // the cells (key[t-1], key[t]]; the last one also ends the
+                // rest.  Long runs (sparse targets) are filled by the whole
+                // wavefront, so that no lane writes millions of entries.
+                uint32_t q0 = 0, q1 = 0;   // cells [q0, q1) take value t (then nT for the tail)
+                uint32_t e0 = 0, e1 = 0;
+                if (t < nT) {
+                    const uint32_t c = sk[t];
+                    q0 = t == 0 ? 0u : sk[t - 1] + 1u;
+                    q1 = c + 1u;
+                    if (t == nT - 1) {
+                        e0 = c + 1u;
+                        e1 = P.n_cells + 1u;
+                    }
+                }
+                auto fill = [&](uint32_t f0, uint32_t f1, uint32_t val) {
+                    if (f1 - f0 <= 32u) {
+                        for (uint32_t q = f0; q < f1; ++q) tcs[q] = val;
+                        f1 = f0;
+                    }
+                    // (lanes past the end of the loop are inactive: stride by
+                    // the active lanes)
+                    const uint64_t act = __ballot(true);
+                    const uint32_t nact = (uint32_t)__popcll(act);
+                    const uint32_t me = (uint32_t)__popcll(act & lanemask_lt());
+                    uint64_t m = __ballot(f1 > f0);
+                    while (m) {
+                        const int ln = __builtin_ctzll(m);
+                        m &= m - 1;
+                        const uint32_t g0 = (uint32_t)__shfl((int)f0, ln, kWave);
+                        const uint32_t g1 = (uint32_t)__shfl((int)f1, ln, kWave);
+                        const uint32_t gv = (uint32_t)__shfl((int)val, ln, kWave);
+                        for (uint32_t q = g0 + me; q < g1; q += nact) tcs[q] = gv;
+                    }
+                };
+                fill(q0, q1, (uint32_t)t);
+                fill(e0, e1, (uint32_t)nT);
             }
         }
     }

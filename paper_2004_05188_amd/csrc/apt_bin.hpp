@@ -135,6 +135,9 @@ struct OrderArgs {
     float* tz;
     const uint32_t* keys[2];   // sorted target keys
     uint32_t* distinct;     // may be NULL: += number of distinct target cells
+    // [n_cells + 1] start of each cell's targets (targets in plain cell
+    // order), written when the plan chose mode 3; may be NULL
+    uint32_t* t_cell_start;
 };
 
 struct GatherArgs {

@@ -36,7 +36,9 @@ struct GridPlan {
     float zscale;       // z scale applied to positions (1 for the plain path)
     int32_t nonfinite;
     int32_t tile_mode;  // 0: one target per wavefront; 64 targets per wavefront: 1 sharing staged
-                        // candidates (dense targets), 2 one target per lane (sparse neighbours)
+                        // candidates (dense targets), 2 one target per lane (sparse neighbours);
+                        // 3: kNN one target per lane, RDF one target per wavefront (dense
+                        // neighbours, kNN radius well below r_max)
     float rk_tile;      // kNN radius certified by the tile pass
 };
 
@@ -47,7 +49,8 @@ struct PlanParams {
     int32_t k;          // kNN order (0: no kNN)
     uint32_t cell_cap;  // largest number of cells the workspace holds
     int32_t tile_policy;  // 0: automatic, 1: one target per wavefront, 2: 64 targets per wavefront
-                          // sharing staged candidates, 3: one target per lane
+                          // sharing staged candidates, 3: one target per lane, 4: kNN per lane and
+                          // RDF per wavefront
     float r_enum;       // RDF enumeration radius (0: no RDF)
     float tile_occ;     // aimed-for neighbours per cell with 64 targets per wavefront (<= 0: occ)
     // > 0: one target per wavefront also tries the edge h_min * h_shrink and

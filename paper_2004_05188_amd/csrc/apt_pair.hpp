@@ -43,6 +43,7 @@ struct PairArgs {
     uint32_t* strag;             // [nT] target slots (cell order)
     uint32_t* strag_count;       // [1], zeroed before the tile pass
     const uint32_t* occ;         // [2] occupied-cell counts for refine_radii, or NULL
+    const uint32_t* t_cell_start;  // [n_cells + 1] targets per cell (mode 3: plain cell order)
     // written once per call by k_pair (workgroup 0): the eligible target
     // count, and APT_STATUS_CAPACITY when k > 0 and it exceeds capacity
     int64_t* n_targets;
@@ -54,6 +55,8 @@ struct PairArgs {
 // Variant flags of k_pair: RDF into per-wavefront LDS histograms or straight
 // into the global histogram (many bins); targets may be neighbours themselves.
 constexpr int kRdfLds = 1, kRdfGlobal = 2, kSelf = 4;
+// k_rdf_nbr only: count the pair evaluations into hist[0] instead of the RDF
+constexpr int kCountEvals = 8;
 template <int FLAGS, bool KNN>
 __global__ void k_pair(PairArgs a);
 
@@ -64,6 +67,14 @@ size_t pair_lds_bytes(bool rdf, bool knn, int n_bins, bool hist_in_lds);
 template <int FLAGS, int KMAX>
 __global__ void k_pair_tile(PairArgs a);
 size_t tile_lds_bytes(bool rdf, int n_bins);
+
+// Neighbour-major RDF (mode 3, dense neighbours): each wavefront takes 64
+// consecutive neighbour records and evaluates every target within reach of
+// their bounding box against all of them.  Exits at once unless the plan
+// chose mode 3.
+template <int FLAGS>
+__global__ void k_rdf_nbr(PairArgs a);
+size_t nbr_lds_bytes(int n_bins, bool hist_in_lds);
 __global__ void k_count_candidates(const GridPlan* plan, const uint32_t* occ, const uint32_t* cell_start,
                                    const float* tx, const float* ty, const float* tz, float r_enum, int32_t k,
                                    unsigned long long* out);

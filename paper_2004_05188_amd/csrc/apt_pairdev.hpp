@@ -382,17 +382,21 @@ __device__ __forceinline__ void run_tile(const GridPlan& P, const PairTask& T, b
     (void)l;
 }
 
-// One target per lane for sparse neighbours: each lane walks the cell rows
-// within R of its own target (rows trimmed to the x-range the sphere
-// reaches, as in enumerate_box) and reads the records one by one, kLaneU of
-// them in flight; no staging, and no lane waits on a shared candidate list.
-// Same results as run_tile (same candidate set, order-free updates).
+// One target per lane: each lane walks the cell rows within R of its own
+// target (rows trimmed to the x-range the sphere reaches, as in
+// enumerate_box) and reads the records one by one, kLaneU of them in flight;
+// no staging, and no lane waits on a shared candidate list.  Same results as
+// run_tile (same candidate set, order-free updates).  With rdf_on false only
+// the kNN keys within Rk are taken (a small radius when the neighbours are
+// dense: a few dozen records per lane).
 constexpr int kLaneU = 4;
 
 template <int FLAGS, int KMAX>
 __device__ __forceinline__ void run_lane(const GridPlan& P, const PairTask& T, bool valid, float px, float py,
-                                         float pz, uint32_t i, float Rk, TopK<KMAX>& top, uint32_t& hits) {
-    constexpr bool RDF = (FLAGS & (kRdfLds | kRdfGlobal)) != 0;
+                                         float pz, uint32_t i, float Rk, TopK<KMAX>& top, uint32_t& hits,
+                                         bool rdf_on = true) {
+    constexpr bool RDF_T = (FLAGS & (kRdfLds | kRdfGlobal)) != 0;
+    const bool RDF = RDF_T && rdf_on;
     constexpr bool LDS_HIST = (FLAGS & kRdfLds) != 0;
     constexpr bool SELF = (FLAGS & kSelf) != 0;
 #pragma unroll

@@ -133,7 +133,7 @@ def test_tuning_round_trip_and_validation(aptstat):
         aptstat.set_tuning(2, 3.0, 0.7, 0.5)
         assert aptstat.get_tuning() == {"tile_policy": 2, "cell_occ": 3.0, "h_min_frac": 0.699999988079071,
                                         "tile_occ": 0.5}
-        for bad in ((4, 4.0, 0.5, 1.0), (0, 0.0, 0.5, 1.0), (0, 4.0, math.nan, 1.0), (0, 4.0, 0.5, -1.0),
+        for bad in ((5, 4.0, 0.5, 1.0), (-1, 4.0, 0.5, 1.0), (0, 0.0, 0.5, 1.0), (0, 4.0, math.nan, 1.0), (0, 4.0, 0.5, -1.0),
                     (0, 4.0, 0.5, math.inf)):
             with pytest.raises(aptstat.AptError):
                 aptstat.set_tuning(*bad)

@@ -433,7 +433,8 @@ def test_batched_lattice_ties_equal_looped(gpu, orc):
 
 
 # ---------------------------------------------------------------------------
-# one target per wavefront, 64 per wavefront sharing candidates, one per lane: forced
+# one target per wavefront, 64 per wavefront sharing candidates, one per lane,
+# kNN per lane + RDF per wavefront: forced
 # ---------------------------------------------------------------------------
 
 @pytest.fixture()
@@ -443,7 +444,7 @@ def policy(gpu):
     aptstat.set_tuning()          # back to the defaults
 
 
-@pytest.mark.parametrize("mode", [1, 2, 3])
+@pytest.mark.parametrize("mode", [1, 2, 3, 4])
 @pytest.mark.parametrize("A,B,k,d_srf,r_knn_max,rdf", [
     (SC, SC, 10, 1.0, math.inf, True), (AL, SC, 10, 1.0, math.inf, True), (AL, SI, 4, 1.0, math.inf, True),
     (ANY, SC, 1, 0.5, math.inf, True), (SC, ANY, 16, 1.0, math.inf, True), (AL, SC, 10, 1.0, 1.2, True),
@@ -457,7 +458,7 @@ def test_needle_queries_forced_mode(gpu, orc, small_needle, policy, mode, A, B, 
     check_against_oracle(orc, g, xyz, lab, d, A, B, d_srf, k=k, r_knn_max=r_knn_max, want_rdf=rdf)
 
 
-@pytest.mark.parametrize("mode", [1, 2, 3])
+@pytest.mark.parametrize("mode", [1, 2, 3, 4])
 def test_rdf_only_forced_mode(gpu, orc, small_needle, policy, mode):
     _say(f"case needle rdf-only mode={mode}")
     policy(tile_policy=mode)
@@ -466,7 +467,7 @@ def test_rdf_only_forced_mode(gpu, orc, small_needle, policy, mode):
     check_against_oracle(orc, g, xyz, lab, d, AL, SC, 1.0, k_on=False)
 
 
-@pytest.mark.parametrize("mode", [1, 2, 3])
+@pytest.mark.parametrize("mode", [1, 2, 3, 4])
 def test_edge_cases_forced_mode(gpu, orc, synth, policy, mode):
     _say(f"case edge cases mode={mode}")
     policy(tile_policy=mode)
