@@ -400,6 +400,8 @@ def main():
                     help="replicates timed for the looped baseline (its rate is replicates/s)")
     ap.add_argument("--tile-policy", type=int, default=0,
                     help="pair mode (apt_set_tuning tile_policy; 0 = automatic) for profiling runs")
+    ap.add_argument("--rdf-kernel", type=int, default=0,
+                    help="RDF kernel of the dense-neighbour mode (apt_set_tuning rdf_kernel) for profiling runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (scale of the HBM byte counters)")
     args = ap.parse_args()
@@ -422,8 +424,8 @@ def main():
                           b.numel() * 4, "launches": 5}), flush=True)
         return
 
-    if args.tile_policy:
-        aptstat.set_tuning(tile_policy=args.tile_policy)
+    if args.tile_policy or args.rdf_kernel:
+        aptstat.set_tuning(tile_policy=args.tile_policy, rdf_kernel=args.rdf_kernel)
     ws = aptstat.Workspace()
     head = measure_plain(aptstat, torch, args.workload, args.steps, args.warmup, ws)
     gen_name, queries, d_srf, use_d = WORKLOADS[args.workload]

@@ -259,14 +259,20 @@ apt_status apt_count_candidates(const apt_cloud* cloud, apt_query q, apt_bins bi
  *   h_min_frac   smallest cell edge as a fraction of r_max (default 0.5)
  *   tile_occ     neighbours per grid cell aimed at with 64 targets per
  *                wavefront or one per lane (default 1; 0 selects the default)
+ *   rdf_kernel   the RDF kernel of the dense-neighbour mode (tile_policy 4 or
+ *                its automatic choice): 0 automatic, 1 neighbour-major (64
+ *                neighbour records per wavefront against the targets in
+ *                reach), 2 one target per wavefront
  * Out-of-range values (tile_policy outside 0..4, cell_occ or h_min_frac not
- * finite and > 0, tile_occ not finite and >= 0) return APT_E_ARG and leave
+ * finite and > 0, tile_occ not finite and >= 0, rdf_kernel outside 0..2)
+ * return APT_E_ARG and leave
  * the tuning unchanged.  apt_set_tuning(NULL) restores the defaults. */
 typedef struct {
     int32_t tile_policy;
     float cell_occ;
     float h_min_frac;
     float tile_occ;
+    int32_t rdf_kernel;
 } apt_tuning;
 apt_status apt_set_tuning(const apt_tuning* t);
 apt_status apt_get_tuning(apt_tuning* t);

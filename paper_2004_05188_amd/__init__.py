@@ -45,7 +45,7 @@ class _Query(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("tile_policy", ctypes.c_int32), ("cell_occ", ctypes.c_float), ("h_min_frac", ctypes.c_float),
-                ("tile_occ", ctypes.c_float)]
+                ("tile_occ", ctypes.c_float), ("rdf_kernel", ctypes.c_int32)]
 
 
 class _Bins(ctypes.Structure):
@@ -170,13 +170,16 @@ class Workspace:
         return self.buf
 
 
-def set_tuning(tile_policy: int = 0, cell_occ: float = 4.0, h_min_frac: float = 0.5, tile_occ: float = 1.0):
+def set_tuning(tile_policy: int = 0, cell_occ: float = 4.0, h_min_frac: float = 0.5, tile_occ: float = 1.0,
+               rdf_kernel: int = 0):
     """Process-wide speed knobs (results do not depend on them).
 
     tile_policy: 0 automatic, 1 one target per wavefront, 2 64 targets per
     wavefront sharing staged candidates, 3 one target per lane, 4 the kNN one
-    target per lane and the RDF one target per wavefront."""
-    t = _Tuning(int(tile_policy), float(cell_occ), float(h_min_frac), float(tile_occ))
+    target per lane and the RDF one target per wavefront; rdf_kernel: the
+    RDF kernel of the dense-neighbour mode (0 automatic, 1 neighbour-major,
+    2 one target per wavefront)."""
+    t = _Tuning(int(tile_policy), float(cell_occ), float(h_min_frac), float(tile_occ), int(rdf_kernel))
     _check(lib().apt_set_tuning(ctypes.byref(t)), "apt_set_tuning")
 
 
@@ -184,7 +187,7 @@ def get_tuning() -> dict:
     t = _Tuning()
     _check(lib().apt_get_tuning(ctypes.byref(t)), "apt_get_tuning")
     return {"tile_policy": t.tile_policy, "cell_occ": t.cell_occ, "h_min_frac": t.h_min_frac,
-            "tile_occ": t.tile_occ}
+            "tile_occ": t.tile_occ, "rdf_kernel": t.rdf_kernel}
 
 
 def trace_enable(on: bool = True, pair_only: bool = False):

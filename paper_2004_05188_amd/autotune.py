@@ -14,20 +14,21 @@ import time
 
 from . import Cloud, Workspace, count_targets, get_tuning, knn_rdf, set_tuning, trace_enable, trace_read
 
-STAGES = ("binning", "pair", "tile")
+STAGES = ("binning", "pair", "tile", "nbr")
 
 DEFAULT_GRID = {
     "tile_policy": (1, 2, 3, 4),
     "cell_occ": (2.0, 4.0, 8.0),
     "h_min_frac": (0.35, 0.5, 0.7),
     "tile_occ": (0.5, 1.0, 2.0),
+    "rdf_kernel": (0,),
 }
 
 
 def autotune(cloud: Cloud, queries, d_srf: float = 0.0, k: int = 10, r_max: float = 2.0, n_bins: int = 200,
              grid: dict | None = None, reps: int = 3, ws: Workspace | None = None, apply: bool = True) -> dict:
     """Time knn_rdf over `queries` [(A, B), ...] for every combination of
-    `grid` (keys: tile_policy, cell_occ, h_min_frac, tile_occ; a missing key keeps the
+    `grid` (keys: tile_policy, cell_occ, h_min_frac, tile_occ, rdf_kernel; a missing key keeps the
     current value) and keep the fastest, timed as the GPU time of the
     binning, pair and tile stages averaged over `reps` passes.
 
@@ -39,14 +40,14 @@ def autotune(cloud: Cloud, queries, d_srf: float = 0.0, k: int = 10, r_max: floa
     ws = ws if ws is not None else Workspace()
     caps = [int(count_targets(cloud, A, d_srf, ws=ws).item()) for A, _ in queries]
     before = get_tuning()
-    keys = ("tile_policy", "cell_occ", "h_min_frac", "tile_occ")
+    keys = ("tile_policy", "cell_occ", "h_min_frac", "tile_occ", "rdf_kernel")
     settings = []
     for st in itertools.product(*(grid.get(kk, (before[kk],)) for kk in keys)):
         # the cell occupancy of the mode not chosen does not matter
         if st[0] == 1:
-            st = (st[0], st[1], st[2], before["tile_occ"])
+            st = (st[0], st[1], st[2], before["tile_occ"], before["rdf_kernel"])
         elif st[0] in (2, 3):
-            st = (st[0], before["cell_occ"], st[2], st[3])
+            st = (st[0], before["cell_occ"], st[2], st[3], before["rdf_kernel"])
         if st not in settings:
             settings.append(st)
     times = {}

@@ -47,7 +47,7 @@ static DevInfo device_info() {
 
 // ------------------------------------------------------------- tuning --
 static std::mutex g_tune_mu;
-static apt_tuning g_tune = {0, 4.0f, 0.5f, 1.0f};
+static apt_tuning g_tune = {0, 4.0f, 0.5f, 1.0f, 0};
 
 static apt_tuning tuning() {
     std::lock_guard<std::mutex> g(g_tune_mu);
@@ -529,6 +529,7 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     pp.tile_policy = (!tile_fits || (do_knn && k > 16)) ? 1 : tu.tile_policy;
     pp.r_enum = do_rdf ? rb->r_max : 0.0f;
     pp.h_shrink = 0.7f;
+    pp.rdf_kernel = tu.rdf_kernel;
     {
         TraceSpan span("binning", st);
         if ((s = run_binning(cl, q, pp, w, status, st, nullptr, 0, &ia)) != APT_OK) return s;
@@ -623,6 +624,13 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
         auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(resident_grid(kern, nl)), dim3(kBlock), nl, st, pa); };
         if (in_lds) self ? go(k_rdf_nbr<kRdfLds | kSelf>) : go(k_rdf_nbr<kRdfLds>);
         else self ? go(k_rdf_nbr<kRdfGlobal | kSelf>) : go(k_rdf_nbr<kRdfGlobal>);
+        if (tu.rdf_kernel == 2) {
+            // (the tuning asks for the one-target-per-wavefront RDF in mode 3)
+            const size_t tl = pair_lds_bytes(true, false, n_bins, in_lds);
+            auto go2 = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(resident_grid(kern, tl)), dim3(kBlock), tl, st, pa); };
+            if (in_lds) self ? go2(k_rdf_tgt<kRdfLds | kSelf>) : go2(k_rdf_tgt<kRdfLds>);
+            else self ? go2(k_rdf_tgt<kRdfGlobal | kSelf>) : go2(k_rdf_tgt<kRdfGlobal>);
+        }
     }
     if (pp.tile_policy != 1) {
         // 64 targets per wavefront when the plan chooses it (exits otherwise)
@@ -993,8 +1001,9 @@ extern "C" {
 const char* apt_last_error(void) { return g_err.c_str(); }
 
 apt_status apt_set_tuning(const apt_tuning* t) {
-    apt_tuning v = {0, 4.0f, 0.5f, 1.0f};
+    apt_tuning v = {0, 4.0f, 0.5f, 1.0f, 0};
     if (t) {
+        if (t->rdf_kernel < 0 || t->rdf_kernel > 2) return fail(APT_E_ARG, "rdf_kernel must be 0, 1 or 2");
         if (t->tile_policy < 0 || t->tile_policy > 4) return fail(APT_E_ARG, "tile_policy must be 0, 1, 2, 3 or 4");
         if (!(t->cell_occ > 0.0f) || !(t->h_min_frac > 0.0f) || !isfinite(t->cell_occ) || !isfinite(t->h_min_frac))
             return fail(APT_E_ARG, "cell_occ and h_min_frac must be finite and > 0");

@@ -303,7 +303,9 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
     P.rk0 = pp.k > 0 ? (float)fmin(rk_raw, (double)P.r_all) : 0.0f;
     P.zscale = a.zscale ? (float)*a.zscale : 1.0f;
     P.nonfinite = s_nf[0];
-    P.rk_tile = pp.k > 0 ? (float)fmin(1.6 / 1.15 * (double)P.rk0, (double)P.r_all) : 0.0f;
+    P.rk_tile = pp.k > 0 ? (float)fmin((P.tile_mode == 3 ? 1.3 : 1.6) / 1.15 * (double)P.rk0, (double)P.r_all)
+                         : 0.0f;
+    P.rdf_nbr = (P.tile_mode == 3 && pp.rdf_kernel != 2) ? 1 : 0;
     *a.plan = P;
     if (s_nf[0] && a.status) atomicOr(a.status, APT_STATUS_NONFINITE);
 }

@@ -185,8 +185,9 @@ __device__ inline void refine_radii(GridPlan& P, const uint32_t* occ, int32_t k)
     P.rk0 = (float)fmin(r, (double)P.r_all);
     // tiles: certified within 1.6x the Poisson mean k-th distance (species
     // that cluster leave the matrix poorer than the mean: a tighter radius
-    // sends too many targets to the one-by-one search)
-    P.rk_tile = (float)fmin(1.6 / 1.15 * (double)P.rk0, (double)P.r_all);
+    // sends too many targets to the one-by-one search); mode 3 (dense
+    // neighbours, nearly uniform): 1.3x, which leaves a few per mille
+    P.rk_tile = (float)fmin((P.tile_mode == 3 ? 1.3 : 1.6) / 1.15 * (double)P.rk0, (double)P.r_all);
 }
 
 // Squared bin edges e_b^2, e_b = b * r_max / n_bins in FP64, b = 0..n_bins,

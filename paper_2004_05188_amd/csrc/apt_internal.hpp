@@ -40,6 +40,7 @@ struct GridPlan {
                         // 3: kNN one target per lane, RDF one target per wavefront (dense
                         // neighbours, kNN radius well below r_max)
     float rk_tile;      // kNN radius certified by the tile pass
+    int32_t rdf_nbr;    // mode 3: the RDF runs neighbour-major (k_rdf_nbr), else one target per wavefront
 };
 
 // Host-chosen parameters of the plan.
@@ -56,6 +57,9 @@ struct PlanParams {
     // > 0: one target per wavefront also tries the edge h_min * h_shrink and
     // keeps it when the cell ids need no more bytes (no extra radix pass)
     float h_shrink = 0.0f;
+    // mode 3's RDF kernel: 0 automatic (neighbour-major), 1 neighbour-major,
+    // 2 one target per wavefront
+    int32_t rdf_kernel = 0;
 };
 
 // ---------------------------------------------------------------- waves --

@@ -175,6 +175,50 @@ __global__ __launch_bounds__(kBlock, 6) void k_pair(PairArgs a) {
     if (LDS_HIST) flush_hist(T.hist_l, a.hist, a.n_bins);
 }
 
+// Mode 3 with the RDF one target per wavefront (tuning): the RDF of every
+// target, no kNN (the lane pass and k_pair do that).  Without the kNN state
+// the loop fits 64 VGPRs: eight wavefronts per SIMD to hide the candidate
+// loads' latency.
+template <int FLAGS>
+__global__ __launch_bounds__(kBlock, 8) void k_rdf_tgt(PairArgs a) {
+    constexpr bool LDS_HIST = (FLAGS & kRdfLds) != 0;
+    extern __shared__ __align__(16) uint8_t smem[];
+    GridPlan P = *a.plan;
+    if (P.tile_mode != 3 || P.rdf_nbr) return;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int l = lane_id();
+    PairTask T;
+    T.bpos = a.bpos;
+    T.cell_start = a.cell_start;
+    T.n_bins = a.n_bins;
+    T.r_enum = a.r_enum;
+    T.thr2 = a.thr2;
+    T.inv_w = a.inv_w;
+    T.lo_b = a.delta_b;
+    T.hi_b = 1.0f - a.delta_b;
+    T.inv_w64 = a.inv_w64;
+    T.E2 = a.E2;
+    T.hist_l = reinterpret_cast<uint32_t*>(smem) + (size_t)w * hist_stride(a.n_bins);
+    T.hist_g = a.hist;
+    T.k = 0;
+    T.rk0 = 0.0f;
+    T.rknn = INFINITY;
+    T.rknn2 = INFINITY;
+    T.kbuf = nullptr;
+    if (LDS_HIST)
+        for (int b = l; b < a.n_bins; b += kWave) T.hist_l[b] = 0;
+    wave_sync();
+    uint32_t since_flush = 0;
+    const uint32_t flush_at = P.nB >= 0x7FFFFFFFu ? 0u : 0xFFFFFFFFu - P.nB;
+    pair_items<FLAGS, false>(a, P, T, false, true, since_flush, flush_at);
+    if (LDS_HIST) flush_hist(T.hist_l, a.hist, a.n_bins);
+}
+
+template __global__ void k_rdf_tgt<kRdfLds>(PairArgs);
+template __global__ void k_rdf_tgt<kRdfLds | kSelf>(PairArgs);
+template __global__ void k_rdf_tgt<kRdfGlobal>(PairArgs);
+template __global__ void k_rdf_tgt<kRdfGlobal | kSelf>(PairArgs);
+
 // Diagnostic: the neighbour records in the cell rows of the first
 // enumeration of every eligible target in the one-target-per-wavefront
 // kernel (radius r_enum, or the first kNN radius when that is larger),
@@ -184,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_count_candidates(const GridPlan* pla
                                                              const float* ty, const float* tz, float r_enum,
                                                              int32_t k, unsigned long long* out) {
     GridPlan P = *plan;
-    if (P.tile_mode == 3) return;   // counted by k_rdf_nbr<kCountEvals>
+    if (P.tile_mode == 3 && P.rdf_nbr) return;   // counted by k_rdf_nbr<kCountEvals>
     refine_radii(P, occ, k);
     const float rk = P.rk0 * 1.000001f;
     const float R = (k > 0 && !(rk < r_enum)) ? rk : r_enum;
@@ -339,8 +383,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_pair_tile(PairArgs a) {
 // access per pair, and each record is read once per launch.
 constexpr int kNbrList = 256;   // targets staged per wavefront per round
 
+// (the LDS histogram has one more counter: pairs whose bin is n_bins, just
+// beyond r_max, go there uncounted instead of taking a branch)
 size_t nbr_lds_bytes(int n_bins, bool hist_in_lds) {
-    size_t b = hist_in_lds ? (size_t)kWavesPerBlock * (size_t)hist_stride(n_bins) * 4u : 0;
+    size_t b = hist_in_lds ? (size_t)kWavesPerBlock * (size_t)hist_stride(n_bins + 1) * 4u : 0;
     b = (b + 15) & ~size_t(15);
     return b + (size_t)kWavesPerBlock * kNbrList * sizeof(float4);
 }
@@ -352,17 +398,17 @@ __global__ __launch_bounds__(kBlock, 8) void k_rdf_nbr(PairArgs a) {
     constexpr bool LDS_HIST = !COUNT && (FLAGS & kRdfLds) != 0;
     constexpr bool SELF = (FLAGS & kSelf) != 0;
     const GridPlan P = *a.plan;
-    if (P.tile_mode != 3) return;
+    if (P.tile_mode != 3 || !P.rdf_nbr) return;
     unsigned long long evals = 0;   // COUNT: pair evaluations (records x staged targets)
     extern __shared__ __align__(16) uint8_t smem[];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int l = lane_id();
-    uint32_t* hist_l = reinterpret_cast<uint32_t*>(smem) + (size_t)w * hist_stride(a.n_bins);
-    size_t off = LDS_HIST ? (size_t)kWavesPerBlock * hist_stride(a.n_bins) * 4u : 0;
+    uint32_t* hist_l = reinterpret_cast<uint32_t*>(smem) + (size_t)w * hist_stride(a.n_bins + 1);
+    size_t off = LDS_HIST ? (size_t)kWavesPerBlock * hist_stride(a.n_bins + 1) * 4u : 0;
     off = (off + 15) & ~size_t(15);
     float4* list = reinterpret_cast<float4*>(smem + off) + (size_t)w * kNbrList;
     if (LDS_HIST)
-        for (int b = l; b < a.n_bins; b += kWave) hist_l[b] = 0;
+        for (int b = l; b <= a.n_bins; b += kWave) hist_l[b] = 0;
     wave_sync();
 
     const uint32_t nB = P.nB;
@@ -378,6 +424,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_rdf_nbr(PairArgs a) {
     const float Re = a.r_enum + P.eps;
     const float R2 = Re * Re;
     const float thr2 = a.thr2, inv_w = a.inv_w, lo_b = a.delta_b, hi_b = 1.0f - a.delta_b;
+    const float half_band = 0.5f - a.delta_b;   // |fract - 1/2| beyond it: within delta_b of an edge
     uint32_t since_flush = 0;
     const uint32_t flush_at = 0xFFFFFFFFu - (uint32_t)(kWave * kNbrList);
 
@@ -385,116 +432,129 @@ __global__ __launch_bounds__(kBlock, 8) void k_rdf_nbr(PairArgs a) {
         const uint32_t j = c * (uint32_t)kWave + (uint32_t)l;
         const bool valid = j < nB;
         const float4 rec = a.bpos[valid ? j : nB - 1];
-        const bool fin = valid && isfinite(rec.x) && isfinite(rec.y) && isfinite(rec.z);
+        const bool fin0 = valid && isfinite(rec.x) && isfinite(rec.y) && isfinite(rec.z);
         const uint32_t rid = __builtin_bit_cast(uint32_t, rec.w);
-        // bounding box of the chunk's finite records
-        float x0 = fin ? rec.x : INFINITY, y0 = fin ? rec.y : INFINITY, z0 = fin ? rec.z : INFINITY;
-        float x1 = fin ? rec.x : -INFINITY, y1 = fin ? rec.y : -INFINITY, z1 = fin ? rec.z : -INFINITY;
+        // a run of 64 records may end one cell row and start the next, far
+        // apart in x: each row's part is evaluated with its own bounding box
+        const uint32_t crow = fin0 ? (uint32_t)cell_axis(P, 2, rec.z) * (uint32_t)P.dim[1] +
+                                         (uint32_t)cell_axis(P, 1, rec.y)
+                                   : 0xFFFFFFFFu;
+        uint64_t todo = __ballot(fin0);
+        while (todo) {
+            const uint32_t row_sel = readlane(crow, __builtin_ctzll(todo));
+            const bool fin = fin0 && crow == row_sel;
+            todo &= ~__ballot(fin);
+            // bounding box of the part's records
+            float x0 = fin ? rec.x : INFINITY, y0 = fin ? rec.y : INFINITY, z0 = fin ? rec.z : INFINITY;
+            float x1 = fin ? rec.x : -INFINITY, y1 = fin ? rec.y : -INFINITY, z1 = fin ? rec.z : -INFINITY;
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) {
-            x0 = fminf(x0, __shfl_xor(x0, d, kWave));
-            y0 = fminf(y0, __shfl_xor(y0, d, kWave));
-            z0 = fminf(z0, __shfl_xor(z0, d, kWave));
-            x1 = fmaxf(x1, __shfl_xor(x1, d, kWave));
-            y1 = fmaxf(y1, __shfl_xor(y1, d, kWave));
-            z1 = fmaxf(z1, __shfl_xor(z1, d, kWave));
-        }
-        if (!(x0 <= x1)) continue;   // no finite record in the chunk (uniform)
-
-        uint32_t hits = 0;
-        const uint32_t n_rec = (uint32_t)__popcll(__ballot(valid));
-        // every staged target against the 64 records
-        auto run = [&](int cnt) {
-            if (COUNT) {
-                evals += (unsigned long long)cnt * n_rec;
-                return;
+            for (int d = 32; d >= 1; d >>= 1) {
+                x0 = fminf(x0, __shfl_xor(x0, d, kWave));
+                y0 = fminf(y0, __shfl_xor(y0, d, kWave));
+                z0 = fminf(z0, __shfl_xor(z0, d, kWave));
+                x1 = fmaxf(x1, __shfl_xor(x1, d, kWave));
+                y1 = fmaxf(y1, __shfl_xor(y1, d, kWave));
+                z1 = fmaxf(z1, __shfl_xor(z1, d, kWave));
             }
-            wave_sync();
-            for (int t = 0; t < cnt; ++t) {
-                const float4 T = list[t];
-                const float dx = rec.x - T.x, dy = rec.y - T.y, dz = rec.z - T.z;
-                const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                bool ok = fin && d2 < thr2;
-                if (SELF) ok = ok && rid != __builtin_bit_cast(uint32_t, T.w);
-                if (ok) {
-                    const float tt = __builtin_amdgcn_sqrtf(d2) * inv_w;
-                    int b = (int)tt;
-                    const float fr = tt - (float)b;
-                    if (__builtin_expect(fr < lo_b || fr > hi_b, 0))
-                        b = exact_bin(exact_D2(T.x, T.y, T.z, rec.x, rec.y, rec.z), a.E2, a.n_bins, a.inv_w64);
-                    if (b < a.n_bins) {
-                        if (LDS_HIST) atomicAdd(&hist_l[b], 1u);
-                        else atomicAdd((unsigned long long*)&a.hist[b], 1ull);
-                        ++hits;
+            const uint32_t n_rec = (uint32_t)__popcll(__ballot(fin));
+            // every staged target against the 64 records
+            auto run = [&](int cnt) {
+                if (COUNT) {
+                    evals += (unsigned long long)cnt * n_rec;
+                    return;
+                }
+                wave_sync();
+                float4 Tn = list[0];
+                for (int t = 0; t < cnt; ++t) {
+                    // the next target's LDS read is in flight during this one
+                    const float4 T = Tn;
+                    if (t + 1 < cnt) Tn = list[t + 1];
+                    const float dx = rec.x - T.x, dy = rec.y - T.y, dz = rec.z - T.z;
+                    const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                    bool ok = fin && d2 < thr2;
+                    if (SELF) ok = ok && rid != __builtin_bit_cast(uint32_t, T.w);
+                    if (ok) {
+                        const float tt = __builtin_amdgcn_sqrtf(d2) * inv_w;
+                        int b = (int)tt;
+                        if (LDS_HIST) {
+                            // b == n_bins (beyond r_max) lands in the spare counter
+                            if (__builtin_expect(fabsf(__builtin_amdgcn_fractf(tt) - 0.5f) > half_band, 0))
+                                b = exact_bin(exact_D2(T.x, T.y, T.z, rec.x, rec.y, rec.z), a.E2, a.n_bins, a.inv_w64);
+                            atomicAdd(&hist_l[b], 1u);
+                        } else {
+                            const float fr = tt - (float)b;
+                            if (__builtin_expect(fr < lo_b || fr > hi_b, 0))
+                                b = exact_bin(exact_D2(T.x, T.y, T.z, rec.x, rec.y, rec.z), a.E2, a.n_bins, a.inv_w64);
+                            if (b < a.n_bins) atomicAdd((unsigned long long*)&a.hist[b], 1ull);
+                        }
+                    }
+                }
+                wave_sync();
+                if (LDS_HIST) {
+                    // at most cnt * 64 counts were added
+                    since_flush += (uint32_t)cnt * n_rec;
+                    if (since_flush >= flush_at) {
+                        flush_hist(hist_l, a.hist, a.n_bins);
+                        since_flush = 0;
+                    }
+                }
+            };
+
+            // target rows that the box grown by Re meets, each trimmed in x
+            int cnt = 0;
+            const int cy0 = cell_axis(P, 1, y0 - Re), cy1 = cell_axis(P, 1, y1 + Re);
+            const int cz0 = cell_axis(P, 2, z0 - Re), cz1 = cell_axis(P, 2, z1 + Re);
+            const int ny = cy1 - cy0 + 1, nz = cz1 - cz0 + 1;
+            const int nrows = ny * nz;
+            for (int rb = 0; rb < nrows; rb += kWave) {
+                const int r = rb + l;
+                uint32_t st = 0, len = 0;
+                if (r < nrows)
+                    row_span(P, a.t_cell_start, cy0 + r % ny, cz0 + r / ny, x0, y0, z0, x1, y1, z1, R2, st, len);
+                const uint32_t inc = wave_incl_scan(len);
+                const uint32_t tot = readlane(inc, kWave - 1);
+                const uint32_t offr = inc - len;
+                for (uint32_t b0 = 0; b0 < tot; b0 += kWave) {
+                    // the target slot of lane v: the last row starting at or before v
+                    const uint32_t v = b0 + (uint32_t)l;
+                    const uint32_t lim = b0 + kWave < tot ? b0 + kWave : tot;
+                    const int r0 = __popcll(__ballot(inc <= b0));
+                    const int r1 = __popcll(__ballot(offr < lim)) - 1;
+                    int row = r0;
+                    for (int step = 32; step > 0; step >>= 1) {
+                        if (step > r1 - r0) continue;            // uniform
+                        const int cc = row + step;
+                        const uint32_t oc = (uint32_t)__shfl((int)offr, cc < kWave ? cc : kWave - 1, kWave);
+                        if (cc <= r1 && oc <= v) row = cc;
+                    }
+                    const uint32_t base = (uint32_t)__shfl((int)(st - offr), row, kWave);
+                    bool keep = v < tot;
+                    float tx = 0.0f, ty = 0.0f, tz = 0.0f;
+                    uint32_t ti = 0;
+                    if (keep) {
+                        const uint32_t q = base + v;
+                        tx = a.tx[q];
+                        ty = a.ty[q];
+                        tz = a.tz[q];
+                        ti = a.t_id[q];
+                        // exact cull against the records' box (a pair within
+                        // r_max lies within r_max of the box)
+                        const float ex = fmaxf(0.0f, fmaxf(x0 - tx, tx - x1));
+                        const float ey = fmaxf(0.0f, fmaxf(y0 - ty, ty - y1));
+                        const float ez = fmaxf(0.0f, fmaxf(z0 - tz, tz - z1));
+                        keep = isfinite(tx) && isfinite(ty) && isfinite(tz) && ex * ex + ey * ey + ez * ez <= R2;
+                    }
+                    const uint64_t m = __ballot(keep);
+                    if (keep) list[cnt + __popcll(m & lanemask_lt())] = make_float4(tx, ty, tz, __builtin_bit_cast(float, ti));
+                    cnt += __popcll(m);
+                    if (cnt > kNbrList - kWave) {
+                        run(cnt);
+                        cnt = 0;
                     }
                 }
             }
-            wave_sync();
-            if (LDS_HIST) {
-                since_flush += wave_sum(hits);
-                hits = 0;
-                if (since_flush >= flush_at) {
-                    flush_hist(hist_l, a.hist, a.n_bins);
-                    since_flush = 0;
-                }
-            }
-        };
-
-        // target rows that the box grown by Re meets, each trimmed in x
-        int cnt = 0;
-        const int cy0 = cell_axis(P, 1, y0 - Re), cy1 = cell_axis(P, 1, y1 + Re);
-        const int cz0 = cell_axis(P, 2, z0 - Re), cz1 = cell_axis(P, 2, z1 + Re);
-        const int ny = cy1 - cy0 + 1, nz = cz1 - cz0 + 1;
-        const int nrows = ny * nz;
-        for (int rb = 0; rb < nrows; rb += kWave) {
-            const int r = rb + l;
-            uint32_t st = 0, len = 0;
-            if (r < nrows)
-                row_span(P, a.t_cell_start, cy0 + r % ny, cz0 + r / ny, x0, y0, z0, x1, y1, z1, R2, st, len);
-            const uint32_t inc = wave_incl_scan(len);
-            const uint32_t tot = readlane(inc, kWave - 1);
-            const uint32_t offr = inc - len;
-            for (uint32_t b0 = 0; b0 < tot; b0 += kWave) {
-                // the target slot of lane v: the last row starting at or before v
-                const uint32_t v = b0 + (uint32_t)l;
-                const uint32_t lim = b0 + kWave < tot ? b0 + kWave : tot;
-                const int r0 = __popcll(__ballot(inc <= b0));
-                const int r1 = __popcll(__ballot(offr < lim)) - 1;
-                int row = r0;
-                for (int step = 32; step > 0; step >>= 1) {
-                    if (step > r1 - r0) continue;            // uniform
-                    const int cc = row + step;
-                    const uint32_t oc = (uint32_t)__shfl((int)offr, cc < kWave ? cc : kWave - 1, kWave);
-                    if (cc <= r1 && oc <= v) row = cc;
-                }
-                const uint32_t base = (uint32_t)__shfl((int)(st - offr), row, kWave);
-                bool keep = v < tot;
-                float tx = 0.0f, ty = 0.0f, tz = 0.0f;
-                uint32_t ti = 0;
-                if (keep) {
-                    const uint32_t q = base + v;
-                    tx = a.tx[q];
-                    ty = a.ty[q];
-                    tz = a.tz[q];
-                    ti = a.t_id[q];
-                    // exact cull against the records' box (a pair within
-                    // r_max lies within r_max of the box)
-                    const float ex = fmaxf(0.0f, fmaxf(x0 - tx, tx - x1));
-                    const float ey = fmaxf(0.0f, fmaxf(y0 - ty, ty - y1));
-                    const float ez = fmaxf(0.0f, fmaxf(z0 - tz, tz - z1));
-                    keep = isfinite(tx) && isfinite(ty) && isfinite(tz) && ex * ex + ey * ey + ez * ez <= R2;
-                }
-                const uint64_t m = __ballot(keep);
-                if (keep) list[cnt + __popcll(m & lanemask_lt())] = make_float4(tx, ty, tz, __builtin_bit_cast(float, ti));
-                cnt += __popcll(m);
-                if (cnt > kNbrList - kWave) {
-                    run(cnt);
-                    cnt = 0;
-                }
-            }
+            if (cnt > 0) run(cnt);
         }
-        if (cnt > 0) run(cnt);
-        if (!LDS_HIST) (void)hits;
     }
     if (LDS_HIST) flush_hist(hist_l, a.hist, a.n_bins);
     if (COUNT && l == 0 && evals) atomicAdd((unsigned long long*)a.hist, evals);

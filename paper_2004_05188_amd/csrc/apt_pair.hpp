@@ -74,6 +74,10 @@ size_t tile_lds_bytes(bool rdf, int n_bins);
 // chose mode 3.
 template <int FLAGS>
 __global__ void k_rdf_nbr(PairArgs a);
+// Mode 3 with the RDF one target per wavefront (tuning rdf_kernel 2): RDF
+// of every target, eight wavefronts per SIMD; exits otherwise.
+template <int FLAGS>
+__global__ void k_rdf_tgt(PairArgs a);
 size_t nbr_lds_bytes(int n_bins, bool hist_in_lds);
 __global__ void k_count_candidates(const GridPlan* plan, const uint32_t* occ, const uint32_t* cell_start,
                                    const float* tx, const float* ty, const float* tz, float r_enum, int32_t k,

@@ -132,16 +132,17 @@ def test_tuning_round_trip_and_validation(aptstat):
     try:
         aptstat.set_tuning(2, 3.0, 0.7, 0.5)
         assert aptstat.get_tuning() == {"tile_policy": 2, "cell_occ": 3.0, "h_min_frac": 0.699999988079071,
-                                        "tile_occ": 0.5}
+                                        "tile_occ": 0.5, "rdf_kernel": 0}
         for bad in ((5, 4.0, 0.5, 1.0), (-1, 4.0, 0.5, 1.0), (0, 0.0, 0.5, 1.0), (0, 4.0, math.nan, 1.0), (0, 4.0, 0.5, -1.0),
-                    (0, 4.0, 0.5, math.inf)):
+                    (0, 4.0, 0.5, math.inf), (0, 4.0, 0.5, 1.0, 3), (0, 4.0, 0.5, 1.0, -1)):
             with pytest.raises(aptstat.AptError):
                 aptstat.set_tuning(*bad)
             assert aptstat.get_tuning()["tile_occ"] == 0.5
         aptstat.set_tuning(0, 4.0, 0.5, 0.0)           # 0 selects the default tile occupancy
         assert aptstat.get_tuning()["tile_occ"] == 1.0
         assert aptstat.lib().apt_set_tuning(None) == 0
-        assert aptstat.get_tuning() == {"tile_policy": 0, "cell_occ": 4.0, "h_min_frac": 0.5, "tile_occ": 1.0}
+        assert aptstat.get_tuning() == {"tile_policy": 0, "cell_occ": 4.0, "h_min_frac": 0.5, "tile_occ": 1.0,
+                                        "rdf_kernel": 0}
     finally:
         aptstat.set_tuning()
 

@@ -440,11 +440,19 @@ def test_batched_lattice_ties_equal_looped(gpu, orc):
 @pytest.fixture()
 def policy(gpu):
     aptstat = gpu[0]
-    yield aptstat.set_tuning
+
+    def set_mode(tile_policy):
+        # 42: the dense-neighbour mode (4) with its RDF one target per wavefront
+        if tile_policy == 42:
+            aptstat.set_tuning(tile_policy=4, rdf_kernel=2)
+        else:
+            aptstat.set_tuning(tile_policy=tile_policy)
+
+    yield set_mode
     aptstat.set_tuning()          # back to the defaults
 
 
-@pytest.mark.parametrize("mode", [1, 2, 3, 4])
+@pytest.mark.parametrize("mode", [1, 2, 3, 4, 42])
 @pytest.mark.parametrize("A,B,k,d_srf,r_knn_max,rdf", [
     (SC, SC, 10, 1.0, math.inf, True), (AL, SC, 10, 1.0, math.inf, True), (AL, SI, 4, 1.0, math.inf, True),
     (ANY, SC, 1, 0.5, math.inf, True), (SC, ANY, 16, 1.0, math.inf, True), (AL, SC, 10, 1.0, 1.2, True),
@@ -452,25 +460,25 @@ def policy(gpu):
 ])
 def test_needle_queries_forced_mode(gpu, orc, small_needle, policy, mode, A, B, k, d_srf, r_knn_max, rdf):
     _say(f"case needle mode={mode} A={A} B={B} k={k} d_srf={d_srf} rknn={r_knn_max} rdf={rdf}")
-    policy(tile_policy=mode)
+    policy(mode)
     xyz, lab, d = small_needle
     g = run_gpu(gpu, xyz, lab, d, A, B, d_srf, k=k, r_knn_max=r_knn_max, want_rdf=rdf)
     check_against_oracle(orc, g, xyz, lab, d, A, B, d_srf, k=k, r_knn_max=r_knn_max, want_rdf=rdf)
 
 
-@pytest.mark.parametrize("mode", [1, 2, 3, 4])
+@pytest.mark.parametrize("mode", [1, 2, 3, 4, 42])
 def test_rdf_only_forced_mode(gpu, orc, small_needle, policy, mode):
     _say(f"case needle rdf-only mode={mode}")
-    policy(tile_policy=mode)
+    policy(mode)
     xyz, lab, d = small_needle
     g = run_gpu(gpu, xyz, lab, d, AL, SC, 1.0, k_on=False)
     check_against_oracle(orc, g, xyz, lab, d, AL, SC, 1.0, k_on=False)
 
 
-@pytest.mark.parametrize("mode", [1, 2, 3, 4])
+@pytest.mark.parametrize("mode", [1, 2, 3, 4, 42])
 def test_edge_cases_forced_mode(gpu, orc, synth, policy, mode):
     _say(f"case edge cases mode={mode}")
-    policy(tile_policy=mode)
+    policy(mode)
     xyz = np.array([[1, 1, 1], [1, 1, 1], [1, 1, 1], [1.5, 1, 1], [3, 3, 3], [np.nan, 0, 0]], np.float32)
     lab = np.array([SC, SC, AL, AL, SC, SC], np.uint8)
     for A, B in ((SC, ANY), (SC, SC), (ANY, ANY), (AL, SC)):
