@@ -177,10 +177,17 @@ def batched_vs_looped(aptstat, torch, cloud, ws, n_rep, n_loop):
     rh = torch.empty((n_rep, len(pairs), N_BINS), dtype=torch.int64, device=dev)
     kh = torch.empty((n_rep, len(pairs), KB_NBINS + 1), dtype=torch.int64, device=dev)
     st = torch.empty(1, dtype=torch.int32, device=dev)
-    log(f"[bench] batched: warm-up (2 replicates)")
-    aptstat.rdf_batched(cloud, pairs, seeds[:2], r_max=R_MAX, n_bins=N_BINS, k=K, kb_rmax=KB_RMAX,
-                        kb_nbins=KB_NBINS, ws=ws)
+    # warm-up: with tuning NULL the library tunes the plan for this call
+    # (trial launches), caches it, captures the launch sequence in a graph
+    # and launches it
+    log(f"[bench] batched: warm-up ({n_rep} replicates; plan tuned and cached)")
+    aptstat.batched_plan_clear()
+    t0 = time.perf_counter()
+    aptstat.rdf_batched(cloud, pairs, seeds, r_max=R_MAX, n_bins=N_BINS, k=K, kb_rmax=KB_RMAX,
+                        kb_nbins=KB_NBINS, ws=ws, out=(rh, kh, st))
     torch.cuda.synchronize()
+    t_first = time.perf_counter() - t0
+    plan = aptstat.batched_plan(cloud, pairs, r_max=R_MAX, n_bins=N_BINS, k=K, kb_rmax=KB_RMAX, kb_nbins=KB_NBINS)
     log(f"[bench] batched: {n_rep} replicates x {len(pairs)} pairs")
     for stage in ("pair", "tile", "binning", "permute", "partition"):
         aptstat.trace_read(stage)
@@ -192,6 +199,13 @@ def batched_vs_looped(aptstat, torch, cloud, ws, n_rep, n_loop):
     tb = time.perf_counter() - t0
     aptstat.trace_enable(False)
     stages = {s_: aptstat.trace_read(s_)[0] for s_ in ("pair", "tile", "binning", "permute", "partition")}
+    # the library's own graph of the call (tracing off: replayed)
+    log(f"[bench] batched: library graph replay")
+    t0 = time.perf_counter()
+    aptstat.rdf_batched(cloud, pairs, seeds, r_max=R_MAX, n_bins=N_BINS, k=K, kb_rmax=KB_RMAX,
+                        kb_nbins=KB_NBINS, ws=ws, out=(rh, kh, st))
+    torch.cuda.synchronize()
+    t_lib = time.perf_counter() - t0
     # the same call captured once in a HIP graph and replayed (its outputs
     # must equal the eager call's)
     want = (rh.clone(), kh.clone())
@@ -233,12 +247,13 @@ def batched_vs_looped(aptstat, torch, cloud, ws, n_rep, n_loop):
     torch.cuda.synchronize()
     tl = time.perf_counter() - t0
     return {"replicates": n_rep, "pairs": [f"{NAMES[a]}->{NAMES[b]}" for a, b, _ in pairs],
-            "batched_replicates_per_s": n_rep / tb, "batched_s": tb,
-            "batched_stage_ms": stages,
+            "batched_replicates_per_s": n_rep / t_lib, "batched_s": t_lib, "traced_eager_s": tb,
+            "batched_stage_ms": stages, "plan": plan, "first_call_s": t_first,
+            "library_graph_replicates_per_s": n_rep / t_lib,
             "graph_replicates_per_s": n_rep / tg, "graph_equals_eager": graph_equal,
             "looped_replicates_per_s": n_loop / tl, "looped_replicates_timed": n_loop,
             "looped_calls_timed": n_loop * (1 + len(pairs)),
-            "speedup": (n_rep / tb) / (n_loop / tl), "status": int(st.item())}
+            "speedup": (n_rep / t_lib) / (n_loop / tl), "status": int(st.item())}
 
 
 def traffic_for(workload, kernel):

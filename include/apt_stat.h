@@ -169,6 +169,22 @@ apt_status apt_knn_rdf(const apt_cloud* cloud, apt_query q, apt_bins rdf_bins, u
 apt_status apt_permute_labels(const uint8_t* lab, int64_t n, uint64_t seed, uint8_t* out, int32_t* status,
                               void* ws, size_t ws_bytes, void* stream);
 
+/* Speed knobs of apt_rdf_batched (results do not depend on them):
+ *   cell_frac   grid cell edge as a fraction of rdf_bins.r_max, in (0, 4]
+ *               (0 selects the default 0.5)
+ *   rep_block   replicates permuted and evaluated per block, 1..64 (0 selects
+ *               64; the workspace for n_rep may cap it lower)
+ *   tile_reach  certified kNN reach of the 64-target tiles, as a multiple of
+ *               the Poisson mean k-th neighbour distance, in [1, 4] (0 selects
+ *               the default 1.3)
+ *   tiles       0 automatic, 1 never use 64-target tiles */
+typedef struct {
+    float cell_frac;
+    int32_t rep_block;
+    float tile_reach;
+    int32_t tiles;
+} apt_batched_tuning;
+
 /* Null-model replicates of several species pairs in one call (paper, Suppl.:
  * every statistic for randomised labels; Methods: "User-defined batch
  * processing queues").  For replicate r (0 <= r < n_rep) the labels are
@@ -180,13 +196,33 @@ apt_status apt_permute_labels(const uint8_t* lab, int64_t n, uint64_t seed, uint
  *   rdf_hist         [n_rep][n_pairs][rdf_bins.n_bins] uint64 (n_bins <= 3072)
  *   knn_hist         [n_rep][n_pairs][knn_bins.n_bins + 1] uint64, or NULL;
  *                    k-th neighbour distance of every eligible target
- *   tuning           reserved, pass NULL
+ *   tuning           host pointer to an apt_batched_tuning, or NULL: the plan
+ *                    is looked up in a process-wide cache keyed by the device,
+ *                    n, the pairs, the bins and k; on a miss it is autotuned
+ *                    first (timed trial launches of a few replicates on this
+ *                    stream, which wait for the GPU; skipped, with the
+ *                    defaults, while the stream is being captured), then
+ *                    cached.  With NULL the launch sequence is also captured
+ *                    once into a HIP graph, cached per call signature
+ *                    (pointers, sizes, seeds), and replayed on later calls
+ *                    with the same signature (not while the stream is being
+ *                    captured or tracing is on)
  * Positions are binned once; replicates run in blocks of up to 64.
  * Workspace: apt_workspace_size(APT_OP_BATCHED, n, n_pairs, n_rep). */
 apt_status apt_rdf_batched(const apt_cloud* cloud, const apt_query* pairs, int32_t n_pairs, const uint64_t* seeds,
                            int32_t n_rep, apt_bins rdf_bins, int32_t k, apt_bins knn_bins, uint64_t* rdf_hist,
-                           uint64_t* knn_hist, const void* tuning, int32_t* status, void* ws, size_t ws_bytes,
-                           void* stream);
+                           uint64_t* knn_hist, const apt_batched_tuning* tuning, int32_t* status, void* ws,
+                           size_t ws_bytes, void* stream);
+
+/* The plan apt_rdf_batched(tuning = NULL) uses for these arguments
+ * (want_knn_hist: whether knn_hist is non-NULL), if cached (host only, no
+ * GPU work): *cached = 1 and *out filled (rep_block 0: as many as the
+ * workspace holds), or *cached = 0.  apt_batched_plan_clear empties the plan
+ * and graph caches (a later call tunes again). */
+apt_status apt_batched_plan(const apt_cloud* cloud, const apt_query* pairs, int32_t n_pairs, apt_bins rdf_bins,
+                            int32_t k, apt_bins knn_bins, int32_t want_knn_hist, apt_batched_tuning* out,
+                            int32_t* cached);
+apt_status apt_batched_plan_clear(void);
 
 /* Gaussian-smoothed RDF, an extension (not in the paper) of the RDF's
  * rectangular transfer function (paper, Methods: "Descriptive, two-point

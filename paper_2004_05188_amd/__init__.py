@@ -48,6 +48,14 @@ class _Tuning(ctypes.Structure):
                 ("tile_occ", ctypes.c_float), ("rdf_kernel", ctypes.c_int32)]
 
 
+class _BatchedTuning(ctypes.Structure):
+    _fields_ = [("cell_frac", ctypes.c_float), ("rep_block", ctypes.c_int32), ("tile_reach", ctypes.c_float),
+                ("tiles", ctypes.c_int32)]
+
+
+BATCHED_TUNING_KEYS = ("cell_frac", "rep_block", "tile_reach", "tiles")
+
+
 class _Bins(ctypes.Structure):
     _fields_ = [("r_max", ctypes.c_float), ("n_bins", ctypes.c_int32)]
 
@@ -69,6 +77,9 @@ _SIGS = {
     "apt_permute_labels": ([_P, ctypes.c_int64, ctypes.c_uint64, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_rdf_batched": ([ctypes.POINTER(_Cloud), _P, ctypes.c_int32, _P, ctypes.c_int32, _Bins, ctypes.c_int32,
                          _Bins, _P, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
+    "apt_batched_plan": ([ctypes.POINTER(_Cloud), _P, ctypes.c_int32, _Bins, ctypes.c_int32, _Bins, ctypes.c_int32,
+                          _P, _P], ctypes.c_int),
+    "apt_batched_plan_clear": ([], ctypes.c_int),
     "apt_rdf": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_rdf_noalloc": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, _P, _P], ctypes.c_int),
     "apt_knn": ([ctypes.POINTER(_Cloud), _Query, ctypes.c_int32, ctypes.c_float, ctypes.c_int64, _P, _P, _P,
@@ -270,11 +281,13 @@ def permute_labels(lab: torch.Tensor, seed: int, out: torch.Tensor | None = None
 
 def rdf_batched(cloud: Cloud, pairs, seeds, r_max: float = 2.0, n_bins: int = 200, k: int = 10,
                 kb_rmax: float = 5.0, kb_nbins: int = 5000, want_knn: bool = True,
-                ws: Workspace | None = None, out=None):
+                ws: Workspace | None = None, out=None, tuning: dict | None = None):
     """Null-model replicates: pairs = [(A, B, d_srf), ...], seeds = [seed_r, ...].
 
     Returns (rdf int64 [n_rep, n_pairs, n_bins], knn int64 [n_rep, n_pairs, kb_nbins + 1] or None,
-    status int32 [1]); (r, p) equals knn_rdf of pair p on permute_labels(lab, seeds[r])."""
+    status int32 [1]); (r, p) equals knn_rdf of pair p on permute_labels(lab, seeds[r]).
+    tuning: {cell_frac, rep_block, tile_reach, tiles} (missing keys: 0, the
+    library's default), or None for the library's cached autotuned plan."""
     n_pairs, n_rep = len(pairs), len(seeds)
     qs = (_Query * n_pairs)(*[_query(a, b, d) for a, b, d in pairs])
     sd = (ctypes.c_uint64 * n_rep)(*[int(x) & (2**64 - 1) for x in seeds])
@@ -288,10 +301,36 @@ def rdf_batched(cloud: Cloud, pairs, seeds, r_max: float = 2.0, n_bins: int = 20
     ws = ws if ws is not None else Workspace()
     nb = workspace_size(OP_BATCHED, cloud.n, n_pairs, n_rep)
     buf = ws.get(nb, dev)
+    tu = None
+    if tuning is not None:
+        unknown = set(tuning) - set(BATCHED_TUNING_KEYS)
+        if unknown:
+            raise ValueError(f"unknown batched tuning keys {sorted(unknown)}")
+        tu = ctypes.byref(_BatchedTuning(float(tuning.get("cell_frac", 0.0)), int(tuning.get("rep_block", 0)),
+                                         float(tuning.get("tile_reach", 0.0)), int(tuning.get("tiles", 0))))
     _check(lib().apt_rdf_batched(cloud.c(), qs, n_pairs, sd, n_rep, _bins(r_max, n_bins), int(k),
-                                 _bins(kb_rmax, kb_nbins), _ptr(rh), _ptr(kh), None, _ptr(st), _ptr(buf), nb,
+                                 _bins(kb_rmax, kb_nbins), _ptr(rh), _ptr(kh), tu, _ptr(st), _ptr(buf), nb,
                                  _stream(cloud.xyz)), "apt_rdf_batched")
     return rh, kh, st
+
+
+def batched_plan(cloud: Cloud, pairs, r_max: float = 2.0, n_bins: int = 200, k: int = 10, kb_rmax: float = 5.0,
+                 kb_nbins: int = 5000, want_knn: bool = True):
+    """The cached plan rdf_batched(tuning=None) uses for these arguments, or None."""
+    n_pairs = len(pairs)
+    qs = (_Query * n_pairs)(*[_query(a, b, d) for a, b, d in pairs])
+    out = _BatchedTuning()
+    cached = ctypes.c_int32(0)
+    _check(lib().apt_batched_plan(cloud.c(), qs, n_pairs, _bins(r_max, n_bins), int(k), _bins(kb_rmax, kb_nbins),
+                                  int(bool(want_knn)), ctypes.byref(out), ctypes.byref(cached)), "apt_batched_plan")
+    if not cached.value:
+        return None
+    return {kk: getattr(out, kk) for kk in BATCHED_TUNING_KEYS}
+
+
+def batched_plan_clear():
+    """Empty the library's batched plan and graph caches."""
+    _check(lib().apt_batched_plan_clear(), "apt_batched_plan_clear")
 
 
 def rdf(cloud: Cloud, target: int, neighbor: int, d_srf: float, r_max: float, n_bins: int,

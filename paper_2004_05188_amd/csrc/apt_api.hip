@@ -669,9 +669,55 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     return hip_check("pair launch");
 }
 
+// Argument checks of the batched path (no GPU work).
+static apt_status check_batched(const apt_cloud* cl, const apt_query* pairs, int32_t n_pairs, const uint64_t* seeds,
+                                int32_t n_rep, apt_bins rb, int32_t k, apt_bins kb, uint64_t* rdf_hist,
+                                uint64_t* knn_hist, int32_t* status) {
+    apt_status s;
+    if ((s = check_cloud(cl)) != APT_OK) return s;
+    if (!pairs || n_pairs < 1) return fail(APT_E_ARG, "pairs is NULL or n_pairs < 1");
+    if (n_pairs > kMaxPairs) return fail(APT_E_UNSUPPORTED, "at most 16 pairs per call");
+    if (!seeds || n_rep < 1) return fail(APT_E_ARG, "seeds is NULL or n_rep < 1");
+    if ((s = check_bins(rb, "rdf_bins")) != APT_OK) return s;
+    if (!rdf_hist) return fail(APT_E_ARG, "rdf_hist is NULL");
+    if (k < 1) return fail(APT_E_ARG, "k must be >= 1");
+    if (k > APT_MAX_K) return fail(APT_E_UNSUPPORTED, "k must be in [1, 256]");
+    if (knn_hist && (s = check_bins(kb, "knn_bins")) != APT_OK) return s;
+    if (!status) return fail(APT_E_ARG, "status is NULL");
+    if (batched_lds_bytes(rb.n_bins) > kMaxLds)
+        return fail(APT_E_UNSUPPORTED, "batched RDF supports at most 3072 bins");
+    // the output histograms are zeroed and indexed with 32-bit counts
+    const int64_t nh = (int64_t)n_rep * n_pairs * rb.n_bins;
+    const int64_t nk = knn_hist ? (int64_t)n_rep * n_pairs * ((int64_t)kb.n_bins + 1) : 0;
+    if (nh > (int64_t)INT32_MAX || nk > (int64_t)INT32_MAX)
+        return fail(APT_E_UNSUPPORTED, "n_rep * n_pairs * bins must stay below 2^31 for each histogram");
+    // species -> class; every species of the pairs gets one class
+    uint8_t slot[256];
+    int C = 0;
+    int cls_of[256];
+    for (int q = 0; q < 256; ++q) cls_of[q] = -1;
+    for (int p = 0; p < n_pairs; ++p) {
+        if (isnan(pairs[p].d_srf)) return fail(APT_E_ARG, "pair d_srf is NaN");
+        for (int v = 0; v < 2; ++v) {
+            const int sp = v ? pairs[p].neighbor : pairs[p].target;
+            if (sp == APT_ANY) return fail(APT_E_UNSUPPORTED, "batched pairs name concrete species (not APT_ANY)");
+            if (cls_of[sp] < 0) {
+                if (C >= kMaxClasses - 1) return fail(APT_E_UNSUPPORTED, "at most 7 species over all pairs");
+                cls_of[sp] = C++;
+            }
+        }
+    }
+    (void)slot;
+    return APT_OK;
+}
+
+// The batched path with a resolved tuning.  mid (optional) is recorded on
+// the stream once all ions are binned (the autotuner splits its trial
+// times there).
 static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32_t n_pairs, const uint64_t* seeds,
                               int32_t n_rep, apt_bins rb, int32_t k, apt_bins kb, uint64_t* rdf_hist,
-                              uint64_t* knn_hist, int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+                              uint64_t* knn_hist, int32_t* status, void* ws, size_t ws_bytes, void* stream,
+                              const apt_batched_tuning& bt, hipEvent_t mid = nullptr) {
     apt_status s;
     if ((s = check_cloud(cl)) != APT_OK) return s;
     if (!pairs || n_pairs < 1) return fail(APT_E_ARG, "pairs is NULL or n_pairs < 1");
@@ -709,7 +755,8 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
     const int Cn = C + 1;   // plus "other"
     for (int q = 0; q < 256; ++q) slot[q] = (uint8_t)(cls_of[q] >= 0 ? cls_of[q] : C);
     const int64_t n = cl->n;
-    const int R = batch_reps(n, n_rep);
+    int R = batch_reps(n, n_rep);
+    if (bt.rep_block > 0 && bt.rep_block < R) R = bt.rep_block;
     BatchWs w = carve_batched(ws, n, R);
     if ((s = check_ws(ws, ws_bytes, w.bytes)) != APT_OK) return s;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -730,7 +777,7 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
         CountArgs ca{cl->xyz, cl->lab, nullptr, n, chunk, APT_ANY, APT_ANY, 0.0f, nullptr, pw.part_cnt, pw.part_bbox,
                      pw.part_nf};
         hipLaunchKernelGGL(k_count, dim3(G), dim3(kBlock), 0, st, ca);
-        PlanParams pp{rb.r_max * 0.5f, 4.0f, k, cell_cap_for(n), 1, rb.r_max};
+        PlanParams pp{rb.r_max * bt.cell_frac, 4.0f, k, cell_cap_for(n), 1, rb.r_max};
         PlanArgs pa{G, pw.part_cnt, pw.part_bbox, pw.part_nf, pw.part_off, pp, nullptr, pw.plan, status};
         hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, pa);
         const int Gk = cus * 8;
@@ -758,6 +805,7 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
         hipLaunchKernelGGL(k_occupied, dim3(cus * 4), dim3(kBlock), 0, st, w.plain.plan, w.plain.cell_start,
                            reinterpret_cast<uint32_t*>(w.work + 4));
     }
+    if (mid) (void)hipEventRecord(mid, st);
     const int Gp = part_blocks(n);
     const int64_t pchunk = ((n + Gp - 1) / Gp + kPartTile - 1) / kPartTile * kPartTile;
     const size_t lds = batched_lds_bytes(rb.n_bins);
@@ -819,7 +867,8 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
         ba.items = w.items;
         ba.titems = w.titems;
         ba.work = w.work;
-        ba.tile_ok = (k <= 16 && batched_tile_lds_bytes(rb.n_bins) <= kMaxLds) ? 1 : 0;
+        ba.tile_ok = (k <= 16 && batched_tile_lds_bytes(rb.n_bins) <= kMaxLds && bt.tiles == 0) ? 1 : 0;
+        ba.tile_reach = bt.tile_reach;
         ba.occ = reinterpret_cast<const uint32_t*>(w.work + 4);
         ba.n_bins = rb.n_bins;
         ba.r_enum = (float)((double)rb.r_max * (1.0 + 4e-5));
@@ -851,6 +900,149 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
         }
     }
     return hip_check("batched launch");
+}
+
+// ------------------------------------------------- batched plans --
+// apt_rdf_batched(tuning = NULL): the tuning comes from a process-wide plan
+// cache keyed by what decides the best one (device, n, the pairs, bins, k,
+// whether the k-th histogram is wanted), filled on a miss by timing trial
+// launches; the launch sequence is captured once per call signature into a
+// HIP graph and replayed.
+static const apt_batched_tuning kBatchedDefaults = {0.5f, 0, 1.3f, 0};
+
+static apt_status resolve_batched_tuning(const apt_batched_tuning* t, apt_batched_tuning* out) {
+    apt_batched_tuning v = kBatchedDefaults;
+    if (t) {
+        if (!(t->cell_frac >= 0.0f && t->cell_frac <= 4.0f))
+            return fail(APT_E_ARG, "tuning.cell_frac must be in (0, 4] (0: default)");
+        if (t->rep_block < 0 || t->rep_block > kMaxRepPerLaunch)
+            return fail(APT_E_ARG, "tuning.rep_block must be in [1, 64] (0: default)");
+        if (!(t->tile_reach == 0.0f || (t->tile_reach >= 1.0f && t->tile_reach <= 4.0f)))
+            return fail(APT_E_ARG, "tuning.tile_reach must be in [1, 4] (0: default)");
+        if (t->tiles != 0 && t->tiles != 1) return fail(APT_E_ARG, "tuning.tiles must be 0 or 1");
+        v = *t;
+        if (v.cell_frac == 0.0f) v.cell_frac = kBatchedDefaults.cell_frac;
+        if (v.tile_reach == 0.0f) v.tile_reach = kBatchedDefaults.tile_reach;
+    }
+    *out = v;
+    return APT_OK;
+}
+
+template <class T>
+static void key_put(std::string& k, const T& v) {
+    k.append(reinterpret_cast<const char*>(&v), sizeof(T));
+}
+
+static std::string batched_plan_key(const apt_cloud* cl, const apt_query* pairs, int32_t n_pairs, apt_bins rb,
+                                    int32_t k, apt_bins kb, bool want_knn) {
+    std::string key;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    key_put(key, dev);
+    key_put(key, cl->n);
+    key_put(key, cl->d_bnd != nullptr);
+    key_put(key, n_pairs);
+    for (int p = 0; p < n_pairs; ++p) {
+        key_put(key, pairs[p].target);
+        key_put(key, pairs[p].neighbor);
+        key_put(key, pairs[p].d_srf);
+    }
+    key_put(key, rb.r_max);
+    key_put(key, rb.n_bins);
+    key_put(key, k);
+    key_put(key, want_knn);
+    if (want_knn) {
+        key_put(key, kb.r_max);
+        key_put(key, kb.n_bins);
+    }
+    return key;
+}
+
+static std::mutex g_plan_mu;
+static std::map<std::string, apt_batched_tuning> g_plans;
+
+// Trial launches of a few replicates for a grid of cell edges and tile
+// reaches, timed with events on the caller's stream; the score weights the
+// per-replicate time by the call's replicate count.
+static apt_status autotune_batched(const apt_cloud* cl, const apt_query* pairs, int32_t n_pairs, const uint64_t* seeds,
+                                   int32_t n_rep, apt_bins rb, int32_t k, apt_bins kb, uint64_t* rdf_hist,
+                                   uint64_t* knn_hist, int32_t* status, void* ws, size_t ws_bytes, void* stream,
+                                   apt_batched_tuning* best) {
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int nt = n_rep < 4 ? n_rep : 4;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto& f : ev)
+                if (f) (void)hipEventDestroy(f);
+            return fail(APT_E_HIP, "autotune: hipEventCreate failed");
+        }
+    apt_batched_tuning base = kBatchedDefaults;
+    base.rep_block = nt;
+    apt_status s = run_batched(cl, pairs, n_pairs, seeds, nt, rb, k, kb, rdf_hist, knn_hist, status, ws, ws_bytes,
+                               stream, base);                  // warm-up
+    double best_score = INFINITY;
+    *best = kBatchedDefaults;
+    const float cells[] = {0.35f, 0.5f, 0.7f};
+    const float reaches[] = {1.15f, 1.3f, 1.6f};
+    for (float cf : cells) {
+        for (float tr : reaches) {
+            if (s != APT_OK) break;
+            apt_batched_tuning t = base;
+            t.cell_frac = cf;
+            t.tile_reach = tr;
+            (void)hipEventRecord(ev[0], st);
+            s = run_batched(cl, pairs, n_pairs, seeds, nt, rb, k, kb, rdf_hist, knn_hist, status, ws, ws_bytes,
+                            stream, t, ev[1]);
+            (void)hipEventRecord(ev[2], st);
+            if (s != APT_OK) break;
+            float t_bin = 0.0f, t_rep = 0.0f;
+            if (hipEventSynchronize(ev[2]) != hipSuccess || hipEventElapsedTime(&t_bin, ev[0], ev[1]) != hipSuccess ||
+                hipEventElapsedTime(&t_rep, ev[1], ev[2]) != hipSuccess) {
+                s = fail(APT_E_HIP, "autotune: event timing failed");
+                break;
+            }
+            const double score = (double)t_bin + (double)t_rep * (double)n_rep / (double)nt;
+            if (score < best_score) {
+                best_score = score;
+                *best = t;
+            }
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    best->rep_block = 0;      // as many replicates per block as the workspace holds
+    return s;
+}
+
+struct GraphEntry {
+    std::string key;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+static std::mutex g_graph_mu;
+static std::vector<GraphEntry> g_graphs;     // most recent last
+constexpr size_t kMaxGraphs = 8;
+
+static void drop_graph(GraphEntry& e) {
+    (void)hipGraphExecDestroy(e.exec);
+    (void)hipGraphDestroy(e.graph);
+}
+
+// A stream of the library's own per device to capture on (a capture does
+// not run anything; the graph is launched on the caller's stream, which may
+// be the null stream).  Default priority.
+static hipStream_t capture_stream() {
+    static std::mutex mu;
+    static std::map<int, hipStream_t> streams;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = streams.find(dev);
+    if (it != streams.end()) return it->second;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    streams[dev] = s;
+    return s;
 }
 
 // Workspace of the smoothed RDF: the plain binning, the edges and the
@@ -1099,11 +1291,128 @@ apt_status apt_permute_labels(const uint8_t* lab, int64_t n, uint64_t seed, uint
 
 apt_status apt_rdf_batched(const apt_cloud* cloud, const apt_query* pairs, int32_t n_pairs, const uint64_t* seeds,
                            int32_t n_rep, apt_bins rdf_bins, int32_t k, apt_bins knn_bins, uint64_t* rdf_hist,
-                           uint64_t* knn_hist, const void* tuning, int32_t* status, void* ws, size_t ws_bytes,
-                           void* stream) {
-    (void)tuning;
-    return run_batched(cloud, pairs, n_pairs, seeds, n_rep, rdf_bins, k, knn_bins, rdf_hist, knn_hist, status, ws,
-                       ws_bytes, stream);
+                           uint64_t* knn_hist, const apt_batched_tuning* tuning, int32_t* status, void* ws,
+                           size_t ws_bytes, void* stream) {
+    apt_batched_tuning bt;
+    apt_status s;
+    if (tuning) {
+        if ((s = resolve_batched_tuning(tuning, &bt)) != APT_OK) return s;
+        return run_batched(cloud, pairs, n_pairs, seeds, n_rep, rdf_bins, k, knn_bins, rdf_hist, knn_hist, status,
+                           ws, ws_bytes, stream, bt);
+    }
+    // arguments first (the plan key reads them; the autotuner's trials must
+    // not be the first to reject them)
+    if ((s = check_batched(cloud, pairs, n_pairs, seeds, n_rep, rdf_bins, k, knn_bins, rdf_hist, knn_hist,
+                           status)) != APT_OK)
+        return s;
+    if ((s = check_ws(ws, ws_bytes, carve_batched(nullptr, cloud->n, batch_reps(cloud->n, n_rep)).bytes)) != APT_OK)
+        return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (st && hipStreamIsCapturing(st, &cap) != hipSuccess) cap = hipStreamCaptureStatusNone;
+    const bool capturing = cap != hipStreamCaptureStatusNone;
+    const std::string pkey = batched_plan_key(cloud, pairs, n_pairs, rdf_bins, k, knn_bins, knn_hist != nullptr);
+    bool have = false;
+    {
+        std::lock_guard<std::mutex> g(g_plan_mu);
+        auto it = g_plans.find(pkey);
+        if (it != g_plans.end()) {
+            bt = it->second;
+            have = true;
+        }
+    }
+    if (!have) {
+        if (capturing) {
+            // no timing inside a capture: the defaults, not cached
+            return run_batched(cloud, pairs, n_pairs, seeds, n_rep, rdf_bins, k, knn_bins, rdf_hist, knn_hist,
+                               status, ws, ws_bytes, stream, kBatchedDefaults);
+        }
+        if ((s = autotune_batched(cloud, pairs, n_pairs, seeds, n_rep, rdf_bins, k, knn_bins, rdf_hist, knn_hist,
+                                  status, ws, ws_bytes, stream, &bt)) != APT_OK)
+            return s;
+        std::lock_guard<std::mutex> g(g_plan_mu);
+        g_plans[pkey] = bt;
+    }
+    if (capturing || g_trace_on.load() != 0)
+        return run_batched(cloud, pairs, n_pairs, seeds, n_rep, rdf_bins, k, knn_bins, rdf_hist, knn_hist, status,
+                           ws, ws_bytes, stream, bt);
+    // the launch sequence as a graph, per call signature
+    std::string gkey = pkey;
+    key_put(gkey, n_rep);
+    for (int r = 0; r < n_rep; ++r) key_put(gkey, seeds[r]);
+    key_put(gkey, cloud->xyz);
+    key_put(gkey, cloud->lab);
+    key_put(gkey, cloud->d_bnd);
+    key_put(gkey, rdf_hist);
+    key_put(gkey, knn_hist);
+    key_put(gkey, status);
+    key_put(gkey, ws);
+    key_put(gkey, ws_bytes);
+    {
+        std::lock_guard<std::mutex> g(g_graph_mu);
+        for (auto& e : g_graphs)
+            if (e.key == gkey) {
+                if (hipGraphLaunch(e.exec, st) != hipSuccess) return fail(APT_E_HIP, "hipGraphLaunch failed");
+                return APT_OK;
+            }
+    }
+    hipStream_t cs = capture_stream();
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool ok = cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        s = run_batched(cloud, pairs, n_pairs, seeds, n_rep, rdf_bins, k, knn_bins, rdf_hist, knn_hist, status, ws,
+                        ws_bytes, cs, bt);
+        ok = hipStreamEndCapture(cs, &graph) == hipSuccess && graph != nullptr;
+        if (s != APT_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return s;
+        }
+        ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    }
+    (void)hipGetLastError();
+    if (!ok) {
+        // no graph: the same sequence launched directly
+        if (graph) (void)hipGraphDestroy(graph);
+        return run_batched(cloud, pairs, n_pairs, seeds, n_rep, rdf_bins, k, knn_bins, rdf_hist, knn_hist, status,
+                           ws, ws_bytes, stream, bt);
+    }
+    if (hipGraphLaunch(exec, st) != hipSuccess) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return fail(APT_E_HIP, "hipGraphLaunch failed");
+    }
+    std::lock_guard<std::mutex> g(g_graph_mu);
+    if (g_graphs.size() >= kMaxGraphs) {
+        drop_graph(g_graphs.front());
+        g_graphs.erase(g_graphs.begin());
+    }
+    g_graphs.push_back(GraphEntry{gkey, graph, exec});
+    return APT_OK;
+}
+
+apt_status apt_batched_plan(const apt_cloud* cloud, const apt_query* pairs, int32_t n_pairs, apt_bins rdf_bins,
+                            int32_t k, apt_bins knn_bins, int32_t want_knn_hist, apt_batched_tuning* out,
+                            int32_t* cached) {
+    if (!cloud || !pairs || n_pairs < 1 || n_pairs > kMaxPairs || !out || !cached)
+        return fail(APT_E_ARG, "apt_batched_plan: NULL or out-of-range argument");
+    const std::string key = batched_plan_key(cloud, pairs, n_pairs, rdf_bins, k, knn_bins, want_knn_hist != 0);
+    std::lock_guard<std::mutex> g(g_plan_mu);
+    auto it = g_plans.find(key);
+    *cached = it != g_plans.end() ? 1 : 0;
+    if (*cached) *out = it->second;
+    return APT_OK;
+}
+
+apt_status apt_batched_plan_clear(void) {
+    {
+        std::lock_guard<std::mutex> g(g_plan_mu);
+        g_plans.clear();
+    }
+    std::lock_guard<std::mutex> g(g_graph_mu);
+    for (auto& e : g_graphs) drop_graph(e);
+    g_graphs.clear();
+    return APT_OK;
 }
 
 apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_targets, void* ws, size_t ws_bytes,

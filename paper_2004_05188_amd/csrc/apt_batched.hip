@@ -163,12 +163,12 @@ __global__ __launch_bounds__(kBlock) void k_bpart_empty(PartArgs a) {
         cs[cc] = (uint32_t)s0;
 }
 
-// Certified kNN radius of a tile: 1.3x the Poisson mean k-th distance (the
-// first kNN radius rk0 is 1.15x that mean).  Smaller radii stage fewer
-// candidates, larger ones leave fewer targets to the exact one-by-one
-// fallback; on the clustered needle 1.3x was fastest (1.0x took 3.4x its
-// time, 1.15x 1.2x, 1.6x 1.14x, 2.0x 1.5x).
-constexpr float kTileReach = 1.3f / 1.15f;   // times rk0
+// Certified kNN radius of a tile: tile_reach (default 1.3) times the
+// Poisson mean k-th distance (the first kNN radius rk0 is 1.15x that mean).
+// Smaller radii stage fewer candidates, larger ones leave fewer targets to
+// the exact one-by-one fallback; on the clustered needle 1.3x was fastest
+// (1.0x took 3.4x its time, 1.15x 1.2x, 1.6x 1.14x, 2.0x 1.5x).
+__device__ inline float tile_reach_rk0(const BatchPairArgs& a) { return a.tile_reach / 1.15f; }
 
 // Cells that hold at least one ion (all ions are binned here), counted once
 // per call: their volume is the specimen's, unlike the bounding box's (a
@@ -209,7 +209,7 @@ __device__ inline bool batch_tiled(const BatchPairArgs& a, const GridPlan& P, in
     const uint64_t nb = seg_end(a.cnt, 0, a.C, a.G, a.pairs[p].b, a.n) - seg_start(a.cnt, 0, a.C, a.G, a.pairs[p].b);
     if (na < nb || na < 4096) return false;
     const double vol = batch_volume(a, P);
-    const double rk_tile = (double)kTileReach * (double)batch_rk0(P, vol, nb, a.k);
+    const double rk_tile = (double)tile_reach_rk0(a) * (double)batch_rk0(P, vol, nb, a.k);
     const double R = fmax((double)a.r_enum, rk_tile);
     return 64.0 * vol / (double)na <= R * R * R;
 }
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_pair_batched_tile(BatchPairArgs a
             T.bpos = a.Pp;
             T.cell_start = a.CS + ((size_t)r * (a.C - 1) + bp.b) * (size_t)a.cs_stride;
             T.rk0 = batch_rk0(P, vol, b1 - b0, a.k);
-            Rk = fminf(kTileReach * T.rk0, P.r_all);
+            Rk = fminf(tile_reach_rk0(a) * T.rk0, P.r_all);
             T.hist_g = a.rdf_hist + ((size_t)(a.rep0 + r) * a.n_pairs + p) * a.n_bins;
             d_srf = bp.d_srf;
         }

@@ -52,7 +52,8 @@ struct BatchPairArgs {
     uint64_t* titems;         // [R * n_pairs + 1] prefix of 64-target tiles (tiled pairs)
     uint64_t* work;           // [2] work counters: targets, tiles (zeroed by k_batch_items)
     const uint32_t* occ;      // [1] cells holding at least one ion (the specimen's volume in cells)
-    int32_t tile_ok;          // tiles allowed (k <= 16, LDS fits)
+    int32_t tile_ok;          // tiles allowed (k <= 16, LDS fits, tuning)
+    float tile_reach;         // certified kNN reach of a tile, times the Poisson mean k-th distance
     // RDF
     int32_t n_bins;
     float r_enum, thr2, inv_w, delta_b;
