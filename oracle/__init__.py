@@ -42,6 +42,9 @@ def _load():
         sig = {
             "orc_threads": ([], _i32),
             "orc_set_threads": ([_i32], None),
+            "orc_sdm_faces": ([_f32, _i32, _p], None),
+            "orc_sdm_brute": ([_p, _p, _p, _i64, _i32, _i32, _f32, _f32, _i32, _p], None),
+            "orc_sdm_grid": ([_p, _p, _p, _i64, _i32, _i32, _f32, _f32, _i32, _p], None),
             "orc_d2f": ([_p, _p], _f32),
             "orc_D2": ([_p, _p], _f64),
             "orc_edges2": ([_f32, _i32, _p], None),
@@ -147,6 +150,23 @@ def knn(xyz, lab, d_bnd, A: int, B: int, d_srf: float, k: int, r_knn_max: float 
           tid.ctypes.data, dist.ctypes.data, nid.ctypes.data, kb_rmax, kb_nbins, _ptr(hist))
     assert t == T
     return tid[:T], dist[:T], nid[:T], hist
+
+
+def sdm_faces(R: float, n_vox: int) -> np.ndarray:
+    """Voxel faces f_m = ((2m - n) R) / n, m = 0..n (FP64)."""
+    F = np.empty(n_vox + 1, dtype=np.float64)
+    _load().orc_sdm_faces(R, n_vox, F.ctypes.data)
+    return F
+
+
+def sdm(xyz, lab, d_bnd, A: int, B: int, d_srf: float, R: float, n_vox: int, method: str = "grid") -> np.ndarray:
+    """Two-point statistic: counts of pair displacement vectors per cubic voxel,
+    uint64 [n_vox, n_vox, n_vox] indexed [mz, my, mx]."""
+    xyz, lab, d_bnd = _cloud(xyz, lab, d_bnd)
+    hist = np.zeros(n_vox ** 3, dtype=np.uint64)
+    f = _load().orc_sdm_grid if method == "grid" else _load().orc_sdm_brute
+    f(xyz.ctypes.data, lab.ctypes.data, _ptr(d_bnd), xyz.shape[0], A, B, d_srf, R, n_vox, hist.ctypes.data)
+    return hist.reshape(n_vox, n_vox, n_vox)
 
 
 def splitmix64(seed: int, i: int) -> int:

@@ -753,3 +753,94 @@ void orc_set_threads(int32_t n) {
     (void)n;
 #endif
 }
+
+/* ---------------------------------------------------------------------- */
+/* Two-point statistics: the 3-D histogram of displacement vectors         */
+/* ---------------------------------------------------------------------- */
+/* RDF and kNN integrate the more general two-point statistic over
+ * directions (paper, Methods: "Descriptive, two-point spatial statistics,
+ * and clustering"; its serial sections are the spatial distribution maps).
+ * Here: every ordered pair (target i, neighbour j != i) within R (the RDF's
+ * rule: FP64 squared distance below R*R) adds one count to the cubic voxel
+ * that holds its displacement v = p_j - p_i, each component the FP64
+ * difference of the stored FP32 coordinates.  n voxels per axis cover
+ * [-R, R); voxel m of an axis is [f_m, f_{m+1}) with the faces
+ * f_m = ((2m - n) * R) / n in FP64; the flat index is (mz * n + my) * n + mx. */
+
+void orc_sdm_faces(float R, int32_t n, double* F) {
+    for (int32_t m = 0; m <= n; ++m) F[m] = ((double)(2 * m - n) * (double)R) / (double)n;
+}
+
+/* largest m in [0, n) with F[m] <= v (v in [F[0], F[n]) for a counted pair) */
+static int32_t face_bin(double v, const double* F, int32_t n) {
+    int32_t lo = 0, hi = n; /* F[lo] <= v < F[hi] */
+    while (hi - lo > 1) {
+        int32_t mid = lo + (hi - lo) / 2;
+        if (F[mid] <= v) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+static int64_t sdm_index(const float* pi, const float* pj, const double* F, int32_t n) {
+    int64_t m[3];
+    for (int a = 0; a < 3; ++a) m[a] = face_bin((double)pj[a] - (double)pi[a], F, n);
+    return (m[2] * n + m[1]) * n + m[0];
+}
+
+void orc_sdm_brute(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n, int32_t A, int32_t B,
+                   float d_srf, float R, int32_t n_vox, uint64_t* hist) {
+    double E2[2];
+    orc_edges2(R, 1, E2);
+    double* F = (double*)malloc(sizeof(double) * (size_t)(n_vox + 1));
+    orc_sdm_faces(R, n_vox, F);
+    memset(hist, 0, sizeof(uint64_t) * (size_t)n_vox * (size_t)n_vox * (size_t)n_vox);
+    for (int64_t i = 0; i < n; ++i) {
+        if (!is_target(i, lab, d_bnd, A, d_srf) || !finite3(xyz + 3 * i)) continue;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i || !is_species(lab[j], B) || !finite3(xyz + 3 * j)) continue;
+            if (!(orc_D2(xyz + 3 * i, xyz + 3 * j) < E2[1])) continue;
+            hist[sdm_index(xyz + 3 * i, xyz + 3 * j, F, n_vox)]++;
+        }
+    }
+    free(F);
+}
+
+void orc_sdm_grid(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n, int32_t A, int32_t B,
+                  float d_srf, float R, int32_t n_vox, uint64_t* hist) {
+    double E2[2];
+    orc_edges2(R, 1, E2);
+    double* F = (double*)malloc(sizeof(double) * (size_t)(n_vox + 1));
+    orc_sdm_faces(R, n_vox, F);
+    const size_t nv = (size_t)n_vox * (size_t)n_vox * (size_t)n_vox;
+    ogrid g;
+    ogrid_build(&g, n, lab, B, pos_plain, xyz, (double)R * (1.0 + 1e-6));
+    memset(hist, 0, sizeof(uint64_t) * nv);
+    /* targets in parallel; counts are added with atomic increments (integer
+     * sums: the result does not depend on the order) */
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        if (!is_target(i, lab, d_bnd, A, d_srf) || !finite3(xyz + 3 * i)) continue;
+        const float* pi = xyz + 3 * i;
+        int64_t c[3];
+        for (int a = 0; a < 3; ++a) c[a] = ocell_axis(&g, a, (double)pi[a]);
+        for (int64_t z = c[2] - 1; z <= c[2] + 1; ++z) {
+            if (z < 0 || z >= g.dim[2]) continue;
+            for (int64_t y = c[1] - 1; y <= c[1] + 1; ++y) {
+                if (y < 0 || y >= g.dim[1]) continue;
+                for (int64_t x = c[0] - 1; x <= c[0] + 1; ++x) {
+                    if (x < 0 || x >= g.dim[0]) continue;
+                    int64_t cell = (z * g.dim[1] + y) * g.dim[0] + x;
+                    for (int64_t t = g.start[cell]; t < g.start[cell + 1]; ++t) {
+                        int64_t j = g.item[t];
+                        if (j == i || !(orc_D2(pi, xyz + 3 * j) < E2[1])) continue;
+                        int64_t v = sdm_index(pi, xyz + 3 * j, F, n_vox);
+#pragma omp atomic
+                        hist[v]++;
+                    }
+                }
+            }
+        }
+    }
+    ogrid_free(&g);
+    free(F);
+}

@@ -21,6 +21,11 @@ extern "C" {
 /* Number of OpenMP threads the oracle's loops use. */
 int32_t orc_threads(void);
 void orc_set_threads(int32_t n);
+void orc_sdm_faces(float R, int32_t n, double* F);
+void orc_sdm_brute(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n, int32_t A, int32_t B,
+                   float d_srf, float R, int32_t n_vox, uint64_t* hist);
+void orc_sdm_grid(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n, int32_t A, int32_t B,
+                  float d_srf, float R, int32_t n_vox, uint64_t* hist);
 
 /* Canonical distances between two stored FP32 positions. */
 float orc_d2f(const float* a, const float* b);   /* FP32, fixed evaluation order */

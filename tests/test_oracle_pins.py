@@ -628,3 +628,107 @@ def test_permutation_direction_bit_exact(orc, n):
         inv[np.array(pi)] = lab
         inverse_differs += not np.array_equal(inv, expect)
     assert inverse_differs >= 3
+
+
+# --------------------------------------------------------------------------
+# two-point statistics (displacement-vector histogram)
+# --------------------------------------------------------------------------
+
+def _fcc_block(a, M):
+    g = np.arange(2 * M)
+    I, J, K = np.meshgrid(g, g, g, indexing="ij")
+    keep = (I + J + K) % 2 == 0
+    xyz = (np.stack([I[keep], J[keep], K[keep]], 1) * (a / 2)).astype(np.float32)
+    hi = (2 * M - 1) * a / 2
+    d = np.minimum(xyz, hi - xyz).min(1).astype(np.float32)
+    return xyz, d
+
+
+def _voxel_of(v, R, n):
+    # exact voxel of a displacement component v (a Fraction): largest m with
+    # ((2m - n) R) / n <= v
+    from fractions import Fraction
+
+    m = math.floor((Fraction(v) + Fraction(R)) * n / (2 * Fraction(R)))
+    return min(max(m, 0), n - 1)
+
+
+def test_sdm_fcc_lattice_exact_vectors(orc):
+    # Interior targets of an fcc lattice see every lattice vector (a/2)(h,k,l),
+    # h+k+l even, |v| < R, exactly once: T counts in its voxel, 0 elsewhere.
+    # Components are >= 2e-3 nm from any face (multiples of 0.202 nm against
+    # faces every 0.025 nm) except 0, where the FP32 difference is exactly 0
+    # and the half-open rule puts it in voxel n/2.
+    from fractions import Fraction
+
+    rows, meta = _read_table("fcc_shells.txt")
+    a = meta["lattice_constant_nm"]
+    R, n = 2.0, 160
+    xyz, d = _fcc_block(a, 14)
+    lab = np.zeros(len(xyz), np.uint8)
+    h = orc.sdm(xyz, lab, d, AL, AL, R + 0.01, R, n)
+    T = len(orc.select_targets(lab, d, AL, R + 0.01))
+    assert T > 100
+    expect = np.zeros((n, n, n), np.int64)
+    half = Fraction(a) / 2
+    g = range(-10, 11)
+    vectors = 0
+    for i in g:
+        for j in g:
+            for k in g:
+                if (i + j + k) % 2 or (i, j, k) == (0, 0, 0) or float(half) ** 2 * (i * i + j * j + k * k) >= R * R:
+                    continue
+                mx, my, mz = (_voxel_of(half * c, R, n) for c in (i, j, k))
+                assert expect[mz, my, mx] == 0          # one lattice vector per voxel
+                expect[mz, my, mx] = T
+                vectors += 1
+    assert vectors == 2092
+    assert np.array_equal(h.astype(np.int64), expect)
+
+
+def test_sdm_sign_and_axes_on_placed_pairs(orc):
+    # v = p_neighbour - p_target, voxel index (mz, my, mx): single pairs with
+    # known displacements land in the voxels computed exactly by hand
+    R, n = 1.0, 40                      # voxels of 0.05 nm
+    t = np.array([5.0, 5.0, 5.0], np.float32)
+    cases = [(0.31, 0.12, -0.23), (-0.6, 0.04, 0.3), (0.0, -0.5, 0.0), (0.7, 0.0, -0.04)]
+    for v in cases:
+        xyz = np.stack([t, (t.astype(np.float64) + v).astype(np.float32)])
+        lab = np.array([SC, AL], np.uint8)
+        h = orc.sdm(xyz, lab, None, SC, AL, 0.0, R, n, method="brute")
+        assert h.sum() == 1
+        dv = [float(np.float64(xyz[1, c]) - np.float64(xyz[0, c])) for c in range(3)]
+        mx, my, mz = (_voxel_of(c, R, n) for c in dv)
+        assert h[mz, my, mx] == 1, (v, np.argwhere(h))
+        # the reverse query sees -v
+        hr = orc.sdm(xyz, lab, None, AL, SC, 0.0, R, n, method="brute")
+        rx, ry, rz = (_voxel_of(-c, R, n) for c in dv)
+        assert hr[rz, ry, rx] == 1
+
+
+@pytest.mark.parametrize("A,B,use_d", [(SC, SC, False), (SC, AL, True), (ANY, SI, False), (AL, ANY, True)])
+def test_sdm_brute_equals_grid_and_sums_to_rdf(orc, synth, A, B, use_d):
+    xyz, lab, d = synth.Specimen(shape="box", L=(9.0, 9.0, 9.0), n=6000, seed=41, p_m_sc=0.1,
+                                 p_m_si=0.05, n_clusters=6, r_c=1.0).generate()
+    d = d if use_d else None
+    R, n = 1.5, 30
+    hb = orc.sdm(xyz, lab, d, A, B, 0.5, R, n, method="brute")
+    hg = orc.sdm(xyz, lab, d, A, B, 0.5, R, n, method="grid")
+    assert np.array_equal(hb, hg)
+    # every pair the RDF counts within R is in exactly one voxel
+    assert int(hb.sum()) == int(orc.rdf(xyz, lab, d, A, B, 0.5, R, 7, method="brute").sum())
+
+
+def test_sdm_inversion_symmetry_and_axis_swap(orc, synth):
+    xyz, lab, d = synth.Specimen(shape="box", L=(10.0, 10.0, 10.0), n=8000, seed=43, p_m_sc=0.2).generate()
+    R, n = 2.0, 32
+    h = orc.sdm(xyz, lab, None, SC, SC, 0.0, R, n)
+    # A->A without a surface filter: every unordered pair gives v and -v
+    # (no component lies exactly on a face for these continuous positions)
+    assert np.array_equal(h, h[::-1, ::-1, ::-1])
+    assert h.sum() > 1000
+    # swapping the x and y coordinates swaps the x and y voxel axes
+    sw = np.ascontiguousarray(xyz[:, [1, 0, 2]])
+    hs = orc.sdm(sw, lab, None, SC, SC, 0.0, R, n)
+    assert np.array_equal(hs, np.transpose(h, (0, 2, 1)))
+    assert not np.array_equal(h, np.transpose(h, (0, 2, 1)))
