@@ -163,6 +163,30 @@ def smooth_timing(aptstat, torch, reps=10):
             "smoothed_mass": float(h.sum().item())}
 
 
+def sdm_timing(aptstat, torch, cloud, ws, reps=5):
+    """Two-point statistic (3-D displacement histogram, R = 2 nm, 0.025 nm
+    voxels: 160^3) of Sc -> Al on the 7.7e6-ion needle: ms per call and
+    in-range pairs per second of its kernel."""
+    R, n_vox = 2.0, 160
+    h = aptstat.sdm(cloud, SC, AL, 1.0, R, n_vox, ws=ws)
+    torch.cuda.synchronize()
+    pairs = int(h.sum().item())
+    for stage in ("sdm", "binning"):
+        aptstat.trace_read(stage)
+    aptstat.trace_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        aptstat.sdm(cloud, SC, AL, 1.0, R, n_vox, ws=ws, out=h)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    aptstat.trace_enable(False)
+    k_ms = aptstat.trace_read("sdm")[0] / reps
+    b_ms = aptstat.trace_read("binning")[0] / reps
+    return {"workload": "frustum7m", "query": "Sc->Al", "d_srf_nm": 1.0, "R_nm": R, "n_vox": n_vox,
+            "ms_per_call": 1e3 * dt, "kernel_ms": k_ms, "binning_ms": b_ms, "pairs": pairs,
+            "pairs_per_s_kernel": pairs / (k_ms / 1e3) if k_ms > 0 else None}
+
+
 PAIRS6 = [(AL, SC), (AL, SI), (SC, AL), (SC, SI), (SI, AL), (SI, SC)]
 
 
@@ -468,6 +492,8 @@ def main():
             cloud = aptstat.Cloud(xyz_d, lab_d, d_d)
             line["batched"] = batched_vs_looped(aptstat, torch, cloud, ws, args.batched_reps,
                                                 min(args.looped_reps, args.batched_reps))
+            log("[bench] two-point statistic on frustum7m")
+            line["sdm"] = sdm_timing(aptstat, torch, cloud, ws)
             del cloud, xyz_d, lab_d, d_d
         if not args.no_smooth:
             log("[bench] smoothed RDF on box1m")

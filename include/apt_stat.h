@@ -97,7 +97,8 @@ enum {
     APT_OP_KNN_RDF = 3,   /* apt_knn_rdf                           */
     APT_OP_PERMUTE = 4,   /* apt_permute_labels                    */
     APT_OP_BATCHED = 5,   /* apt_rdf_batched (n_pairs, n_rep used) */
-    APT_OP_SMOOTH = 6     /* apt_rdf_smooth_fwd / _bwd             */
+    APT_OP_SMOOTH = 6,    /* apt_rdf_smooth_fwd / _bwd             */
+    APT_OP_SDM = 7        /* apt_sdm                               */
 };
 
 /* Bytes of device workspace an operation needs for n ions (host only, no
@@ -224,6 +225,24 @@ apt_status apt_batched_plan(const apt_cloud* cloud, const apt_query* pairs, int3
                             int32_t* cached);
 apt_status apt_batched_plan_clear(void);
 
+/* Two-point statistic of one query (paper, Methods: "Descriptive, two-point
+ * spatial statistics, and clustering": the RDF and kNN integrate it over
+ * directions; its sections through the target's plane are the spatial
+ * distribution maps, computed in the paper with R = 2 nm and voxels of
+ * 0.025 nm).  Every ordered pair (eligible target i, neighbour j != i)
+ * within R (FP64 squared distance below R*R, the RDF's rule) adds one count
+ * to the cubic voxel of its displacement v = p_j - p_i, each component the
+ * FP64 difference of the stored FP32 coordinates.  n_vox voxels per axis
+ * cover [-R, R): voxel m of an axis is [f_m, f_{m+1}), f_m = ((2m - n_vox)
+ * R) / n_vox in FP64.
+ *   R        ROI radius (nm), finite, > 0
+ *   n_vox    voxels per axis, 1..512 (R = 2 nm with 0.025 nm voxels: 160)
+ *   hist     [n_vox][n_vox][n_vox] uint64, device, overwritten; element
+ *            (mz, my, mx), x fastest
+ * Workspace: APT_OP_SDM. */
+apt_status apt_sdm(const apt_cloud* cloud, apt_query q, float R, int32_t n_vox, uint64_t* hist, int32_t* status,
+                   void* ws, size_t ws_bytes, void* stream);
+
 /* Gaussian-smoothed RDF, an extension (not in the paper) of the RDF's
  * rectangular transfer function (paper, Methods: "Descriptive, two-point
  * spatial statistics") that is differentiable in the positions and in a
@@ -322,6 +341,7 @@ apt_status apt_get_tuning(apt_tuning* t);
  * (ms) and number of launches of one stage ("binning" = bounding box to
  * sorted records, "pair" = the pair kernel, "tile" = the 64-target kernel
  * (and the per-lane kNN of mode 4), "nbr" = the neighbour-major RDF kernel,
+ * "sdm" = the two-point statistic's kernel,
  * "permute" and "partition" = the batched replicates' label permutation and
  * class split) and forgets that stage's records.  Host only; off by
  * default. */

@@ -26,7 +26,7 @@ _SO = os.path.join(_HERE, "libaptstat.so")
 
 STATUS_NONFINITE = 1
 STATUS_CAPACITY = 2
-OP_RDF, OP_KNN, OP_KNN_RDF, OP_PERMUTE, OP_BATCHED, OP_SMOOTH = 1, 2, 3, 4, 5, 6
+OP_RDF, OP_KNN, OP_KNN_RDF, OP_PERMUTE, OP_BATCHED, OP_SMOOTH, OP_SDM = 1, 2, 3, 4, 5, 6, 7
 
 
 class AptError(RuntimeError):
@@ -82,6 +82,8 @@ _SIGS = {
     "apt_batched_plan_clear": ([], ctypes.c_int),
     "apt_rdf": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_rdf_noalloc": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, _P, _P], ctypes.c_int),
+    "apt_sdm": ([ctypes.POINTER(_Cloud), _Query, ctypes.c_float, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P],
+                ctypes.c_int),
     "apt_knn": ([ctypes.POINTER(_Cloud), _Query, ctypes.c_int32, ctypes.c_float, ctypes.c_int64, _P, _P, _P,
                  _Bins, _P, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_knn_rdf": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, ctypes.c_int32, ctypes.c_float, ctypes.c_int64,
@@ -343,6 +345,20 @@ def rdf(cloud: Cloud, target: int, neighbor: int, d_srf: float, r_max: float, n_
     status = status if status is not None else torch.empty(1, dtype=torch.int32, device=dev)
     _check(lib().apt_rdf(cloud.c(), _query(target, neighbor, d_srf), _bins(r_max, n_bins), _ptr(out),
                          _ptr(status), _ptr(buf), nb, _stream(cloud.xyz)), "apt_rdf")
+    return out
+
+
+def sdm(cloud: Cloud, target: int, neighbor: int, d_srf: float, R: float = 2.0, n_vox: int = 160,
+        ws: Workspace | None = None, out: torch.Tensor | None = None, status: torch.Tensor | None = None):
+    """Two-point statistic: counts of pair displacement vectors p_j - p_i within R
+    per cubic voxel of [-R, R)^3: int64 tensor [n_vox, n_vox, n_vox] indexed [mz, my, mx]."""
+    buf, nb = _ws(ws, OP_SDM, cloud)
+    dev = cloud.device
+    out = out if out is not None else torch.empty((n_vox, n_vox, n_vox), dtype=torch.int64, device=dev)
+    _need(out, torch.int64, (n_vox, n_vox, n_vox), "out")
+    status = status if status is not None else torch.empty(1, dtype=torch.int32, device=dev)
+    _check(lib().apt_sdm(cloud.c(), _query(target, neighbor, d_srf), float(R), int(n_vox), _ptr(out),
+                         _ptr(status), _ptr(buf), nb, _stream(cloud.xyz)), "apt_sdm")
     return out
 
 

@@ -14,6 +14,7 @@
 #include "apt_bin.hpp"
 #include "apt_pair.hpp"
 #include "apt_perm.hpp"
+#include "apt_sdm.hpp"
 #include "apt_smooth.hpp"
 
 namespace apt {
@@ -1045,6 +1046,66 @@ static hipStream_t capture_stream() {
     return s;
 }
 
+// ------------------------------------------------- two-point statistic --
+static apt_status run_sdm(const apt_cloud* cl, apt_query q, float R, int32_t n_vox, uint64_t* hist, int32_t* status,
+                          void* ws, size_t ws_bytes, void* stream) {
+    apt_status s;
+    if ((s = check_cloud(cl)) != APT_OK) return s;
+    if ((s = check_query(q)) != APT_OK) return s;
+    if (!(R > 0.0f) || !isfinite(R)) return fail(APT_E_ARG, "R must be finite and > 0");
+    if (n_vox < 1 || n_vox > kSdmMaxVox) return fail(APT_E_ARG, "n_vox must be in [1, 512]");
+    if (!hist) return fail(APT_E_ARG, "hist is NULL");
+    if (!status) return fail(APT_E_ARG, "status is NULL");
+    PlainWs w = carve_plain(ws, cl->n);
+    if ((s = check_ws(ws, ws_bytes, w.bytes)) != APT_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    const int64_t nv = (int64_t)n_vox * n_vox * n_vox;
+    InitArgs ia{status, hist, (int32_t)nv, nullptr, 0, nullptr, w.strag_count};
+    const apt_tuning tu = tuning();
+    const double Rd = (double)R;
+    PlanParams pp;
+    pp.h_min = R * tu.h_min_frac;
+    pp.occ = tu.cell_occ;
+    pp.tile_occ = tu.tile_occ;
+    pp.k = 0;
+    pp.cell_cap = cell_cap_for(cl->n);
+    pp.tile_policy = 1;                        // one target per wavefront
+    pp.r_enum = (float)(Rd * (1.0 + 4e-5));
+    pp.h_shrink = 0.7f;
+    {
+        TraceSpan span("binning", st);
+        if ((s = run_binning(cl, q, pp, w, status, st, nullptr, 0, &ia)) != APT_OK) return s;
+    }
+    hipLaunchKernelGGL(k_sdm_faces, dim3(1), dim3(kBlock), 0, st, w.E2, R, n_vox);
+    SdmArgs a{};
+    a.plan = w.plan;
+    a.t_id = w.t_id;
+    a.tx = w.tx;
+    a.ty = w.ty;
+    a.tz = w.tz;
+    a.bpos = w.bpos;
+    a.cell_start = w.cell_start;
+    a.self_possible = q.target == APT_ANY || q.neighbor == APT_ANY || q.target == q.neighbor;
+    a.R = R;
+    a.r_enum = pp.r_enum;
+    a.in2 = (float)((Rd * (1.0 - 2e-5)) * (Rd * (1.0 - 2e-5)));
+    a.out2 = (float)((Rd * (1.0 + 2e-5)) * (Rd * (1.0 + 2e-5)));
+    a.R2 = Rd * Rd;
+    a.n_vox = n_vox;
+    a.inv_w = (float)((double)n_vox / (2.0 * Rd));
+    // the FP32 voxel coordinate errs by < 2e-7 * n_vox voxels (difference,
+    // offset and scaling each rounded once): decide in FP64 within 16 ulps
+    a.band = (float)fmin(0.25, fmax(1e-4, 16.0 * 5.9604645e-8 * (double)n_vox));
+    a.F = w.E2;
+    a.hist = hist;
+    {
+        TraceSpan span("sdm", st);
+        hipLaunchKernelGGL(k_sdm, dim3(resident_grid(k_sdm, 0)), dim3(kBlock), 0, st, a);
+    }
+    return hip_check("two-point statistic launch");
+}
+
 // Workspace of the smoothed RDF: the plain binning, the edges and the
 // per-wavefront partial results.
 constexpr size_t kSmoothPart = (size_t)1 << 21;
@@ -1267,6 +1328,8 @@ size_t apt_workspace_size(int32_t op, int64_t n, int32_t n_pairs, int32_t n_rep)
             return carve_batched(nullptr, n, batch_reps(n, n_rep)).bytes;
         case APT_OP_SMOOTH:
             return carve_smooth(nullptr, n).bytes;
+        case APT_OP_SDM:
+            return carve_plain(nullptr, n).bytes;
         default:
             return 0;
     }
@@ -1413,6 +1476,11 @@ apt_status apt_batched_plan_clear(void) {
     for (auto& e : g_graphs) drop_graph(e);
     g_graphs.clear();
     return APT_OK;
+}
+
+apt_status apt_sdm(const apt_cloud* cloud, apt_query q, float R, int32_t n_vox, uint64_t* hist, int32_t* status,
+                   void* ws, size_t ws_bytes, void* stream) {
+    return run_sdm(cloud, q, R, n_vox, hist, status, ws, ws_bytes, stream);
 }
 
 apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_targets, void* ws, size_t ws_bytes,
