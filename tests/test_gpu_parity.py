@@ -385,6 +385,27 @@ def test_batched_equals_looped_frustum7m(gpu, needle7m):
     assert torch.equal(rh, lr) and torch.equal(kh, lk)
 
 
+def test_batched_frustum7m_replicate_against_oracle(gpu, orc, needle7m):
+    # the full-size batched call's first replicate, all six pairs, against
+    # the oracle on the permuted labels
+    _say("case batched frustum7m replicate 0 vs oracle, 6 pairs")
+    aptstat, torch, ws = gpu
+    xyz, lab, d = needle7m
+    args = _to_dev(torch, xyz, lab, d)
+    seeds = [7, 8]
+    pairs = [(A, B, 1.0) for A, B in PAIRS6]
+    rh, kh, st = aptstat.rdf_batched(aptstat.Cloud(*args), pairs, seeds, ws=ws)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    lab_r = orc.permute_labels(lab, seeds[0])
+    assert np.array_equal(aptstat.permute_labels(args[1], seeds[0], ws=ws).cpu().numpy(), lab_r)
+    for p, (A, B) in enumerate(PAIRS6):
+        ref = orc.rdf(xyz, lab_r, d, A, B, 1.0, 2.0, 200)
+        assert np.array_equal(rh[0, p].cpu().numpy().astype(np.uint64), ref), (A, B)
+        kref = orc.knn(xyz, lab_r, d, A, B, 1.0, 10, kb_rmax=5.0, kb_nbins=5000)[3]
+        assert np.array_equal(kh[0, p].cpu().numpy().astype(np.uint64), kref), (A, B)
+
+
 def test_batched_many_replicates_cross_blocks(gpu, synth):
     _say("case batched 70 replicates (two launches)")
     aptstat, torch, ws = gpu

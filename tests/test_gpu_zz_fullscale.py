@@ -1,20 +1,22 @@
 """Full-scale parity: the 2e9-ion needle (Sc -> any species, kNN k = 10 and
 RDF to 2 nm, d_srf = 2 nm) on one GPU, checked on sampled outputs.
 
-The oracle cannot take the whole cloud, so three z-slabs of 4 nm serve as
-samples.  Their ions are collected while the cloud is generated chunk by
-chunk into HBM; each slab with a 3 nm halo on both sides is a sub-cloud
-whose only eligible targets are the slab's own (the halo covers r_max and
-every k-th neighbour distance, which is asserted).
+The oracle cannot take the whole cloud, so three z-slabs of 4 nm and 200
+randomly placed 12 nm cubes (about 1e5 targets, checked by brute force)
+serve as samples.  Their ions are collected while the cloud is generated
+chunk by chunk into HBM; each sample with a 3 nm halo on every side is a
+sub-cloud whose only eligible targets are the sample's own (the halo covers
+r_max and every k-th neighbour distance, which is asserted).
   * kNN rows: the rows of the full run (every target of the cloud, the
-    configuration the benchmark times) for the slab targets equal the
+    configuration the benchmark times) for the sample targets equal the
     oracle's rows on the sub-cloud: identities bit for bit, distances within
     1e-6 relative.
   * RDF and k-th neighbour histogram: a second full-size run whose surface
-    distances are masked so that only slab targets are eligible equals the
-    sum of the oracle's slab histograms, bit for bit.
+    distances are masked so that only sample targets are eligible equals the
+    sum of the oracle's sample histograms, bit for bit.
 Runs last (its name) and takes a few minutes, most of it generating 2e9 ions.
 """
+import os
 import sys
 
 import numpy as np
@@ -25,11 +27,21 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 SC, ANY = 1, 255
 K, R_MAX, N_BINS, KB_RMAX, KB_NBINS, D_SRF = 10, 2.0, 200, 5.0, 5000, 2.0
 SLAB, HALO = 4.0, 3.0
+CUBE, N_CUBES = 12.0, 200
 
 
 def _say(msg):
+    # (also appended to a progress file: the test runs for minutes while
+    # pytest holds its captured output)
     print(msg, flush=True)
     sys.stdout.flush()
+    try:
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        os.makedirs(os.path.join(root, "gpurun_out"), exist_ok=True)
+        with open(os.path.join(root, "gpurun_out", "progress_fullscale.log"), "a") as f:
+            f.write(msg + "\n")
+    except OSError:
+        pass
 
 
 def test_fullscale_needle_2e9(orc, synth):
@@ -46,6 +58,37 @@ def test_fullscale_needle_2e9(orc, synth):
     z0s = [0.06 * H, 0.5 * H, 0.93 * H]
     cores = [(np.float32(z), np.float32(z + SLAB)) for z in z0s]
     picks = [[] for _ in z0s]
+    # random cubes: cells of a lattice of (CUBE + 2 HALO) nm whose cube lies
+    # inside the needle at least 2 nm from its surface and clear of the slabs
+    # with their halos
+    L = CUBE + 2 * HALO
+    rng = np.random.default_rng(2004)
+    R0, R1 = spec.R0, spec.R1
+    cand = []
+    for kz in range(int(H // L)):
+        zlo = kz * L + HALO
+        if any(zlo + CUBE > a - 2 * HALO and zlo < b + 2 * HALO for a, b in cores):
+            continue
+        r_top = R0 + (R1 - R0) * (zlo + CUBE) / H - 2.0 - CUBE * 1.75
+        n_xy = int(r_top // L)
+        for kx in range(-n_xy, n_xy):
+            for ky in range(-n_xy, n_xy):
+                c = np.array([(kx + 0.5) * L, (ky + 0.5) * L])
+                if np.hypot(*c) + CUBE < r_top:
+                    cand.append((kx, ky, kz))
+    chosen = [cand[i] for i in rng.choice(len(cand), size=N_CUBES, replace=False)]
+    # lattice cells -> cube number (-1: not a sample), looked up by the
+    # ions' cell indices (a cube lies HALO inside its cell, so FP32 floors
+    # near cell faces never matter for it)
+    OFF = 16
+    table = np.full((int(H // L) + 2, 2 * OFF, 2 * OFF), -1, np.int32)
+    for q, (kx, ky, kz) in enumerate(chosen):
+        table[kz, ky + OFF, kx + OFF] = q
+    cube_picks = [[] for _ in chosen]
+
+    def cube_lo(c):
+        kx, ky, kz = c
+        return np.array([kx * L + HALO, ky * L + HALO, kz * L + HALO], np.float64)
 
     def on_chunk(i0, xyz, lab, d):
         z = xyz[:, 2]
@@ -60,6 +103,37 @@ def test_fullscale_needle_2e9(orc, synth):
     cloud = aptstat.Cloud(xyz_d, lab_d, d_d)
     ws = aptstat.Workspace()
 
+    # the cubes' cells: each ion's lattice cell looked up on the device (the
+    # needle lies within |x|, |y| < OFF * L and 0 <= z < H), the selected
+    # ions copied to the host; the core test (integer faces, exact in FP32)
+    # is the same FP32 comparison on both sides
+    table_d = torch.from_numpy(table).to("cuda:0")
+    step = 1 << 26
+
+    def cube_and_core(c0):
+        v = xyz_d[c0:c0 + step]
+        k = torch.floor(v / L).to(torch.int64)
+        q = table_d[k[:, 2].clamp(0, table.shape[0] - 1), (k[:, 1] + OFF).clamp(0, 2 * OFF - 1),
+                    (k[:, 0] + OFF).clamp(0, 2 * OFF - 1)]
+        lo = (k * int(L) + int(HALO)).to(torch.float32)
+        core = ((v >= lo) & (v < lo + CUBE)).all(dim=1)
+        return q, core
+
+    cube_picks = [[] for _ in chosen]
+    for c0 in range(0, spec.n, step):
+        q, _ = cube_and_core(c0)
+        sel = torch.nonzero(q >= 0).squeeze(1)
+        if sel.numel():
+            qs = q[sel].cpu().numpy()
+            gid = (sel + c0).cpu().numpy()
+            xs = xyz_d[c0:c0 + step][sel].cpu().numpy()
+            ls = lab_d[c0:c0 + step][sel].cpu().numpy()
+            ds = d_d[c0:c0 + step][sel].cpu().numpy()
+            for qq in np.unique(qs):
+                m = qs == qq
+                cube_picks[qq].append((gid[m], xs[m], ls[m], ds[m]))
+        del q, sel
+
     _say("fullscale: GPU run over every target")
     r = aptstat.knn_rdf(cloud, SC, ANY, D_SRF, K, r_max=R_MAX, n_bins=N_BINS, kb_rmax=KB_RMAX,
                         kb_nbins=KB_NBINS, ws=ws)
@@ -70,15 +144,21 @@ def test_fullscale_needle_2e9(orc, synth):
     gtid = r.target_id[:nt].cpu().numpy()
     assert np.all(np.diff(gtid) > 0)
 
-    # slab targets only: surface distances masked on the device (same FP32
-    # comparisons as on the host)
+    # sample targets only (slabs and cube cores): surface distances masked
+    # on the device (the same FP32 comparisons as on the host)
     z = xyz_d[:, 2]
     keep = torch.zeros_like(z, dtype=torch.bool)
     for a, b in cores:
         keep |= (z >= float(a)) & (z < float(b))
+    del z
+    # cube cores, chunk by chunk
+    for c0 in range(0, spec.n, step):
+        q, core = cube_and_core(c0)
+        keep[c0:c0 + step] |= core & (q >= 0)
+        del q, core
     d_mask = torch.where(keep, d_d, torch.full_like(d_d, -np.inf))
-    del keep, z
-    _say("fullscale: GPU run over the slab targets")
+    del keep
+    _say("fullscale: GPU run over the sample targets")
     rs = aptstat.knn_rdf(aptstat.Cloud(xyz_d, lab_d, d_mask), SC, ANY, D_SRF, K, r_max=R_MAX, n_bins=N_BINS,
                          kb_rmax=KB_RMAX, kb_nbins=KB_NBINS, ws=ws)
     torch.cuda.synchronize()
@@ -110,7 +190,37 @@ def test_fullscale_needle_2e9(orc, synth):
         assert np.array_equal(g_nid, gid[nid]), "kNN identities differ"
         assert np.all(np.abs(g_dist - dist) <= 1e-6 * dist), "kNN distances differ"
         checked += len(tid)
-    _say(f"fullscale: {checked} targets' kNN rows checked")
+    # the cubes: kNN rows by brute force on each sub-cloud, histograms
+    cube_checked = 0
+    for q, c in enumerate(chosen):
+        if q % 25 == 0:
+            _say(f"fullscale: oracle on cubes {q}..{min(q + 25, len(chosen)) - 1}")
+        gid = np.concatenate([p[0] for p in cube_picks[q]])
+        xyz = np.concatenate([p[1] for p in cube_picks[q]])
+        lab = np.concatenate([p[2] for p in cube_picks[q]])
+        d = np.concatenate([p[3] for p in cube_picks[q]])
+        lo = cube_lo(c).astype(np.float32)
+        core = np.ones(len(gid), bool)
+        for ax in range(3):
+            core &= (xyz[:, ax] >= lo[ax]) & (xyz[:, ax] < np.float32(np.float64(lo[ax]) + CUBE))
+        d_o = np.where(core, d, np.float32(-np.inf)).astype(np.float32)
+        o_rdf += orc.rdf(xyz, lab, d_o, SC, ANY, D_SRF, R_MAX, N_BINS)
+        tid, dist, nid, kh = orc.knn(xyz, lab, d_o, SC, ANY, D_SRF, K, np.inf, KB_RMAX, KB_NBINS, method="brute")
+        o_kh += kh
+        if len(tid) == 0:
+            continue
+        assert np.all(dist[:, K - 1] < HALO), "a k-th neighbour lies beyond the halo"
+        rows = np.searchsorted(gtid, gid[tid])
+        assert np.array_equal(gtid[rows], gid[tid])
+        rows_t = torch.from_numpy(rows).to("cuda:0")
+        g_nid = r.nbr_id.index_select(0, rows_t).cpu().numpy()
+        g_dist = r.dist.index_select(0, rows_t).cpu().numpy()
+        assert np.array_equal(g_nid, gid[nid]), f"kNN identities differ in cube {q}"
+        assert np.all(np.abs(g_dist - dist) <= 1e-6 * dist), f"kNN distances differ in cube {q}"
+        cube_checked += len(tid)
+    _say(f"fullscale: {checked} slab targets and {cube_checked} cube targets' kNN rows checked")
+    assert cube_checked >= 90_000
+    checked += cube_checked
     assert int(rs.n_targets.item()) == checked
     assert np.array_equal(g_rdf, o_rdf), f"RDF differs in {np.count_nonzero(g_rdf != o_rdf)} bins"
     assert np.array_equal(g_kh, o_kh), "k-th neighbour histogram differs"
