@@ -43,11 +43,15 @@ K, R_MAX, N_BINS, KB_RMAX, KB_NBINS = 10, 2.0, 200, 5.0, 5000
 # source hash), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a
 # plain-copy calibration; valid only for the kernel sources they were taken
 # on (the summaries under profiles/)
-PAIR_TRAFFIC = {}
+PAIR_TRAFFIC = {
+    # profiles/counters_frustum2g.md: FETCH_SIZE 223 335 771.8 KiB x 2.0 +
+    # WRITE_SIZE 18 944 KiB per k_rdf_nbr<5> launch
+    ("frustum2g", "k_rdf_nbr"): (457_398_518_781, "57f040c7fbeb41aa"),
+}
 PAIR_SOURCES = ("apt_pair.hip", "apt_pair.hpp", "apt_pairdev.hpp", "apt_internal.hpp", "apt_bin.hpp")
-FP32_VECTOR_PEAK_TFLOPS = 157.3
-HBM_PEAK_GBPS = 8000.0            # MI355X HBM3E   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk (packed FMA)
-FLOP_PER_PAIR = 8                 # 3 sub, 1 mul, 2 fma per pair distance
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk (packed FMA)
+HBM_PEAK_GBPS = 8000.0            # MI355X HBM3E
+FLOP_PER_PAIR = 8                 # 3 sub, 3 mul, 2 add per pair distance (no contraction)
 # candidate pair-evaluations per second the FP32 vector units allow: 256 CU x
 # 64 lanes x 2 (packed) x 2.4 GHz over 6 instructions per candidate
 R_PAIR = 256 * 64 * 2 * 2.4e9 / 6

@@ -210,9 +210,13 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
         // neighbours so dense that 64 of them span well under r_max: the RDF
         // runs neighbour-major (64 records per wavefront against every target
         // within reach), and the kNN, whose radius is then well below r_max,
-        // one target per lane among a few dozen records
+        // one target per lane among a few dozen records.  Only for 2^18
+        // targets or more: with fewer, the per-lane kNN fills under four
+        // wavefronts per SIMD and every neighbour chunk is still visited
+        // (the 7.7e6-ion needle's 74 000 Sc targets against Al: 0.59 ms
+        // against 0.40 ms one target per wavefront)
         const double a64 = cbrt(64.0 / rho);
-        if (!P.tile_mode && pp.k <= 16 && pp.r_enum > 0.0f && a64 <= (double)pp.r_enum &&
+        if (!P.tile_mode && pp.k <= 16 && pp.r_enum > 0.0f && a64 <= (double)pp.r_enum && totT >= (1u << 18) &&
             (pp.k == 0 || rk_raw <= 0.5 * (double)pp.r_enum))
             P.tile_mode = 3;
     }
@@ -459,6 +463,30 @@ __device__ __forceinline__ bool rs_active(const GridPlan& P, const SortArgs& a) 
     return (uint32_t)a.pass < (a.count_is_T ? P.passes_T : P.passes);
 }
 
+// The workgroup's sort, taken from the argument set with selects: indexing
+// the array with a run-time value copies it to private memory, and every
+// pointer read back from there becomes a flat one, whose loads the LDS waits
+// of the ranking then also wait for.
+__device__ __forceinline__ SortArgs sort_of(const SortSet& set, int q) {
+    const SortArgs& s0 = set.s[0];
+    const SortArgs& s1 = set.s[1];
+    SortArgs a;
+    a.plan = q ? s1.plan : s0.plan;
+    a.count_is_T = q ? s1.count_is_T : s0.count_is_T;
+    a.pass = q ? s1.pass : s0.pass;
+    a.G = q ? s1.G : s0.G;
+    a.keys[0] = q ? s1.keys[0] : s0.keys[0];
+    a.keys[1] = q ? s1.keys[1] : s0.keys[1];
+    a.vals[0] = q ? s1.vals[0] : s0.vals[0];
+    a.vals[1] = q ? s1.vals[1] : s0.vals[1];
+    a.counts = q ? s1.counts : s0.counts;
+    a.totals = q ? s1.totals : s0.totals;
+    return a;
+}
+
+template <typename T>
+__device__ __forceinline__ T pick2(T p0, T p1, uint32_t bit) { return (bit & 1u) ? p1 : p0; }
+
 __device__ __forceinline__ void rs_chunk(uint32_t n, int G, uint32_t* chunk) {
     uint32_t c = (n + (uint32_t)G - 1u) / (uint32_t)G;
     *chunk = (c + kRsTile - 1u) / kRsTile * kRsTile;
@@ -469,13 +497,13 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortSet set) {
     const uint32_t g0 = (uint32_t)set.s[0].G;
     const int q = blockIdx.x < g0 ? 0 : 1;
     if (q >= set.n) return;
-    const SortArgs a = set.s[q];
+    const SortArgs a = sort_of(set, q);
     const uint32_t bid = blockIdx.x - (q ? g0 : 0u);
     if (bid >= (uint32_t)a.G) return;
     const GridPlan P = *a.plan;
     if (!rs_active(P, a)) return;
     const uint32_t n = a.count_is_T ? P.nT : P.nB;
-    const uint32_t* __restrict__ keys = a.keys[a.pass & 1];
+    const uint32_t* __restrict__ keys = pick2(a.keys[0], a.keys[1], (uint32_t)a.pass);
     __shared__ uint32_t s_h[kWavesPerBlock][kRadix];
     for (int i = threadIdx.x; i < kWavesPerBlock * kRadix; i += kBlock) (&s_h[0][0])[i] = 0;
     __syncthreads();
@@ -513,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortSet set) {
 __global__ __launch_bounds__(kBlock) void k_rs_scan(SortSet set) {
     const int q = blockIdx.x / kRadix;
     if (q >= set.n) return;
-    const SortArgs a = set.s[q];
+    const SortArgs a = sort_of(set, q);
     const GridPlan P = *a.plan;
     if (!rs_active(P, a)) return;
     __shared__ uint32_t s_w[kWavesPerBlock];
@@ -547,16 +575,16 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortSet set) {
     const uint32_t g0 = (uint32_t)set.s[0].G;
     const int q = blockIdx.x < g0 ? 0 : 1;
     if (q >= set.n) return;
-    const SortArgs a = set.s[q];
+    const SortArgs a = sort_of(set, q);
     const uint32_t bid = blockIdx.x - (q ? g0 : 0u);
     if (bid >= (uint32_t)a.G) return;
     const GridPlan P = *a.plan;
     if (!rs_active(P, a)) return;
     const uint32_t n = a.count_is_T ? P.nT : P.nB;
-    const uint32_t* __restrict__ kin = a.keys[a.pass & 1];
-    const uint32_t* __restrict__ vin = a.vals[a.pass & 1];
-    uint32_t* __restrict__ kout = a.keys[(a.pass + 1) & 1];
-    uint32_t* __restrict__ vout = a.vals[(a.pass + 1) & 1];
+    const uint32_t* __restrict__ kin = pick2(a.keys[0], a.keys[1], (uint32_t)a.pass);
+    const uint32_t* __restrict__ vin = pick2(a.vals[0], a.vals[1], (uint32_t)a.pass);
+    uint32_t* __restrict__ kout = pick2(a.keys[0], a.keys[1], (uint32_t)a.pass + 1u);
+    uint32_t* __restrict__ vout = pick2(a.vals[0], a.vals[1], (uint32_t)a.pass + 1u);
     const uint32_t shift = 8u * (uint32_t)a.pass;
 
     __shared__ uint32_t s_key[kRsTile];
