@@ -45,6 +45,8 @@ def _load():
             "orc_sdm_faces": ([_f32, _i32, _p], None),
             "orc_sdm_brute": ([_p, _p, _p, _i64, _i32, _i32, _f32, _f32, _i32, _p], None),
             "orc_sdm_grid": ([_p, _p, _p, _i64, _i32, _i32, _f32, _f32, _i32, _p], None),
+            "orc_cluster_ms_brute": ([_p, _p, _p, _i64, _i32, _f32, _i32, _f32, _p, _p, _p, _i32], None),
+            "orc_cluster_ms_grid": ([_p, _p, _p, _i64, _i32, _f32, _i32, _f32, _p, _p, _p, _i32], None),
             "orc_d2f": ([_p, _p], _f32),
             "orc_D2": ([_p, _p], _f64),
             "orc_edges2": ([_f32, _i32, _p], None),
@@ -167,6 +169,22 @@ def sdm(xyz, lab, d_bnd, A: int, B: int, d_srf: float, R: float, n_vox: int, met
     f = _load().orc_sdm_grid if method == "grid" else _load().orc_sdm_brute
     f(xyz.ctypes.data, lab.ctypes.data, _ptr(d_bnd), xyz.shape[0], A, B, d_srf, R, n_vox, hist.ctypes.data)
     return hist.reshape(n_vox, n_vox, n_vox)
+
+
+def cluster_ms(xyz, lab, d_bnd, A: int, d_max: float, n_min: int, d_srf: float = 0.0, n_size_bins: int = 0,
+               method: str = "grid"):
+    """Maximum-separation clustering of the ions of species A: (label int64
+    [n], counts int64 [3] = kept clusters, truncated kept clusters, ions in
+    kept clusters, size_hist uint64 [n_size_bins] or None)."""
+    xyz, lab, d_bnd = _cloud(xyz, lab, d_bnd)
+    n = xyz.shape[0]
+    label = np.empty(n, dtype=np.int64)
+    counts = np.zeros(3, dtype=np.int64)
+    hist = np.zeros(n_size_bins, dtype=np.uint64) if n_size_bins > 0 else None
+    f = _load().orc_cluster_ms_grid if method == "grid" else _load().orc_cluster_ms_brute
+    f(xyz.ctypes.data, lab.ctypes.data, _ptr(d_bnd), n, A, d_max, n_min, d_srf, label.ctypes.data,
+      counts.ctypes.data, _ptr(hist), n_size_bins)
+    return label, counts, hist
 
 
 def splitmix64(seed: int, i: int) -> int:

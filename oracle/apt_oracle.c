@@ -844,3 +844,122 @@ void orc_sdm_grid(const float* xyz, const uint8_t* lab, const float* d_bnd, int6
     ogrid_free(&g);
     free(F);
 }
+
+/* ------------------------------------------------------------------------
+ * Maximum-separation clustering (paper, Methods: "Descriptive, two-point
+ * spatial statistics, and clustering": the MS method, a DBScan variant with
+ * the two parameters d_max and N_min; Supplementary, "Efficient batch
+ * processing of spatial statistics": clusters that touch the edge of the
+ * dataset are flagged as truncated).
+ *
+ * The vertices are the ions of species A.  Two of them are linked when both
+ * positions are finite and their FP64 squared distance (orc_D2) is at most
+ * d_max^2.  Clusters are the connected components; a component with at
+ * least n_min ions is kept.  A component is found by a breadth-first search
+ * started at its smallest index (indices are scanned upwards, so every
+ * smaller vertex already belongs to another component), which is therefore
+ * the component's name.
+ * ------------------------------------------------------------------------ */
+
+/* outputs from comp[i] (the component's smallest index, -1 off species) */
+static void ms_outputs(const int64_t* comp, const float* d_bnd, int64_t n, int32_t n_min, float d_srf,
+                       int64_t* label, int64_t* counts, uint64_t* size_hist, int32_t n_size_bins) {
+    int64_t* size = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    uint8_t* trunc = (uint8_t*)calloc((size_t)(n > 0 ? n : 1), 1);
+    for (int64_t i = 0; i < n; ++i) {
+        if (comp[i] < 0) continue;
+        size[comp[i]]++;
+        /* at the edge: the distance to the edge is not at least d_srf (NaN included) */
+        if (d_bnd && !(d_bnd[i] >= d_srf)) trunc[comp[i]] = 1;
+    }
+    counts[0] = counts[1] = counts[2] = 0;
+    if (size_hist) memset(size_hist, 0, sizeof(uint64_t) * (size_t)n_size_bins);
+    for (int64_t i = 0; i < n; ++i) {
+        label[i] = (comp[i] >= 0 && size[comp[i]] >= n_min) ? comp[i] : -1;
+        if (comp[i] != i) continue;            /* one visit per component */
+        const int64_t s = size[i];
+        if (size_hist) size_hist[(s < n_size_bins ? s : n_size_bins) - 1]++;
+        if (s >= n_min) {
+            counts[0]++;
+            counts[1] += trunc[i];
+            counts[2] += s;
+        }
+    }
+    free(size);
+    free(trunc);
+}
+
+void orc_cluster_ms_brute(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n, int32_t A,
+                          float d_max, int32_t n_min, float d_srf, int64_t* label, int64_t* counts,
+                          uint64_t* size_hist, int32_t n_size_bins) {
+    const double lim = (double)d_max * (double)d_max;
+    int64_t* comp = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t* queue = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) comp[i] = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!is_species(lab[i], A) || comp[i] >= 0) continue;
+        int64_t head = 0, tail = 0;
+        comp[i] = i;
+        queue[tail++] = i;
+        while (head < tail) {
+            const int64_t u = queue[head++];
+            if (!finite3(xyz + 3 * u)) continue;
+            for (int64_t j = 0; j < n; ++j) {
+                if (comp[j] >= 0 || !is_species(lab[j], A) || !finite3(xyz + 3 * j)) continue;
+                if (orc_D2(xyz + 3 * u, xyz + 3 * j) <= lim) {
+                    comp[j] = i;
+                    queue[tail++] = j;
+                }
+            }
+        }
+    }
+    ms_outputs(comp, d_bnd, n, n_min, d_srf, label, counts, size_hist, n_size_bins);
+    free(queue);
+    free(comp);
+}
+
+/* The same search with the candidates of a vertex taken from the 27 grid
+ * cells around it (cell edge at least d_max). */
+void orc_cluster_ms_grid(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n, int32_t A,
+                         float d_max, int32_t n_min, float d_srf, int64_t* label, int64_t* counts,
+                         uint64_t* size_hist, int32_t n_size_bins) {
+    const double lim = (double)d_max * (double)d_max;
+    ogrid g;
+    ogrid_build(&g, n, lab, A, pos_plain, xyz, (double)d_max * (1.0 + 1e-6));
+    int64_t* comp = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t* queue = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) comp[i] = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!is_species(lab[i], A) || comp[i] >= 0) continue;
+        int64_t head = 0, tail = 0;
+        comp[i] = i;
+        queue[tail++] = i;
+        while (head < tail) {
+            const int64_t u = queue[head++];
+            const float* pu = xyz + 3 * u;
+            if (!finite3(pu)) continue;
+            int64_t c[3];
+            for (int a = 0; a < 3; ++a) c[a] = ocell_axis(&g, a, (double)pu[a]);
+            for (int64_t z = c[2] - 1; z <= c[2] + 1; ++z) {
+                if (z < 0 || z >= g.dim[2]) continue;
+                for (int64_t y = c[1] - 1; y <= c[1] + 1; ++y) {
+                    if (y < 0 || y >= g.dim[1]) continue;
+                    for (int64_t x = c[0] - 1; x <= c[0] + 1; ++x) {
+                        if (x < 0 || x >= g.dim[0]) continue;
+                        const int64_t cell = (z * g.dim[1] + y) * g.dim[0] + x;
+                        for (int64_t t = g.start[cell]; t < g.start[cell + 1]; ++t) {
+                            const int64_t j = g.item[t];
+                            if (comp[j] >= 0 || orc_D2(pu, xyz + 3 * j) > lim) continue;
+                            comp[j] = i;
+                            queue[tail++] = j;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    ms_outputs(comp, d_bnd, n, n_min, d_srf, label, counts, size_hist, n_size_bins);
+    ogrid_free(&g);
+    free(queue);
+    free(comp);
+}

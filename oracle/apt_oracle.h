@@ -2,8 +2,9 @@
  * apt_oracle.h -- TEST INFRASTRUCTURE ONLY.
  *
  * A plain, slow CPU reference for the spatial-statistics path (kNN and RDF
- * of target ions against neighbour ions, the label-randomised null model and
- * a Gaussian-smoothed RDF with its gradient).  Only the test-suite, the
+ * of target ions against neighbour ions, the label-randomised null model, a
+ * Gaussian-smoothed RDF with its gradient, the two-point statistic and the
+ * maximum-separation clustering).  Only the test-suite, the
  * smoke check and the benchmark's CPU baseline may call it; the GPU library
  * never includes, links or calls anything here, and this file shares no code
  * with it.  All pointers are host pointers.  Species 255 means "any species".
@@ -26,6 +27,19 @@ void orc_sdm_brute(const float* xyz, const uint8_t* lab, const float* d_bnd, int
                    float d_srf, float R, int32_t n_vox, uint64_t* hist);
 void orc_sdm_grid(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n, int32_t A, int32_t B,
                   float d_srf, float R, int32_t n_vox, uint64_t* hist);
+
+/* Maximum-separation clustering of the ions of species A: links at FP64
+ * squared distance <= d_max^2, components of at least n_min ions kept.
+ * label[n]: the smallest ion index of the ion's kept cluster, else -1;
+ * counts[3]: kept clusters, kept clusters with an ion whose d_bnd is not
+ * >= d_srf (0 without d_bnd), ions in kept clusters; size_hist[n_size_bins]
+ * (may be NULL): every component by its size s, in bin min(s, n_size_bins)-1. */
+void orc_cluster_ms_brute(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n, int32_t A,
+                          float d_max, int32_t n_min, float d_srf, int64_t* label, int64_t* counts,
+                          uint64_t* size_hist, int32_t n_size_bins);
+void orc_cluster_ms_grid(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n, int32_t A,
+                         float d_max, int32_t n_min, float d_srf, int64_t* label, int64_t* counts,
+                         uint64_t* size_hist, int32_t n_size_bins);
 
 /* Canonical distances between two stored FP32 positions. */
 float orc_d2f(const float* a, const float* b);   /* FP32, fixed evaluation order */

@@ -732,3 +732,120 @@ def test_sdm_inversion_symmetry_and_axis_swap(orc, synth):
     hs = orc.sdm(sw, lab, None, SC, SC, 0.0, R, n)
     assert np.array_equal(hs, np.transpose(h, (0, 2, 1)))
     assert not np.array_equal(h, np.transpose(h, (0, 2, 1)))
+
+
+# --------------------------------------------------------------------------
+# maximum-separation clustering
+# --------------------------------------------------------------------------
+
+def _partition(label):
+    """{root: sorted member indices} of the kept clusters."""
+    out = {}
+    for i in np.flatnonzero(label >= 0):
+        out.setdefault(int(label[i]), []).append(int(i))
+    return out
+
+
+def test_cluster_ms_inclusive_threshold_on_a_chain(orc):
+    # ions 0.5 nm apart on a line (0.5 and its multiples are exact in FP32
+    # and FP64): at d_max = 0.5 every neighbour pair is linked (<=), one ulp
+    # below it none is
+    n = 9
+    xyz = np.zeros((n, 3), np.float32)
+    xyz[:, 0] = np.arange(n, dtype=np.float32) * np.float32(0.5) + np.float32(3.0)
+    lab = np.full(n, SC, np.uint8)
+    label, counts, hist = orc.cluster_ms(xyz, lab, None, SC, 0.5, 2, n_size_bins=n + 1, method="brute")
+    assert np.array_equal(label, np.zeros(n, np.int64)) and list(counts) == [1, 0, n]
+    assert hist[n - 1] == 1 and hist.sum() == 1
+    below = float(np.nextafter(np.float32(0.5), np.float32(0)))
+    label, counts, hist = orc.cluster_ms(xyz, lab, None, SC, below, 1, n_size_bins=4, method="brute")
+    assert np.array_equal(label, np.arange(n)) and list(counts) == [n, 0, n] and hist[0] == n
+    # an ion of another species in the middle breaks the chain
+    lab2 = lab.copy()
+    lab2[4] = AL
+    label, counts, _ = orc.cluster_ms(xyz, lab2, None, SC, 0.5, 1, method="brute")
+    assert list(label) == [0, 0, 0, 0, -1, 5, 5, 5, 5] and list(counts) == [2, 0, 8]
+
+
+def test_cluster_ms_known_blobs_sizes_and_truncation(orc):
+    # compact blobs of known sizes on a 0.3 nm lattice, 5 nm apart, plus
+    # isolated ions: at d_max = 0.35 the clusters are exactly the blobs
+    rng = np.random.default_rng(3)
+    sizes = [1, 2, 4, 5, 7, 12, 20, 33]
+    pts, blob = [], []
+    for b, s in enumerate(sizes):
+        g = np.array([(x, y, z) for z in range(4) for y in range(4) for x in range(4)], np.float32)
+        # a connected subset: the first s sites in an order that keeps it connected
+        g = g[np.lexsort((g[:, 0], g[:, 1], g[:, 2]))][:s]
+        pts.append(g * np.float32(0.3) + np.float32(5.0 * b))
+        blob += [b] * s
+    xyz = np.concatenate(pts).astype(np.float32)
+    blob = np.array(blob)
+    order = rng.permutation(len(xyz))
+    xyz, blob = xyz[order], blob[order]
+    lab = np.full(len(xyz), SC, np.uint8)
+    d = np.full(len(xyz), 10.0, np.float32)
+    d[np.flatnonzero(blob == 6)[0]] = 0.5          # one ion of the 20-ion blob at the edge
+    for n_min in (1, 5, 13):
+        label, counts, hist = orc.cluster_ms(xyz, lab, d, SC, 0.35, n_min, d_srf=1.0, n_size_bins=40,
+                                             method="brute")
+        kept = [b for b, s in enumerate(sizes) if s >= n_min]
+        part = _partition(label)
+        expect = {int(np.flatnonzero(blob == b).min()): sorted(np.flatnonzero(blob == b).tolist()) for b in kept}
+        assert part == expect, n_min
+        assert list(counts) == [len(kept), int(n_min <= 20), sum(sizes[b] for b in kept)]
+        assert [int(hist[s - 1]) for s in sizes] == [1] * len(sizes) and hist.sum() == len(sizes)
+
+
+def test_cluster_ms_equals_single_linkage(orc, synth):
+    # MS clusters at d_max are the flat clusters of single-linkage
+    # agglomeration cut at distance d_max (scipy, FP64 distances)
+    from scipy.cluster.hierarchy import fcluster, linkage
+
+    xyz, lab, _ = synth.Specimen(shape="box", L=(14.0, 14.0, 14.0), n=40_000, seed=51, p_m_sc=0.01,
+                                 n_clusters=12, r_c=1.2).generate()
+    sc = np.flatnonzero(lab == SC)
+    assert 500 < len(sc) < 4000
+    Z = linkage(xyz[sc].astype(np.float64), method="single", metric="euclidean")
+    for d_max in (0.3, 0.45, 0.7, 1.0):
+        t = float(np.float32(d_max))
+        f = fcluster(Z, t=t, criterion="distance")
+        expect = {}
+        for c in np.unique(f):
+            m = sorted(sc[f == c].tolist())
+            if len(m) >= 3:
+                expect[m[0]] = m
+        label, counts, _ = orc.cluster_ms(xyz, lab, None, SC, d_max, 3)
+        assert _partition(label) == expect, d_max
+        assert counts[0] == len(expect) and counts[2] == sum(len(v) for v in expect.values())
+
+
+@pytest.mark.parametrize("A,use_d", [(SC, False), (SI, True), (ANY, True)])
+def test_cluster_ms_brute_equals_grid(orc, synth, A, use_d):
+    xyz, lab, d = synth.Specimen(shape="box", L=(8.0, 8.0, 8.0), n=6000, seed=57, p_m_sc=0.08, p_m_si=0.05,
+                                 n_clusters=5, r_c=1.0).generate()
+    xyz[17] = np.nan                                 # a vertex with no links
+    d = d if use_d else None
+    d_max = 0.25 if A == ANY else 0.6
+    b = orc.cluster_ms(xyz, lab, d, A, d_max, 2, d_srf=0.7, n_size_bins=30, method="brute")
+    g = orc.cluster_ms(xyz, lab, d, A, d_max, 2, d_srf=0.7, n_size_bins=30, method="grid")
+    for x, y in zip(b, g):
+        assert np.array_equal(x, y)
+    assert b[1][0] > 5
+
+
+def test_cluster_ms_refines_and_relabels(orc, synth):
+    xyz, lab, _ = synth.Specimen(shape="box", L=(10.0, 10.0, 10.0), n=20_000, seed=61, p_m_sc=0.02,
+                                 n_clusters=8, r_c=1.0).generate()
+    # a larger d_max only merges clusters: every cluster at 0.5 lies inside one at 0.8
+    small, _, _ = orc.cluster_ms(xyz, lab, None, SC, 0.5, 1)
+    large, _, _ = orc.cluster_ms(xyz, lab, None, SC, 0.8, 1)
+    sc = lab == SC
+    for r in np.unique(small[sc]):
+        assert len(np.unique(large[small == r])) == 1
+    assert len(np.unique(large[sc])) < len(np.unique(small[sc]))
+    # renumbering the ions renumbers the clusters and nothing else
+    perm = np.random.default_rng(5).permutation(len(xyz))
+    lp, cp, _ = orc.cluster_ms(xyz[perm], lab[perm], None, SC, 0.5, 1)
+    assert sorted(sorted(perm[m].tolist()) for m in _partition(lp).values()) == \
+        sorted(_partition(small).values())
