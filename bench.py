@@ -191,6 +191,36 @@ def sdm_timing(aptstat, torch, cloud, ws, reps=5):
             "pairs_per_s_kernel": pairs / (k_ms / 1e3) if k_ms > 0 else None}
 
 
+def cluster_timing(aptstat, torch, cloud, ws, reps=3):
+    """Maximum-separation clustering of the Sc ions of the 7.7e6-ion needle
+    over the d_max sweep of the paper's benchmark task (0.10 to 0.70 nm in
+    steps of 0.05 nm, N_min = 5; clusters with an ion within 1 nm of the
+    surface count as truncated): ms per run, and the kept clusters per d_max."""
+    d_maxes = [round(0.10 + 0.05 * i, 2) for i in range(13)]
+    kept, trunc = [], []
+    for dm in d_maxes:
+        _, c, _, st = aptstat.cluster_ms(cloud, SC, dm, 5, 1.0, ws=ws)
+        c = c.cpu()
+        kept.append(int(c[0]))
+        trunc.append(int(c[1]))
+    for stage in ("cluster", "binning"):
+        aptstat.trace_read(stage)
+    aptstat.trace_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for dm in d_maxes:
+            aptstat.cluster_ms(cloud, SC, dm, 5, 1.0, ws=ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / (reps * len(d_maxes))
+    aptstat.trace_enable(False)
+    k_ms = aptstat.trace_read("cluster")[0] / (reps * len(d_maxes))
+    b_ms = aptstat.trace_read("binning")[0] / (reps * len(d_maxes))
+    return {"workload": "frustum7m", "species": "Sc", "d_max_nm": [0.10, 0.05, 0.70], "n_min": 5,
+            "runs": len(d_maxes), "ms_per_run": 1e3 * dt, "cluster_kernels_ms": k_ms, "binning_ms": b_ms,
+            "sweep_ms": 1e3 * dt * len(d_maxes), "kept_clusters": kept, "truncated_clusters": trunc}
+
+
 PAIRS6 = [(AL, SC), (AL, SI), (SC, AL), (SC, SI), (SI, AL), (SI, SC)]
 
 
@@ -498,6 +528,8 @@ def main():
                                                 min(args.looped_reps, args.batched_reps))
             log("[bench] two-point statistic on frustum7m")
             line["sdm"] = sdm_timing(aptstat, torch, cloud, ws)
+            log("[bench] maximum-separation clustering sweep on frustum7m")
+            line["cluster"] = cluster_timing(aptstat, torch, cloud, ws)
             del cloud, xyz_d, lab_d, d_d
         if not args.no_smooth:
             log("[bench] smoothed RDF on box1m")

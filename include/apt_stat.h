@@ -98,7 +98,8 @@ enum {
     APT_OP_PERMUTE = 4,   /* apt_permute_labels                    */
     APT_OP_BATCHED = 5,   /* apt_rdf_batched (n_pairs, n_rep used) */
     APT_OP_SMOOTH = 6,    /* apt_rdf_smooth_fwd / _bwd             */
-    APT_OP_SDM = 7        /* apt_sdm                               */
+    APT_OP_SDM = 7,       /* apt_sdm                               */
+    APT_OP_CLUSTER = 8    /* apt_cluster_ms                        */
 };
 
 /* Bytes of device workspace an operation needs for n ions (host only, no
@@ -243,6 +244,37 @@ apt_status apt_batched_plan_clear(void);
 apt_status apt_sdm(const apt_cloud* cloud, apt_query q, float R, int32_t n_vox, uint64_t* hist, int32_t* status,
                    void* ws, size_t ws_bytes, void* stream);
 
+/* Maximum-separation clustering (paper, Methods: "Descriptive, two-point
+ * spatial statistics, and clustering": the MS method with its parameters
+ * d_max and N_min; Supplementary, "Efficient batch processing of spatial
+ * statistics": clusters that touch the dataset edge are flagged as
+ * truncated).  The ions of `species` (APT_ANY: every ion) are the vertices;
+ * two of them are linked when both positions are finite and their FP64
+ * squared distance (differences of the stored FP32 coordinates) is at most
+ * d_max^2.  Clusters are the connected components; those of at least n_min
+ * ions are kept.  A cluster is named by its smallest ion index.
+ *   d_max        > 0, finite (nm)
+ *   n_min        >= 1
+ *   d_srf        an ion whose cloud->d_bnd is not >= d_srf (NaN included)
+ *                lies at the edge; not NaN; unused when cloud->d_bnd is NULL
+ *   label        [n] int64, device, overwritten: for an ion of a kept
+ *                cluster the smallest ion index of that cluster, else -1
+ *   counts       [3] int64, device, overwritten: kept clusters, kept clusters
+ *                with an ion at the edge (0 without d_bnd), ions in kept
+ *                clusters
+ *   size_hist    [n_size_bins] uint64, device, overwritten, or NULL: every
+ *                cluster (kept or not) by its ion count s, in bin
+ *                min(s, n_size_bins) - 1 (so any N_min's count follows)
+ *   n_size_bins  1..65536 when size_hist is given
+ * An ion of the species with a non-finite position is a cluster of its own
+ * and sets APT_STATUS_NONFINITE.  Clouds of 2^31 ions or more return
+ * APT_E_UNSUPPORTED.  Labels and counts do not depend on the order in which
+ * the GPU links pairs.
+ * Workspace: APT_OP_CLUSTER. */
+apt_status apt_cluster_ms(const apt_cloud* cloud, uint8_t species, float d_max, int32_t n_min, float d_srf,
+                          int64_t* label, int64_t* counts, uint64_t* size_hist, int32_t n_size_bins,
+                          int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
 /* Gaussian-smoothed RDF, an extension (not in the paper) of the RDF's
  * rectangular transfer function (paper, Methods: "Descriptive, two-point
  * spatial statistics") that is differentiable in the positions and in a
@@ -341,7 +373,8 @@ apt_status apt_get_tuning(apt_tuning* t);
  * (ms) and number of launches of one stage ("binning" = bounding box to
  * sorted records, "pair" = the pair kernel, "tile" = the 64-target kernel
  * (and the per-lane kNN of mode 4), "nbr" = the neighbour-major RDF kernel,
- * "sdm" = the two-point statistic's kernel,
+ * "sdm" = the two-point statistic's kernel, "cluster" = the clustering's
+ * union-find kernels,
  * "permute" and "partition" = the batched replicates' label permutation and
  * class split) and forgets that stage's records.  Host only; off by
  * default. */

@@ -26,7 +26,7 @@ _SO = os.path.join(_HERE, "libaptstat.so")
 
 STATUS_NONFINITE = 1
 STATUS_CAPACITY = 2
-OP_RDF, OP_KNN, OP_KNN_RDF, OP_PERMUTE, OP_BATCHED, OP_SMOOTH, OP_SDM = 1, 2, 3, 4, 5, 6, 7
+OP_RDF, OP_KNN, OP_KNN_RDF, OP_PERMUTE, OP_BATCHED, OP_SMOOTH, OP_SDM, OP_CLUSTER = 1, 2, 3, 4, 5, 6, 7, 8
 
 
 class AptError(RuntimeError):
@@ -82,6 +82,8 @@ _SIGS = {
     "apt_batched_plan_clear": ([], ctypes.c_int),
     "apt_rdf": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_rdf_noalloc": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, _P, _P], ctypes.c_int),
+    "apt_cluster_ms": ([ctypes.POINTER(_Cloud), ctypes.c_uint8, ctypes.c_float, ctypes.c_int32, ctypes.c_float, _P, _P,
+                        _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_sdm": ([ctypes.POINTER(_Cloud), _Query, ctypes.c_float, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P],
                 ctypes.c_int),
     "apt_knn": ([ctypes.POINTER(_Cloud), _Query, ctypes.c_int32, ctypes.c_float, ctypes.c_int64, _P, _P, _P,
@@ -360,6 +362,24 @@ def sdm(cloud: Cloud, target: int, neighbor: int, d_srf: float, R: float = 2.0, 
     _check(lib().apt_sdm(cloud.c(), _query(target, neighbor, d_srf), float(R), int(n_vox), _ptr(out),
                          _ptr(status), _ptr(buf), nb, _stream(cloud.xyz)), "apt_sdm")
     return out
+
+
+def cluster_ms(cloud: Cloud, species: int, d_max: float, n_min: int, d_srf: float = 0.0, n_size_bins: int = 0,
+               ws: Workspace | None = None, status: torch.Tensor | None = None):
+    """Maximum-separation clustering of the ions of `species`: (label int64 [n]:
+    the smallest ion index of the ion's kept cluster or -1, counts int64 [3]:
+    kept clusters, kept clusters with an ion at the edge, ions in kept
+    clusters, size_hist int64 [n_size_bins] or None, status int32 [1])."""
+    buf, nb = _ws(ws, OP_CLUSTER, cloud)
+    dev = cloud.device
+    label = torch.empty(max(cloud.n, 1), dtype=torch.int64, device=dev)
+    counts = torch.empty(3, dtype=torch.int64, device=dev)
+    hist = torch.empty(n_size_bins, dtype=torch.int64, device=dev) if n_size_bins > 0 else None
+    status = status if status is not None else torch.empty(1, dtype=torch.int32, device=dev)
+    _check(lib().apt_cluster_ms(cloud.c(), int(species), float(d_max), int(n_min), float(d_srf), _ptr(label),
+                                _ptr(counts), _ptr(hist), int(n_size_bins), _ptr(status), _ptr(buf), nb,
+                                _stream(cloud.xyz)), "apt_cluster_ms")
+    return label[:cloud.n], counts, hist, status
 
 
 class KnnResult:

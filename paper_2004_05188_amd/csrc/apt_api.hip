@@ -15,6 +15,7 @@
 #include "apt_pair.hpp"
 #include "apt_perm.hpp"
 #include "apt_sdm.hpp"
+#include "apt_cluster.hpp"
 #include "apt_smooth.hpp"
 
 namespace apt {
@@ -1329,6 +1330,7 @@ size_t apt_workspace_size(int32_t op, int64_t n, int32_t n_pairs, int32_t n_rep)
         case APT_OP_SMOOTH:
             return carve_smooth(nullptr, n).bytes;
         case APT_OP_SDM:
+        case APT_OP_CLUSTER:
             return carve_plain(nullptr, n).bytes;
         default:
             return 0;
@@ -1481,6 +1483,92 @@ apt_status apt_batched_plan_clear(void) {
 apt_status apt_sdm(const apt_cloud* cloud, apt_query q, float R, int32_t n_vox, uint64_t* hist, int32_t* status,
                    void* ws, size_t ws_bytes, void* stream) {
     return run_sdm(cloud, q, R, n_vox, hist, status, ws, ws_bytes, stream);
+}
+
+// ------------------------------------------------ maximum separation --
+// The species' ions are binned as the targets and neighbours of one query
+// (no surface filter: every ion of the species is a vertex); the union-find
+// forest and the cluster sizes live in the radix sort's key arrays, which
+// the binning no longer needs once it has finished.
+apt_status apt_cluster_ms(const apt_cloud* cloud, uint8_t species, float d_max, int32_t n_min, float d_srf,
+                          int64_t* label, int64_t* counts, uint64_t* size_hist, int32_t n_size_bins,
+                          int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+    apt_status s;
+    if ((s = check_cloud(cloud)) != APT_OK) return s;
+    if (cloud->n >= ((int64_t)1 << 31)) return fail(APT_E_UNSUPPORTED, "clustering needs fewer than 2^31 ions");
+    if (!(d_max > 0.0f) || !isfinite(d_max)) return fail(APT_E_ARG, "d_max must be finite and > 0");
+    if (n_min < 1) return fail(APT_E_ARG, "n_min must be >= 1");
+    if (isnan(d_srf)) return fail(APT_E_ARG, "d_srf is NaN");
+    if (size_hist && (n_size_bins < 1 || n_size_bins > APT_MAX_BINS))
+        return fail(APT_E_ARG, "n_size_bins must be in [1, 65536]");
+    if (!counts || !status) return fail(APT_E_ARG, "counts or status is NULL");
+    if (cloud->n > 0 && !label) return fail(APT_E_ARG, "label is NULL");
+    PlainWs w = carve_plain(ws, cloud->n);
+    if ((s = check_ws(ws, ws_bytes, w.bytes)) != APT_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    apt_cloud cl = *cloud;
+    cl.d_bnd = nullptr;                        // every ion of the species is a vertex
+    apt_query q{};
+    q.target = species;
+    q.neighbor = species;
+    q.d_srf = 0.0f;
+    InitArgs ia{status, size_hist, size_hist ? n_size_bins : 0, reinterpret_cast<uint64_t*>(counts), 3, nullptr,
+                w.strag_count};
+    const apt_tuning tu = tuning();
+    const double dm = (double)d_max;
+    PlanParams pp;
+    pp.h_min = d_max * tu.h_min_frac;
+    pp.occ = tu.cell_occ;
+    pp.tile_occ = tu.tile_occ;
+    pp.k = 0;
+    pp.cell_cap = cell_cap_for(cl.n);
+    pp.tile_policy = 1;                        // one target per wavefront
+    pp.r_enum = (float)(dm * (1.0 + 4e-5));
+    pp.h_shrink = 0.7f;
+    {
+        TraceSpan span("binning", st);
+        if ((s = run_binning(&cl, q, pp, w, status, st, nullptr, 0, &ia)) != APT_OK) return s;
+    }
+    if (cl.n == 0) return hip_check("clustering launch");
+    const uint32_t n = (uint32_t)cl.n;
+    uint32_t* parent = w.K[0];
+    uint32_t* size = w.K[1];
+    const int g = (int)std::min<int64_t>(((int64_t)n + kBlock - 1) / kBlock, 8192);
+    ClusterLinkArgs la{};
+    la.plan = w.plan;
+    la.t_id = w.t_id;
+    la.tx = w.tx;
+    la.ty = w.ty;
+    la.tz = w.tz;
+    la.bpos = w.bpos;
+    la.cell_start = w.cell_start;
+    la.r_enum = pp.r_enum;
+    la.in2 = (float)((dm * (1.0 - 2e-5)) * (dm * (1.0 - 2e-5)));
+    la.out2 = (float)((dm * (1.0 + 2e-5)) * (dm * (1.0 + 2e-5)));
+    la.lim2 = dm * dm;
+    la.parent = parent;
+    ClusterOutArgs oa{};
+    oa.lab = cl.lab;
+    oa.d_bnd = cloud->d_bnd;
+    oa.d_srf = d_srf;
+    oa.A = species;
+    oa.n = n;
+    oa.n_min = n_min;
+    oa.parent = parent;
+    oa.size = size;
+    oa.label = label;
+    oa.counts = reinterpret_cast<unsigned long long*>(counts);
+    oa.size_hist = size_hist;
+    oa.n_size_bins = size_hist ? n_size_bins : 0;
+    {
+        TraceSpan span("cluster", st);
+        hipLaunchKernelGGL(k_ms_init, dim3(g), dim3(kBlock), 0, st, parent, size, n);
+        hipLaunchKernelGGL(k_ms_link, dim3(resident_grid(k_ms_link, 0)), dim3(kBlock), 0, st, la);
+        hipLaunchKernelGGL(k_ms_roots, dim3(g), dim3(kBlock), 0, st, oa);
+        hipLaunchKernelGGL(k_ms_final, dim3(g), dim3(kBlock), 0, st, oa);
+    }
+    return hip_check("clustering launch");
 }
 
 apt_status apt_count_targets(const apt_cloud* cloud, apt_query q, int64_t* n_targets, void* ws, size_t ws_bytes,

@@ -194,3 +194,27 @@ def test_batched_histogram_size_limit(aptstat):
     # stops at the workspace check instead)
     assert L.apt_rdf_batched(_cloud(aptstat), qs, 16, seeds, n_rep, rb, 10, kb, p, None, None, p, None, big,
                              None) == -2
+
+
+def test_cluster_argument_validation(aptstat):
+    L = aptstat.lib()
+    ws = ctypes.c_void_p(0x100000)
+    big = 1 << 40
+    lab, cnt, st, hist = (ctypes.c_void_p(a) for a in (0x3000, 0x4000, 0x5000, 0x6000))
+    assert aptstat.lib().apt_workspace_size(aptstat.OP_CLUSTER, 1000, 0, 0) == \
+        aptstat.lib().apt_workspace_size(aptstat.OP_RDF, 1000, 0, 0)
+
+    def call(cloud=None, d_max=0.5, n_min=5, d_srf=0.0, label=lab, counts=cnt, h=None, nb=0, status=st, w=ws,
+             wb=big):
+        return L.apt_cluster_ms(cloud if cloud is not None else _cloud(aptstat), 1, d_max, n_min, d_srf, label,
+                                counts, h, nb, status, w, wb, None)
+
+    for bad in (0.0, -1.0, math.inf, math.nan):
+        assert call(d_max=bad) == -1 and "d_max" in _err(aptstat)
+    assert call(n_min=0) == -1 and "n_min" in _err(aptstat)
+    assert call(d_srf=math.nan) == -1
+    assert call(h=hist, nb=0) == -1 and call(h=hist, nb=65537) == -1
+    assert call(counts=None) == -1 and call(status=None) == -1 and call(label=None) == -1
+    c = aptstat._Cloud(0x1000, 0x2000, None, 1 << 31)
+    assert call(cloud=ctypes.byref(c)) == -3 and "2^31" in _err(aptstat)
+    assert call(w=None) == -2 and call(wb=1024) == -2
