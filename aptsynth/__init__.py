@@ -19,6 +19,9 @@ five workloads this library is measured on:
 * ``frustum2g`` 2e9 ions, the H = 2000 nm, R 60 -> 30 nm needle scaled by
   1.7159 in every length so that it holds 2e9 ions at 30 ions/nm^3; chemistry
   and cluster density as ``frustum7m``; no noise.
+
+``frustum_mesh`` triangulates a frustum specimen's surface: the triangle
+hull that the ion-to-edge distancing takes as its input.
 """
 from __future__ import annotations
 
@@ -207,6 +210,33 @@ def frustum200m(seed: int = 1) -> Specimen:
     """The full-scale needle's shape and chemistry at a tenth of its ions (same
     density: the same per-target work, for profiling runs)."""
     return frustum2g(seed=seed, n=200_000_000)
+
+
+def frustum_mesh(spec: Specimen, n_phi: int, n_z: int) -> np.ndarray:
+    """A closed triangle hull of a frustum specimen (side, bottom and top
+    caps), float32 [n_tri, 3, 3]: the given edge of the ion-to-edge
+    distancing.  The side is n_z rings of n_phi quads, each split into two
+    triangles; each cap is a fan of n_phi triangles around the axis.  The
+    vertices lie on the analytic surface, so the hull is inscribed in it
+    (the side's chords sit at most R (1 - cos(pi / n_phi)) inside)."""
+    H, R0, R1 = float(spec.H), float(spec.R0), float(spec.R1)
+    phi = 2.0 * np.pi * np.arange(n_phi + 1) / n_phi
+    phi[-1] = 0.0                                     # the seam closes exactly
+    z = H * np.arange(n_z + 1) / n_z
+    R = R0 + (R1 - R0) * z / H
+    X = R[:, None] * np.cos(phi)[None, :]
+    Y = R[:, None] * np.sin(phi)[None, :]
+    Z = np.broadcast_to(z[:, None], X.shape)
+    V = np.stack([X, Y, Z], -1)                       # [n_z + 1, n_phi + 1, 3]
+    a, b = V[:-1, :-1], V[:-1, 1:]
+    c, d = V[1:, :-1], V[1:, 1:]
+    side = np.concatenate([np.stack([a, b, d], 2).reshape(-1, 3, 3), np.stack([a, d, c], 2).reshape(-1, 3, 3)])
+    ctr0 = np.zeros((n_phi, 3))
+    ctr1 = np.zeros((n_phi, 3))
+    ctr1[:, 2] = H
+    cap0 = np.stack([ctr0, V[0, 1:], V[0, :-1]], 1)
+    cap1 = np.stack([ctr1, V[-1, :-1], V[-1, 1:]], 1)
+    return np.ascontiguousarray(np.concatenate([side, cap0, cap1]).astype(np.float32))
 
 
 WORKLOADS = {"box240k": box240k, "frustum7m": frustum7m, "box1m": box1m, "frustum2g": frustum2g,

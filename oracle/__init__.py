@@ -47,6 +47,8 @@ def _load():
             "orc_sdm_grid": ([_p, _p, _p, _i64, _i32, _i32, _f32, _f32, _i32, _p], None),
             "orc_cluster_ms_brute": ([_p, _p, _p, _i64, _i32, _f32, _i32, _f32, _p, _p, _p, _i32], None),
             "orc_cluster_ms_grid": ([_p, _p, _p, _i64, _i32, _f32, _i32, _f32, _p, _p, _p, _i32], None),
+            "orc_edge_brute": ([_p, _i64, _p, _i64, _f32, _p], None),
+            "orc_edge_grid": ([_p, _i64, _p, _i64, _f32, _p], None),
             "orc_d2f": ([_p, _p], _f32),
             "orc_D2": ([_p, _p], _f64),
             "orc_edges2": ([_f32, _i32, _p], None),
@@ -185,6 +187,18 @@ def cluster_ms(xyz, lab, d_bnd, A: int, d_max: float, n_min: int, d_srf: float =
     f(xyz.ctypes.data, lab.ctypes.data, _ptr(d_bnd), n, A, d_max, n_min, d_srf, label.ctypes.data,
       counts.ctypes.data, _ptr(hist), n_size_bins)
     return label, counts, hist
+
+
+def edge_distance(xyz, tri, d_prb: float = float("inf"), method: str = "grid") -> np.ndarray:
+    """Distance of every ion to the closest point of the triangles (float32
+    [n]): +inf at or beyond d_prb, NaN for a non-finite position.  The grid
+    form needs a finite d_prb (the brute-force form is taken otherwise)."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+    tri = np.ascontiguousarray(tri, dtype=np.float32).reshape(-1, 9)
+    d = np.empty(xyz.shape[0], dtype=np.float32)
+    f = _load().orc_edge_grid if (method == "grid" and np.isfinite(d_prb)) else _load().orc_edge_brute
+    f(xyz.ctypes.data, xyz.shape[0], tri.ctypes.data, tri.shape[0], d_prb, d.ctypes.data)
+    return d
 
 
 def splitmix64(seed: int, i: int) -> int:

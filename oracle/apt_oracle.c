@@ -963,3 +963,214 @@ void orc_cluster_ms_grid(const float* xyz, const uint8_t* lab, const float* d_bn
     free(queue);
     free(comp);
 }
+
+/* ------------------------------------------------------------------------
+ * Ion-to-edge distancing (paper, Methods: "Ion-to-edge distancing";
+ * Supplementary: "Triangle filtering methods for ion-to-edge distancing";
+ * the benchmark table's "Surfacing" task with its probe distance d_prb).
+ *
+ * The distance of a point to a closed triangle is the smallest distance to
+ * any point of it: the distance to the triangle's plane when the foot of the
+ * perpendicular lies inside the triangle, else the smallest distance to its
+ * three edges.  A triangle of zero area is its edges.  Arithmetic in FP64 on
+ * the stored FP32 values.  d[i] is the smallest distance over the triangles,
+ * rounded to FP32, when it is below d_prb, else +inf; NaN for an ion with a
+ * non-finite position.  Triangles with a non-finite vertex are left out.
+ * ------------------------------------------------------------------------ */
+static void v3sub(const double* a, const double* b, double* r) {
+    r[0] = a[0] - b[0];
+    r[1] = a[1] - b[1];
+    r[2] = a[2] - b[2];
+}
+static double v3dot(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void v3cross(const double* a, const double* b, double* r) {
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* squared distance of p to the segment [a, b] */
+static double seg_d2(const double* p, const double* a, const double* b) {
+    double ab[3], ap[3], q[3], pq[3];
+    v3sub(b, a, ab);
+    v3sub(p, a, ap);
+    const double L = v3dot(ab, ab);
+    double t = L > 0 ? v3dot(ap, ab) / L : 0.0;
+    if (t < 0) t = 0;
+    if (t > 1) t = 1;
+    for (int k = 0; k < 3; ++k) q[k] = a[k] + t * ab[k];
+    v3sub(p, q, pq);
+    return v3dot(pq, pq);
+}
+
+/* squared distance of p to the closed triangle (v0, v1, v2) */
+static double tri_d2(const double* p, const double* v0, const double* v1, const double* v2) {
+    double best = seg_d2(p, v0, v1);
+    double s = seg_d2(p, v1, v2);
+    if (s < best) best = s;
+    s = seg_d2(p, v2, v0);
+    if (s < best) best = s;
+    double e1[3], e2[3], nrm[3], w[3];
+    v3sub(v1, v0, e1);
+    v3sub(v2, v0, e2);
+    v3cross(e1, e2, nrm);
+    const double nn = v3dot(nrm, nrm);
+    if (nn > 0) {
+        v3sub(p, v0, w);
+        const double h = v3dot(w, nrm);
+        double f[3];
+        for (int k = 0; k < 3; ++k) f[k] = p[k] - (h / nn) * nrm[k];   /* foot of the perpendicular */
+        /* inside: on the inner side of all three edges */
+        const double* V[3] = {v0, v1, v2};
+        int inside = 1;
+        for (int e = 0; e < 3; ++e) {
+            double ed[3], fv[3], c[3];
+            v3sub(V[(e + 1) % 3], V[e], ed);
+            v3sub(f, V[e], fv);
+            v3cross(ed, fv, c);
+            if (v3dot(c, nrm) < 0) inside = 0;
+        }
+        if (inside) {
+            const double h2 = h * h / nn;
+            if (h2 < best) best = h2;
+        }
+    }
+    return best;
+}
+
+static int tri_finite(const float* t) {
+    for (int k = 0; k < 9; ++k)
+        if (!isfinite(t[k])) return 0;
+    return 1;
+}
+
+static float edge_result(const float* p, double best2, float d_prb) {
+    if (!finite3(p)) return NAN;
+    const double d = sqrt(best2);
+    return d < (double)d_prb ? (float)d : INFINITY;
+}
+
+void orc_edge_brute(const float* xyz, int64_t n, const float* tri, int64_t n_tri, float d_prb, float* d) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        const double p[3] = {xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2]};
+        double best2 = INFINITY;
+        for (int64_t t = 0; t < n_tri; ++t) {
+            const float* T = tri + 9 * t;
+            if (!tri_finite(T)) continue;
+            const double v0[3] = {T[0], T[1], T[2]}, v1[3] = {T[3], T[4], T[5]}, v2[3] = {T[6], T[7], T[8]};
+            const double s = tri_d2(p, v0, v1, v2);
+            if (s < best2) best2 = s;
+        }
+        d[i] = edge_result(xyz + 3 * i, best2, d_prb);
+    }
+}
+
+/* The same with the triangles binned into cubic cells of edge >= d_prb
+ * (each in every cell its bounding box meets): only the triangles of the
+ * cells that the cube [p - d_prb, p + d_prb] meets can lie within d_prb.
+ * d_prb must be finite. */
+typedef struct {
+    double lo[3];
+    double h;
+    int64_t dim[3];
+} tgrid;
+
+/* cells [c0, c1] of the interval [x0, x1] on axis a, clamped to the grid;
+ * 0 when the interval misses the grid */
+static int tgrid_range(const tgrid* g, int a, double x0, double x1, int64_t* c0, int64_t* c1) {
+    const double f0 = floor((x0 - g->lo[a]) / g->h), f1 = floor((x1 - g->lo[a]) / g->h);
+    if (f1 < 0 || f0 > (double)(g->dim[a] - 1)) return 0;
+    *c0 = f0 < 0 ? 0 : (int64_t)f0;
+    *c1 = f1 > (double)(g->dim[a] - 1) ? g->dim[a] - 1 : (int64_t)f1;
+    return 1;
+}
+
+/* the cell box of a triangle's vertices; 0 when it misses the grid */
+static int tri_cells(const tgrid* g, const float* T, int64_t c0[3], int64_t c1[3]) {
+    for (int a = 0; a < 3; ++a) {
+        const double x0 = fmin(fmin(T[a], T[3 + a]), T[6 + a]), x1 = fmax(fmax(T[a], T[3 + a]), T[6 + a]);
+        if (!tgrid_range(g, a, x0, x1, &c0[a], &c1[a])) return 0;
+    }
+    return 1;
+}
+
+void orc_edge_grid(const float* xyz, int64_t n, const float* tri, int64_t n_tri, float d_prb, float* d) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    int64_t nv = 0;
+    for (int64_t t = 0; t < n_tri; ++t) {
+        if (!tri_finite(tri + 9 * t)) continue;
+        ++nv;
+        for (int k = 0; k < 9; ++k) {
+            const double v = tri[9 * t + k];
+            if (v < lo[k % 3]) lo[k % 3] = v;
+            if (v > hi[k % 3]) hi[k % 3] = v;
+        }
+    }
+    if (nv == 0) {
+        for (int64_t i = 0; i < n; ++i) d[i] = edge_result(xyz + 3 * i, INFINITY, d_prb);
+        return;
+    }
+    tgrid g;
+    g.h = (double)d_prb;
+    for (;;) {   /* bounded table: at most ~8 cells per triangle */
+        double cells = 1;
+        for (int a = 0; a < 3; ++a) cells *= floor((hi[a] - lo[a]) / g.h) + 1;
+        if (cells <= 8.0 * (double)nv + 64.0) break;
+        g.h *= 1.5;
+    }
+    int64_t ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        g.lo[a] = lo[a];
+        g.dim[a] = (int64_t)floor((hi[a] - lo[a]) / g.h) + 1;
+        ncell *= g.dim[a];
+    }
+    int64_t* start = (int64_t*)calloc((size_t)ncell + 1, sizeof(int64_t));
+    int64_t c0[3], c1[3];
+    for (int64_t t = 0; t < n_tri; ++t) {                    /* count */
+        if (!tri_finite(tri + 9 * t) || !tri_cells(&g, tri + 9 * t, c0, c1)) continue;
+        for (int64_t z = c0[2]; z <= c1[2]; ++z)
+            for (int64_t y = c0[1]; y <= c1[1]; ++y)
+                for (int64_t x = c0[0]; x <= c1[0]; ++x) start[(z * g.dim[1] + y) * g.dim[0] + x + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
+    int64_t* item = (int64_t*)malloc(sizeof(int64_t) * (size_t)(start[ncell] > 0 ? start[ncell] : 1));
+    int64_t* fill = (int64_t*)calloc((size_t)ncell, sizeof(int64_t));
+    for (int64_t t = 0; t < n_tri; ++t) {                    /* fill */
+        if (!tri_finite(tri + 9 * t) || !tri_cells(&g, tri + 9 * t, c0, c1)) continue;
+        for (int64_t z = c0[2]; z <= c1[2]; ++z)
+            for (int64_t y = c0[1]; y <= c1[1]; ++y)
+                for (int64_t x = c0[0]; x <= c1[0]; ++x) {
+                    const int64_t c = (z * g.dim[1] + y) * g.dim[0] + x;
+                    item[start[c] + fill[c]++] = t;
+                }
+    }
+    free(fill);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        const float* pi = xyz + 3 * i;
+        double best2 = INFINITY;
+        int64_t q0[3], q1[3];
+        int ok = finite3(pi);
+        for (int a = 0; ok && a < 3; ++a)
+            ok = tgrid_range(&g, a, (double)pi[a] - (double)d_prb, (double)pi[a] + (double)d_prb, &q0[a], &q1[a]);
+        if (ok) {
+            const double p[3] = {pi[0], pi[1], pi[2]};
+            for (int64_t z = q0[2]; z <= q1[2]; ++z)
+                for (int64_t y = q0[1]; y <= q1[1]; ++y)
+                    for (int64_t x = q0[0]; x <= q1[0]; ++x) {
+                        const int64_t c = (z * g.dim[1] + y) * g.dim[0] + x;
+                        for (int64_t k = start[c]; k < start[c + 1]; ++k) {
+                            const float* T = tri + 9 * item[k];
+                            const double v0[3] = {T[0], T[1], T[2]}, v1[3] = {T[3], T[4], T[5]},
+                                         v2[3] = {T[6], T[7], T[8]};
+                            const double s = tri_d2(p, v0, v1, v2);
+                            if (s < best2) best2 = s;
+                        }
+                    }
+        }
+        d[i] = edge_result(pi, best2, d_prb);
+    }
+    free(item);
+    free(start);
+}

@@ -3,8 +3,8 @@
  *
  * A plain, slow CPU reference for the spatial-statistics path (kNN and RDF
  * of target ions against neighbour ions, the label-randomised null model, a
- * Gaussian-smoothed RDF with its gradient, the two-point statistic and the
- * maximum-separation clustering).  Only the test-suite, the
+ * Gaussian-smoothed RDF with its gradient, the two-point statistic, the
+ * maximum-separation clustering and the ion-to-edge distancing).  Only the test-suite, the
  * smoke check and the benchmark's CPU baseline may call it; the GPU library
  * never includes, links or calls anything here, and this file shares no code
  * with it.  All pointers are host pointers.  Species 255 means "any species".
@@ -40,6 +40,13 @@ void orc_cluster_ms_brute(const float* xyz, const uint8_t* lab, const float* d_b
 void orc_cluster_ms_grid(const float* xyz, const uint8_t* lab, const float* d_bnd, int64_t n, int32_t A,
                          float d_max, int32_t n_min, float d_srf, int64_t* label, int64_t* counts,
                          uint64_t* size_hist, int32_t n_size_bins);
+
+/* Ion-to-edge distancing: d[i] = the FP64 distance of ion i to the closest
+ * point of the closed triangles tri[n_tri][3][3], rounded to FP32, when
+ * below d_prb, else +inf; NaN for a non-finite position; triangles with a
+ * non-finite vertex are left out.  The grid form needs a finite d_prb. */
+void orc_edge_brute(const float* xyz, int64_t n, const float* tri, int64_t n_tri, float d_prb, float* d);
+void orc_edge_grid(const float* xyz, int64_t n, const float* tri, int64_t n_tri, float d_prb, float* d);
 
 /* Canonical distances between two stored FP32 positions. */
 float orc_d2f(const float* a, const float* b);   /* FP32, fixed evaluation order */

@@ -849,3 +849,126 @@ def test_cluster_ms_refines_and_relabels(orc, synth):
     lp, cp, _ = orc.cluster_ms(xyz[perm], lab[perm], None, SC, 0.5, 1)
     assert sorted(sorted(perm[m].tolist()) for m in _partition(lp).values()) == \
         sorted(_partition(small).values())
+
+
+# --------------------------------------------------------------------------
+# ion-to-edge distancing
+# --------------------------------------------------------------------------
+
+def _ulps(a, b):
+    """FP32 ulps between two finite float32 arrays of one sign."""
+    ia = np.asarray(a, np.float32).view(np.int32).astype(np.int64)
+    ib = np.asarray(b, np.float32).view(np.int32).astype(np.int64)
+    return np.abs(ia - ib)
+
+
+def test_edge_single_triangle_regions(orc):
+    # the right triangle (0,0,0), (4,0,0), (0,4,0): exact distances per region
+    tri = np.array([[[0, 0, 0], [4, 0, 0], [0, 4, 0]]], np.float32)
+    pts = np.array([
+        [1, 1, 3],        # above the interior: the height
+        [1, 1, -2],       # below it
+        [2, -3, 0],       # beyond the edge on the x axis: to the edge
+        [-2, 1, 4],       # beyond the edge on the y axis, off the plane
+        [3, 3, 0],        # beyond the hypotenuse, in the plane
+        [6, -1, 2],       # beyond the vertex (4, 0, 0)
+        [-3, -4, 0],      # beyond the vertex (0, 0, 0)
+        [0, 0, 0],        # on a vertex
+    ], np.float32)
+    expect = [3.0, 2.0, 3.0, np.sqrt(4 + 16), np.sqrt(2.0), np.sqrt(4 + 1 + 4), 5.0, 0.0]
+    got = orc.edge_distance(pts, tri, np.inf, method="brute")
+    assert np.array_equal(got, np.array(expect, np.float32))
+    # zero-area triangles are their edges: a segment and a point
+    seg = np.array([[[0, 0, 0], [2, 0, 0], [1, 0, 0]]], np.float32)
+    assert np.array_equal(orc.edge_distance(np.array([[1, 3, 4], [5, 0, 4]], np.float32), seg, np.inf, "brute"),
+                          np.array([5.0, 5.0], np.float32))
+    dot = np.array([[[1, 1, 1]] * 3], np.float32)
+    assert orc.edge_distance(np.array([[4, 5, 1]], np.float32), dot, np.inf, "brute")[0] == np.float32(5.0)
+
+
+def _box_mesh(lo, hi):
+    c = np.array([[lo[0] if i & 1 == 0 else hi[0], lo[1] if i & 2 == 0 else hi[1], lo[2] if i & 4 == 0 else hi[2]]
+                  for i in range(8)], np.float64)
+    quads = [(0, 1, 3, 2), (4, 5, 7, 6), (0, 1, 5, 4), (2, 3, 7, 6), (0, 2, 6, 4), (1, 3, 7, 5)]
+    tris = []
+    for a, b, cc, d in quads:
+        tris += [[c[a], c[b], c[cc]], [c[a], c[cc], c[d]]]
+    return np.array(tris, np.float32)
+
+
+def test_edge_box_surface_closed_form(orc):
+    # a box surface of 12 triangles: inside, the distance to the nearest
+    # face; outside, the Euclidean distance to the box
+    lo, hi = np.array([1.0, 2.0, 0.5]), np.array([7.0, 5.0, 4.5])
+    mesh = _box_mesh(lo, hi)
+    rng = np.random.default_rng(11)
+    p = rng.uniform(lo - 3.0, hi + 3.0, (20000, 3)).astype(np.float32)
+    P = p.astype(np.float64)
+    inside = np.all((P >= lo) & (P <= hi), 1)
+    d_in = np.minimum(P - lo, hi - P).min(1)
+    d_out = np.sqrt((np.maximum(np.maximum(lo - P, 0.0), P - hi) ** 2).sum(1))
+    expect = np.where(inside, d_in, d_out).astype(np.float32)
+    got = orc.edge_distance(p, mesh, np.inf, method="brute")
+    assert inside.sum() > 1000 and (~inside).sum() > 1000
+    assert _ulps(got, expect).max() <= 1
+    g2 = orc.edge_distance(p, mesh, 1.5, method="grid")
+    near = expect.astype(np.float64) < 1.5 * (1 - 1e-6)
+    far = expect.astype(np.float64) > 1.5 * (1 + 1e-6)
+    assert np.array_equal(g2[near], got[near]) and np.isinf(g2[far]).all()
+
+
+def test_edge_sampled_triangles_bracket(orc):
+    # the distance lies between the closest of a dense sample of the
+    # triangle's points and that value less the sample spacing
+    rng = np.random.default_rng(13)
+    m = 60
+    u, v = np.meshgrid(np.arange(m + 1) / m, np.arange(m + 1) / m)
+    keep = (u + v) <= 1.0 + 1e-12
+    u, v = u[keep], v[keep]
+    for _ in range(20):
+        T = rng.normal(0, 2, (3, 3)).astype(np.float32)
+        q = rng.normal(0, 3, (50, 3)).astype(np.float32)
+        S = T[0].astype(np.float64) + u[:, None] * (T[1] - T[0]).astype(np.float64) + \
+            v[:, None] * (T[2] - T[0]).astype(np.float64)
+        ds = np.sqrt(((q.astype(np.float64)[:, None, :] - S[None]) ** 2).sum(-1)).min(1)
+        got = orc.edge_distance(q, T[None], np.inf, method="brute").astype(np.float64)
+        spacing = max(np.linalg.norm((T[1] - T[0]).astype(np.float64)),
+                      np.linalg.norm((T[2] - T[0]).astype(np.float64))) / m
+        assert np.all(got <= ds * (1 + 1e-6) + 1e-6)
+        assert np.all(got >= ds - spacing - 1e-6)
+
+
+def test_edge_frustum_mesh_against_analytic_surface(orc, synth):
+    # the hull is inscribed in the frustum: its distance differs from the
+    # analytic surface distance by at most the chords' sagitta
+    spec = synth.clustered_needle(30.0, 10.0, 6.0, seed=7)
+    xyz, _, d_an = spec.generate()
+    n_phi = 96
+    mesh = synth.frustum_mesh(spec, n_phi, 60)
+    got = orc.edge_distance(xyz, mesh, 3.0, method="grid")
+    sag = spec.R0 * (1 - np.cos(np.pi / n_phi))
+    near = d_an < 3.0 - sag - 1e-4
+    assert near.sum() > 1000
+    assert np.all(np.abs(got[near].astype(np.float64) - d_an[near]) <= sag + 1e-5)
+    assert np.all(np.isinf(got[d_an > 3.0 + sag + 1e-4]))
+
+
+def test_edge_brute_equals_grid_and_rigid_shift(orc, synth):
+    spec = synth.clustered_needle(20.0, 8.0, 5.0, seed=9)
+    xyz, _, _ = spec.generate()
+    xyz = xyz[:20000].copy()
+    xyz[5] = np.nan
+    mesh = synth.frustum_mesh(spec, 48, 30)
+    mesh[3, 1, 2] = np.inf                      # a triangle left out
+    b = orc.edge_distance(xyz, mesh, 2.0, method="brute")
+    g = orc.edge_distance(xyz, mesh, 2.0, method="grid")
+    assert np.array_equal(b, g, equal_nan=True)
+    assert np.isnan(b[5]) and np.isfinite(b).sum() > 1000
+    # on a dyadic grid a shift by whole nanometres is exact: equal distances
+    q = np.round(xyz[:3000] * 1024) / 1024
+    t = np.round(mesh * 1024) / 1024
+    t[3, 1, 2] = 0.5
+    s = np.array([64.0, -128.0, 256.0], np.float32)
+    d0 = orc.edge_distance(q.astype(np.float32), t.astype(np.float32), 2.0)
+    d1 = orc.edge_distance((q + s).astype(np.float32), (t + s).astype(np.float32), 2.0)
+    assert np.array_equal(d0, d1, equal_nan=True)
