@@ -221,6 +221,34 @@ def cluster_timing(aptstat, torch, cloud, ws, reps=3):
             "sweep_ms": 1e3 * dt * len(d_maxes), "kept_clusters": kept, "truncated_clusters": trunc}
 
 
+def edge_timing(aptstat, torch, cloud, ws, reps=5):
+    """Ion-to-edge distancing of the 7.7e6-ion needle against its inscribed
+    hull (256 x 200 side quads and two caps: 102 912 triangles, about the
+    paper's triangle density per surface area at 2e9 ions) at the benchmark's
+    probe distance d_prb = 2.5 nm: ms per call and the ions within d_prb."""
+    import aptsynth
+
+    mesh = aptsynth.frustum_mesh(aptsynth.frustum7m(), 256, 200)
+    tri = torch.from_numpy(mesh).to(cloud.device)
+    d, st = aptstat.edge_distance(cloud, tri, 2.5, ws=ws)
+    torch.cuda.synchronize()
+    within = int(torch.isfinite(d).sum().item())
+    for stage in ("edge", "binning"):
+        aptstat.trace_read(stage)
+    aptstat.trace_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        aptstat.edge_distance(cloud, tri, 2.5, ws=ws, out=d)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    aptstat.trace_enable(False)
+    k_ms = aptstat.trace_read("edge")[0] / reps
+    b_ms = aptstat.trace_read("binning")[0] / reps
+    return {"workload": "frustum7m", "triangles": int(mesh.shape[0]), "d_prb_nm": 2.5, "ms_per_call": 1e3 * dt,
+            "edge_kernels_ms": k_ms, "binning_ms": b_ms, "ions_within_d_prb": within,
+            "ions_per_s": cloud.n / dt, "status": int(st.item())}
+
+
 PAIRS6 = [(AL, SC), (AL, SI), (SC, AL), (SC, SI), (SI, AL), (SI, SC)]
 
 
@@ -530,6 +558,8 @@ def main():
             line["sdm"] = sdm_timing(aptstat, torch, cloud, ws)
             log("[bench] maximum-separation clustering sweep on frustum7m")
             line["cluster"] = cluster_timing(aptstat, torch, cloud, ws)
+            log("[bench] ion-to-edge distancing on frustum7m")
+            line["edge"] = edge_timing(aptstat, torch, cloud, ws)
             del cloud, xyz_d, lab_d, d_d
         if not args.no_smooth:
             log("[bench] smoothed RDF on box1m")

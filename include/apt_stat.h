@@ -244,6 +244,29 @@ apt_status apt_batched_plan_clear(void);
 apt_status apt_sdm(const apt_cloud* cloud, apt_query q, float R, int32_t n_vox, uint64_t* hist, int32_t* status,
                    void* ws, size_t ws_bytes, void* stream);
 
+/* Ion-to-edge distancing (paper, Methods: "Ion-to-edge distancing";
+ * Supplementary: "Triangle filtering methods for ion-to-edge distancing";
+ * its benchmark's "Surfacing" task with the probe distance d_prb).  For
+ * every ion, the distance to the closest point of a given triangle hull
+ * (closed triangles; a zero-area triangle is its edges), computed in FP64
+ * on the stored FP32 values and rounded to FP32, when it is below d_prb;
+ * +inf otherwise.  The result serves as cloud->d_bnd of the other calls
+ * (an ion is a target when d >= d_srf: every ion at +inf is one for
+ * d_srf <= d_prb).
+ *   cloud        xyz and lab are read (lab only to bin the ions; any
+ *                values); d_bnd is not
+ *   tri          [n_tri][3][3] FP32, device: the vertices; triangles with a
+ *                non-finite vertex are left out and set APT_STATUS_NONFINITE
+ *   d_prb        > 0; +inf: exact for every ion (the search then spans the
+ *                whole depth of the cloud: for large clouds give the largest
+ *                distance that matters, e.g. the largest d_srf to be used)
+ *   d            [n] FP32, device, overwritten; NaN for an ion with a
+ *                non-finite position (APT_STATUS_NONFINITE)
+ * Workspace: apt_edge_workspace_size(n, n_tri) bytes. */
+size_t apt_edge_workspace_size(int64_t n, int64_t n_tri);
+apt_status apt_edge_distance(const apt_cloud* cloud, const float* tri, int64_t n_tri, float d_prb, float* d,
+                             int32_t* status, void* ws, size_t ws_bytes, void* stream);
+
 /* Maximum-separation clustering (paper, Methods: "Descriptive, two-point
  * spatial statistics, and clustering": the MS method with its parameters
  * d_max and N_min; Supplementary, "Efficient batch processing of spatial
@@ -374,7 +397,7 @@ apt_status apt_get_tuning(apt_tuning* t);
  * sorted records, "pair" = the pair kernel, "tile" = the 64-target kernel
  * (and the per-lane kNN of mode 4), "nbr" = the neighbour-major RDF kernel,
  * "sdm" = the two-point statistic's kernel, "cluster" = the clustering's
- * union-find kernels,
+ * union-find kernels, "edge" = the distancing's triangle grid and search,
  * "permute" and "partition" = the batched replicates' label permutation and
  * class split) and forgets that stage's records.  Host only; off by
  * default. */

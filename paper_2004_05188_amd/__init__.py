@@ -82,6 +82,9 @@ _SIGS = {
     "apt_batched_plan_clear": ([], ctypes.c_int),
     "apt_rdf": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_rdf_noalloc": ([ctypes.POINTER(_Cloud), _Query, _Bins, _P, _P, _P], ctypes.c_int),
+    "apt_edge_workspace_size": ([ctypes.c_int64, ctypes.c_int64], ctypes.c_size_t),
+    "apt_edge_distance": ([ctypes.POINTER(_Cloud), _P, ctypes.c_int64, ctypes.c_float, _P, _P, _P, ctypes.c_size_t,
+                           _P], ctypes.c_int),
     "apt_cluster_ms": ([ctypes.POINTER(_Cloud), ctypes.c_uint8, ctypes.c_float, ctypes.c_int32, ctypes.c_float, _P, _P,
                         _P, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P], ctypes.c_int),
     "apt_sdm": ([ctypes.POINTER(_Cloud), _Query, ctypes.c_float, ctypes.c_int32, _P, _P, _P, ctypes.c_size_t, _P],
@@ -362,6 +365,28 @@ def sdm(cloud: Cloud, target: int, neighbor: int, d_srf: float, R: float = 2.0, 
     _check(lib().apt_sdm(cloud.c(), _query(target, neighbor, d_srf), float(R), int(n_vox), _ptr(out),
                          _ptr(status), _ptr(buf), nb, _stream(cloud.xyz)), "apt_sdm")
     return out
+
+
+def edge_distance(cloud: Cloud, tri: torch.Tensor, d_prb: float = float("inf"), ws: Workspace | None = None,
+                  out: torch.Tensor | None = None, status: torch.Tensor | None = None):
+    """Distance of every ion to the closest point of the triangle hull `tri`
+    (float32 [n_tri, 3, 3] on the cloud's device): float32 [n], +inf at or
+    beyond d_prb, NaN for a non-finite position.  Returns (d, status)."""
+    dev = cloud.device
+    _need(tri, torch.float32, None, "tri")
+    if tri.dim() != 3 or tri.shape[1:] != (3, 3) or not tri.is_contiguous():
+        raise AptError("tri must be a contiguous float32 tensor [n_tri, 3, 3]")
+    n_tri = tri.shape[0]
+    nb = lib().apt_edge_workspace_size(cloud.n, n_tri)
+    if nb == 0:
+        raise AptError("cloud or hull too large for apt_edge_distance")
+    ws = ws if ws is not None else Workspace()
+    buf = ws.get(nb, dev)
+    d = out if out is not None else torch.empty(max(cloud.n, 1), dtype=torch.float32, device=dev)
+    status = status if status is not None else torch.empty(1, dtype=torch.int32, device=dev)
+    _check(lib().apt_edge_distance(cloud.c(), _ptr(tri) if n_tri else None, n_tri, float(d_prb), _ptr(d),
+                                   _ptr(status), _ptr(buf), nb, _stream(cloud.xyz)), "apt_edge_distance")
+    return d[:cloud.n], status
 
 
 def cluster_ms(cloud: Cloud, species: int, d_max: float, n_min: int, d_srf: float = 0.0, n_size_bins: int = 0,

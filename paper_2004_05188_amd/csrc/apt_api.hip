@@ -16,6 +16,7 @@
 #include "apt_perm.hpp"
 #include "apt_sdm.hpp"
 #include "apt_cluster.hpp"
+#include "apt_edge.hpp"
 #include "apt_smooth.hpp"
 
 namespace apt {
@@ -1483,6 +1484,113 @@ apt_status apt_batched_plan_clear(void) {
 apt_status apt_sdm(const apt_cloud* cloud, apt_query q, float R, int32_t n_vox, uint64_t* hist, int32_t* status,
                    void* ws, size_t ws_bytes, void* stream) {
     return run_sdm(cloud, q, R, n_vox, hist, status, ws, ws_bytes, stream);
+}
+
+// ------------------------------------------------- ion-to-edge distance --
+// The plain binning (every ion a neighbour, no targets) puts the ions in cell
+// order; the triangle arrays follow it in the workspace.
+struct EdgeWs {
+    PlainWs plain;
+    TriPlan* tp;
+    float4* tc;
+    uint32_t* tcell;
+    uint32_t* tcnt;
+    uint32_t* tstart;
+    uint32_t* tblk;
+    uint32_t* torder;
+    float4* tsorted;
+    size_t bytes;
+};
+
+static EdgeWs carve_edge(void* base, int64_t n, int64_t n_tri) {
+    EdgeWs w;
+    w.plain = carve_plain(base, n);
+    Carve c{reinterpret_cast<char*>(base), w.plain.bytes};
+    const size_t T = (size_t)(n_tri > 0 ? n_tri : 1);
+    w.tp = c.take<TriPlan>(1);
+    w.tc = c.take<float4>(T);
+    w.tcell = c.take<uint32_t>(T);
+    w.tcnt = c.take<uint32_t>(kTriCells);
+    w.tstart = c.take<uint32_t>((size_t)kTriCells + 1);
+    w.tblk = c.take<uint32_t>(kTriScanBlocks);
+    w.torder = c.take<uint32_t>(T);
+    w.tsorted = c.take<float4>(T);
+    w.bytes = c.off;
+    return w;
+}
+
+size_t apt_edge_workspace_size(int64_t n, int64_t n_tri) {
+    if (n < 0 || n >= (int64_t)0xFFFFFFFFll || n_tri < 0 || n_tri >= (int64_t)0xFFFFFFFFll) return 0;
+    return carve_edge(nullptr, n, n_tri).bytes;
+}
+
+apt_status apt_edge_distance(const apt_cloud* cloud, const float* tri, int64_t n_tri, float d_prb, float* d,
+                             int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+    apt_status s;
+    if ((s = check_cloud(cloud)) != APT_OK) return s;
+    if (n_tri < 0) return fail(APT_E_ARG, "n_tri is negative");
+    if (n_tri >= (int64_t)0xFFFFFFFFll) return fail(APT_E_UNSUPPORTED, "n_tri must be below 2^32 - 1");
+    if (n_tri > 0 && !tri) return fail(APT_E_ARG, "tri is NULL");
+    if (!(d_prb > 0.0f)) return fail(APT_E_ARG, "d_prb must be > 0 (+inf: no probe limit)");
+    if (cloud->n > 0 && !d) return fail(APT_E_ARG, "d is NULL");
+    if (!status) return fail(APT_E_ARG, "status is NULL");
+    EdgeWs w = carve_edge(ws, cloud->n, n_tri);
+    if ((s = check_ws(ws, ws_bytes, w.bytes)) != APT_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    (void)hipGetLastError();
+    apt_cloud cl = *cloud;
+    cl.d_bnd = nullptr;
+    apt_query q{};
+    q.target = 254;                            // no targets: the ions are binned as neighbours only
+    q.neighbor = APT_ANY;
+    q.d_srf = 0.0f;
+    InitArgs ia{status, nullptr, 0, nullptr, 0, nullptr, w.plain.strag_count};
+    const apt_tuning tu = tuning();
+    PlanParams pp;
+    pp.h_min = tu.h_min_frac;                  // about 0.5 nm: the lanes of a wavefront stay close
+    pp.occ = tu.cell_occ;
+    pp.tile_occ = tu.tile_occ;
+    pp.k = 0;
+    pp.cell_cap = cell_cap_for(cl.n);
+    pp.tile_policy = 1;
+    pp.r_enum = 1.0f;
+    pp.h_shrink = 0.7f;
+    EdgeArgs a{};
+    a.plan = w.plain.plan;
+    a.bpos = w.plain.bpos;
+    a.tp = w.tp;
+    a.tri = tri;
+    a.n_tri = (uint32_t)n_tri;
+    a.d_prb = d_prb;
+    a.tc = w.tc;
+    a.tcell = w.tcell;
+    a.tcnt = w.tcnt;
+    a.tstart = w.tstart;
+    a.tblk = w.tblk;
+    a.torder = w.torder;
+    a.tsorted = w.tsorted;
+    a.d_out = d;
+    a.n = cl.n;
+    a.status = status;
+    {
+        TraceSpan span("binning", st);
+        if ((s = run_binning(&cl, q, pp, w.plain, status, st, nullptr, 0, &ia)) != APT_OK) return s;
+    }
+    const int gn = (int)std::min<int64_t>(std::max<int64_t>((cl.n + kBlock - 1) / kBlock, 1), 8192);
+    const int gt = (int)std::min<int64_t>(std::max<int64_t>((n_tri + kBlock - 1) / kBlock, 1), 4096);
+    {
+        TraceSpan span("edge", st);
+        hipLaunchKernelGGL(k_edge_zero, dim3(gn), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_edge_prep, dim3(gt), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_edge_plan, dim3(1), dim3(64), 0, st, a);
+        hipLaunchKernelGGL(k_edge_clear, dim3(1024), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_edge_count, dim3(gt), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_edge_scan_blocks, dim3(kTriScanBlocks), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_edge_scan_add, dim3(kTriScanBlocks), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_edge_fill, dim3(gt), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_edge_dist, dim3(gn), dim3(kBlock), 0, st, a);
+    }
+    return hip_check("edge distance launch");
 }
 
 // ------------------------------------------------ maximum separation --

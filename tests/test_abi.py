@@ -218,3 +218,25 @@ def test_cluster_argument_validation(aptstat):
     c = aptstat._Cloud(0x1000, 0x2000, None, 1 << 31)
     assert call(cloud=ctypes.byref(c)) == -3 and "2^31" in _err(aptstat)
     assert call(w=None) == -2 and call(wb=1024) == -2
+
+
+def test_edge_argument_validation(aptstat):
+    L = aptstat.lib()
+    ws = ctypes.c_void_p(0x100000)
+    big = 1 << 40
+    tri, d, st = (ctypes.c_void_p(a) for a in (0x3000, 0x4000, 0x5000))
+    a = L.apt_edge_workspace_size(1000, 100)
+    assert a > L.apt_workspace_size(aptstat.OP_RDF, 1000, 0, 0)
+    assert L.apt_edge_workspace_size(1000, 10_000_000) > a
+    assert L.apt_edge_workspace_size(-1, 1) == 0 and L.apt_edge_workspace_size(1, -1) == 0
+
+    def call(n_tri=100, t=tri, d_prb=2.5, out=d, status=st, w=ws, wb=big):
+        return L.apt_edge_distance(_cloud(aptstat), t, n_tri, d_prb, out, status, w, wb, None)
+
+    assert call(n_tri=-1) == -1
+    assert call(n_tri=1 << 32) == -3
+    assert call(t=None) == -1 and "tri" in _err(aptstat)
+    for bad in (0.0, -1.0, math.nan):
+        assert call(d_prb=bad) == -1 and "d_prb" in _err(aptstat)
+    assert call(out=None) == -1 and call(status=None) == -1
+    assert call(w=None) == -2 and call(wb=1024) == -2
