@@ -1493,7 +1493,10 @@ struct EdgeWs {
     PlainWs plain;
     TriPlan* tp;
     float4* tc;
-    uint32_t* tcell;
+    uint32_t piece_cap;
+    float4* pc;
+    uint32_t* ptri;
+    uint32_t* pcell;
     uint32_t* tcnt;
     uint32_t* tstart;
     uint32_t* tblk;
@@ -1502,19 +1505,26 @@ struct EdgeWs {
     size_t bytes;
 };
 
+// pieces the triangles may be cut into: four per triangle and a fixed reserve
+static uint32_t edge_piece_cap(int64_t n_tri) { return (uint32_t)std::min<int64_t>(4 * n_tri + 65536, 0xF0000000ll); }
+
 static EdgeWs carve_edge(void* base, int64_t n, int64_t n_tri) {
     EdgeWs w;
     w.plain = carve_plain(base, n);
     Carve c{reinterpret_cast<char*>(base), w.plain.bytes};
     const size_t T = (size_t)(n_tri > 0 ? n_tri : 1);
+    w.piece_cap = edge_piece_cap(n_tri);
+    const size_t PC = w.piece_cap;
     w.tp = c.take<TriPlan>(1);
     w.tc = c.take<float4>(T);
-    w.tcell = c.take<uint32_t>(T);
+    w.pc = c.take<float4>(PC);
+    w.ptri = c.take<uint32_t>(PC);
+    w.pcell = c.take<uint32_t>(PC);
     w.tcnt = c.take<uint32_t>(kTriCells);
     w.tstart = c.take<uint32_t>((size_t)kTriCells + 1);
     w.tblk = c.take<uint32_t>(kTriScanBlocks);
-    w.torder = c.take<uint32_t>(T);
-    w.tsorted = c.take<float4>(T);
+    w.torder = c.take<uint32_t>(PC);
+    w.tsorted = c.take<float4>(PC);
     w.bytes = c.off;
     return w;
 }
@@ -1562,8 +1572,11 @@ apt_status apt_edge_distance(const apt_cloud* cloud, const float* tri, int64_t n
     a.tri = tri;
     a.n_tri = (uint32_t)n_tri;
     a.d_prb = d_prb;
+    a.piece_cap = w.piece_cap;
     a.tc = w.tc;
-    a.tcell = w.tcell;
+    a.pc = w.pc;
+    a.ptri = w.ptri;
+    a.pcell = w.pcell;
     a.tcnt = w.tcnt;
     a.tstart = w.tstart;
     a.tblk = w.tblk;
@@ -1583,11 +1596,14 @@ apt_status apt_edge_distance(const apt_cloud* cloud, const float* tri, int64_t n
         hipLaunchKernelGGL(k_edge_zero, dim3(gn), dim3(kBlock), 0, st, a);
         hipLaunchKernelGGL(k_edge_prep, dim3(gt), dim3(kBlock), 0, st, a);
         hipLaunchKernelGGL(k_edge_plan, dim3(1), dim3(64), 0, st, a);
+        hipLaunchKernelGGL(k_edge_measure, dim3(gt), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_edge_plan_pieces, dim3(1), dim3(64), 0, st, a);
+        hipLaunchKernelGGL(k_edge_pieces, dim3(gt), dim3(kBlock), 0, st, a);
         hipLaunchKernelGGL(k_edge_clear, dim3(1024), dim3(kBlock), 0, st, a);
-        hipLaunchKernelGGL(k_edge_count, dim3(gt), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_edge_count, dim3(4096), dim3(kBlock), 0, st, a);
         hipLaunchKernelGGL(k_edge_scan_blocks, dim3(kTriScanBlocks), dim3(kBlock), 0, st, a);
         hipLaunchKernelGGL(k_edge_scan_add, dim3(kTriScanBlocks), dim3(kBlock), 0, st, a);
-        hipLaunchKernelGGL(k_edge_fill, dim3(gt), dim3(kBlock), 0, st, a);
+        hipLaunchKernelGGL(k_edge_fill, dim3(4096), dim3(kBlock), 0, st, a);
         hipLaunchKernelGGL(k_edge_dist, dim3(gn), dim3(kBlock), 0, st, a);
     }
     return hip_check("edge distance launch");

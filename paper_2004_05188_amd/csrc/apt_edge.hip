@@ -2,20 +2,24 @@
 // Supplementary: "Triangle filtering methods for ion-to-edge distancing").
 //
 // The paper filters the candidate triangles of each ion with a coarse
-// distance map and an R-tree.  Here the triangles are binned once by their
-// centroid into a uniform grid over the ions' bounding box (a triangle lies
-// within its radius r of its centroid, so one registration per triangle
-// suffices: a cell at Chebyshev ring q from an ion's cell holds only
-// triangles at least (q - 1) h - r_max away).  Ions are taken in the cell
-// order of the ions' own binning, one per lane, so that the lanes of a
-// wavefront search neighbouring cells.  Each lane walks the rings around its
-// cell, nearest first, and stops when the next ring cannot hold a triangle
-// closer than the best one found or the probe distance d_prb; inside a ring,
-// cells and then triangles whose FP32 lower bound already reaches that
-// distance are skipped.  The distance itself is FP64 on the stored FP32
-// values: the plane distance when the perpendicular's foot lies inside the
-// triangle (all three barycentric weights of the foot, in dot-product form,
-// non-negative), else the nearest of the three edges.
+// distance map and an R-tree.  Here every triangle is covered by pieces (the
+// m x m sub-triangles of a barycentric subdivision, m from the triangle's
+// size) that are binned once by their centroid into a uniform grid over the
+// ions' bounding box.  A piece lies within its radius of its centroid, so a
+// cell at Chebyshev ring q from an ion's cell holds only pieces at least
+// (q - 1) h - r_piece away, and the distance to a piece bounds the distance
+// to its triangle from above: the exact distance is always taken to the
+// whole triangle.  The pieces keep long slivers (a hull's cap fans) from
+// widening every ion's search.  Ions are taken in the cell order of their
+// own binning, one per lane, so that the lanes of a wavefront search
+// neighbouring cells.  Each lane walks the rings around its cell, nearest
+// first, and stops when the next ring cannot hold a piece closer than the
+// best distance found or the probe distance d_prb; slabs, rows, cells and
+// pieces whose FP32 lower bound already reaches that distance are skipped.
+// The distance itself is FP64 on the stored FP32 values: the plane distance
+// when the perpendicular's foot lies inside the triangle (all three
+// barycentric weights of the foot, in dot-product form, non-negative), else
+// the nearest of the three edges.
 #include "apt_edge.hpp"
 
 namespace apt {
@@ -27,14 +31,30 @@ __global__ __launch_bounds__(kBlock) void k_edge_zero(EdgeArgs a) {
         a.tp->rmax_bits = 0u;
         a.tp->n_valid = 0u;
         a.tp->r_sum = 0.0;
+        for (int j = 0; j < kPieceSizes; ++j) a.tp->pieces_at[j] = 0ull;
+        a.tp->piece_ctr = 0u;
+        a.tp->piece_rmax_bits = 0u;
+        a.tp->piece_cap = a.piece_cap;
     }
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock)
         a.d_out[i] = __builtin_nanf("");
 }
 
-// centroid and radius of every triangle (FP32; the radius is measured from
-// the stored centroid to the vertices and widened for its own rounding, so
-// the whole triangle lies within it: the triangle is the vertices' hull)
+// FP32 radius of the points q[0..2] about their centroid c, widened for its
+// own rounding (the triangle is the vertices' hull, so it lies within it)
+__device__ __forceinline__ float4 centroid_radius(const float* q) {
+    const float cx = ((q[0] + q[3]) + q[6]) / 3.0f;
+    const float cy = ((q[1] + q[4]) + q[7]) / 3.0f;
+    const float cz = ((q[2] + q[5]) + q[8]) / 3.0f;
+    float r2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float dx = q[3 * k] - cx, dy = q[3 * k + 1] - cy, dz = q[3 * k + 2] - cz;
+        r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
+    }
+    return make_float4(cx, cy, cz, sqrtf(r2) * 1.00001f + 1e-6f);
+}
+
 __global__ __launch_bounds__(kBlock) void k_edge_prep(EdgeArgs a) {
     uint32_t nv = 0;
     float rm = 0.0f;
@@ -53,20 +73,11 @@ __global__ __launch_bounds__(kBlock) void k_edge_prep(EdgeArgs a) {
             atomicOr(a.status, APT_STATUS_NONFINITE);
             continue;
         }
-        const float cx = ((v[0] + v[3]) + v[6]) / 3.0f;
-        const float cy = ((v[1] + v[4]) + v[7]) / 3.0f;
-        const float cz = ((v[2] + v[5]) + v[8]) / 3.0f;
-        float r2 = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const float dx = v[3 * k] - cx, dy = v[3 * k + 1] - cy, dz = v[3 * k + 2] - cz;
-            r2 = fmaxf(r2, dx * dx + dy * dy + dz * dz);
-        }
-        const float r = sqrtf(r2) * 1.00001f + 1e-6f;
-        a.tc[t] = make_float4(cx, cy, cz, r);
+        const float4 c = centroid_radius(v);
+        a.tc[t] = c;
         ++nv;
-        rm = fmaxf(rm, r);
-        rs += (double)r;
+        rm = fmaxf(rm, c.w);
+        rs += (double)c.w;
     }
     nv = wave_sum(nv);
 #pragma unroll
@@ -115,10 +126,116 @@ __global__ void k_edge_plan(EdgeArgs a) {
     T.n_cells = nc;
     T.h = (float)h;
     T.inv_h = (float)(1.0 / h);
-    // cell indices and centroids are FP32: a point may land one rounding
-    // away from its true cell, a centroid one rounding away from the exact
-    T.slack = (float)(4e-6 * (amax + h) + 1e-6);
+    T.rho = (float)(0.5 * h);
+    // cell indices, centroids and piece vertices are FP32: each may sit a
+    // few roundings away from the exact value
+    T.slack = (float)(1e-5 * (amax + h) + 1e-6);
     T.prb2 = isfinite(a.d_prb) ? (double)a.d_prb * (double)a.d_prb : INFINITY;
+}
+
+__device__ __forceinline__ float piece_rho(const TriPlan& T, int j) {
+    return j < kPieceSizes - 1 ? T.rho * (float)(1u << j) : T.r_max;
+}
+__device__ __forceinline__ uint32_t pieces_per_side(float r, float rho) {
+    const float m = ceilf(r / rho);
+    return m < 1.0f ? 1u : (m > 4096.0f ? 4096u : (uint32_t)m);
+}
+
+// pieces the triangles would take for each candidate piece radius
+__global__ __launch_bounds__(kBlock) void k_edge_measure(EdgeArgs a) {
+    const TriPlan T = *a.tp;
+    unsigned long long acc[kPieceSizes];
+#pragma unroll
+    for (int j = 0; j < kPieceSizes; ++j) acc[j] = 0ull;
+    for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < a.n_tri; t += gridDim.x * kBlock) {
+        const float r = a.tc[t].w;
+        if (r < 0.0f) continue;
+#pragma unroll
+        for (int j = 0; j < kPieceSizes; ++j) {
+            const unsigned long long m = pieces_per_side(r, piece_rho(T, j));
+            acc[j] += m * m;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kPieceSizes; ++j) {
+        unsigned long long v = acc[j];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, d, kWave);
+            const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), d, kWave);
+            v += ((unsigned long long)hi << 32) | lo;
+        }
+        if (lane_id() == 0 && v) atomicAdd(&a.tp->pieces_at[j], v);
+    }
+}
+
+// the smallest piece radius whose pieces fit the workspace (the last
+// candidate, one piece per triangle, always does)
+__global__ void k_edge_plan_pieces(EdgeArgs a) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    TriPlan& T = *a.tp;
+    int j = 0;
+    while (j < kPieceSizes - 1 && T.pieces_at[j] > (unsigned long long)T.piece_cap) ++j;
+    T.rho = piece_rho(T, j);
+    T.n_pieces = (uint32_t)T.pieces_at[j];
+}
+
+// grid point (i, k) of the m x m subdivision: a + (i/m)(b - a) + (k/m)(c - a)
+__device__ __forceinline__ void sub_point(const float* v, uint32_t i, uint32_t k, float inv_m, float* q) {
+    const float u = (float)i * inv_m, w = (float)k * inv_m;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q[c] = v[c] + u * (v[3 + c] - v[c]) + w * (v[6 + c] - v[c]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_edge_pieces(EdgeArgs a) {
+    const TriPlan T = *a.tp;
+    float rmax = 0.0f;
+    for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < a.n_tri; t += gridDim.x * kBlock) {
+        const float4 tc = a.tc[t];
+        if (tc.w < 0.0f) continue;
+        const uint32_t m = pieces_per_side(tc.w, T.rho);
+        const uint32_t base = atomicAdd(&a.tp->piece_ctr, m * m);
+        if (m == 1u) {
+            a.pc[base] = tc;
+            a.ptri[base] = t;
+            rmax = fmaxf(rmax, tc.w);
+            continue;
+        }
+        float v[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) v[k] = a.tri[9 * (size_t)t + k];
+        const float inv_m = 1.0f / (float)m;
+        uint32_t out = base;
+        // rows of the subdivision: m - r upward and m - r - 1 downward pieces
+        for (uint32_t r = 0; r < m; ++r) {
+            for (uint32_t i = 0; i + r < m; ++i) {
+                float q[9];
+                sub_point(v, i, r, inv_m, q);
+                sub_point(v, i + 1, r, inv_m, q + 3);
+                sub_point(v, i, r + 1, inv_m, q + 6);
+                float4 c = centroid_radius(q);
+                c.w += T.slack;
+                a.pc[out] = c;
+                a.ptri[out] = t;
+                rmax = fmaxf(rmax, c.w);
+                ++out;
+                if (i + r + 1 < m) {
+                    sub_point(v, i + 1, r, inv_m, q);
+                    sub_point(v, i + 1, r + 1, inv_m, q + 3);
+                    sub_point(v, i, r + 1, inv_m, q + 6);
+                    c = centroid_radius(q);
+                    c.w += T.slack;
+                    a.pc[out] = c;
+                    a.ptri[out] = t;
+                    rmax = fmaxf(rmax, c.w);
+                    ++out;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, d, kWave));
+    if (lane_id() == 0 && rmax > 0.0f) atomicMax(&a.tp->piece_rmax_bits, __float_as_uint(rmax));
 }
 
 __global__ __launch_bounds__(kBlock) void k_edge_clear(EdgeArgs a) {
@@ -135,12 +252,11 @@ __device__ __forceinline__ int edge_axis(const TriPlan& T, int c, float x) {
 
 __global__ __launch_bounds__(kBlock) void k_edge_count(EdgeArgs a) {
     const TriPlan T = *a.tp;
-    for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < a.n_tri; t += gridDim.x * kBlock) {
-        const float4 c = a.tc[t];
-        if (c.w < 0.0f) continue;
+    for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < T.n_pieces; p += gridDim.x * kBlock) {
+        const float4 c = a.pc[p];
         const uint32_t cell = ((uint32_t)edge_axis(T, 2, c.z) * (uint32_t)T.dim[1] + (uint32_t)edge_axis(T, 1, c.y)) *
                                   (uint32_t)T.dim[0] + (uint32_t)edge_axis(T, 0, c.x);
-        a.tcell[t] = cell;
+        a.pcell[p] = cell;
         atomicAdd(a.tcnt + cell, 1u);
     }
 }
@@ -194,13 +310,12 @@ __global__ __launch_bounds__(kBlock) void k_edge_scan_add(EdgeArgs a) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_edge_fill(EdgeArgs a) {
-    for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < a.n_tri; t += gridDim.x * kBlock) {
-        const float4 c = a.tc[t];
-        if (c.w < 0.0f) continue;
-        const uint32_t cell = a.tcell[t];
+    const uint32_t np = a.tp->n_pieces;
+    for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < np; p += gridDim.x * kBlock) {
+        const uint32_t cell = a.pcell[p];
         const uint32_t pos = a.tstart[cell] + atomicSub(a.tcnt + cell, 1u) - 1u;
-        a.torder[pos] = t;
-        a.tsorted[pos] = c;
+        a.torder[pos] = a.ptri[p];
+        a.tsorted[pos] = a.pc[p];
     }
 }
 
@@ -246,20 +361,16 @@ __device__ __forceinline__ double tri_dist2(double px, double py, double pz, con
     return d;
 }
 
-// FP32 lower bound (nm) of the distance from p to the box of cell (x, y, z)
-__device__ __forceinline__ float cell_gap(const TriPlan& T, float px, float py, float pz, int x, int y, int z) {
-    auto gap = [&](int c, float p, int m) {
-        const float l = T.lo[c] + (float)m * T.h, u = l + T.h;
-        return fmaxf(fmaxf(l - p, p - u), 0.0f);
-    };
-    const float gx = gap(0, px, x), gy = gap(1, py, y), gz = gap(2, pz, z);
-    return sqrtf(gx * gx + gy * gy + gz * gz);
+// FP32 gap (nm) between a coordinate and cell m's interval on axis c
+__device__ __forceinline__ float axis_gap(const TriPlan& T, int c, float p, int m) {
+    const float l = T.lo[c] + (float)m * T.h, u = l + T.h;
+    return fmaxf(fmaxf(l - p, p - u), 0.0f);
 }
 
 __global__ __launch_bounds__(kBlock) void k_edge_dist(EdgeArgs a) {
     const GridPlan P = *a.plan;
     const TriPlan T = *a.tp;
-    const float skip = T.r_max + T.slack;        // a cell's triangles reach this far out of it
+    const float skip = __uint_as_float(T.piece_rmax_bits) + T.slack;   // a cell's pieces reach this far out
     for (uint32_t p = blockIdx.x * kBlock + threadIdx.x; p < P.nB; p += gridDim.x * kBlock) {
         const float4 r = a.bpos[p];
         const uint32_t idx = __builtin_bit_cast(uint32_t, r.w);
@@ -268,27 +379,36 @@ __global__ __launch_bounds__(kBlock) void k_edge_dist(EdgeArgs a) {
             continue;
         }
         double best2 = T.prb2;
-        if (T.n_valid > 0) {
+        // a gap g (FP32, nm) is beyond reach when g - skip >= the best distance
+        auto beyond = [&](float g) {
+            const float s = g * 0.99999f - skip;
+            return s > 0.0f && (double)s * (double)s >= best2;
+        };
+        if (T.n_pieces > 0) {
             const double px = r.x, py = r.y, pz = r.z;
             const int cx = edge_axis(T, 0, r.x), cy = edge_axis(T, 1, r.y), cz = edge_axis(T, 2, r.z);
             for (int q = 0;; ++q) {
-                const float lb = (float)(q - 1) * T.h - skip;
-                if (lb > 0.0f && (double)lb * (double)lb >= best2) break;
+                if (beyond((float)(q - 1) * T.h)) break;
                 if (cx - q < 0 && cy - q < 0 && cz - q < 0 && cx + q >= T.dim[0] && cy + q >= T.dim[1] &&
                     cz + q >= T.dim[2])
                     break;                           // every cell has been visited
                 for (int dz = -q; dz <= q; ++dz) {
                     const int z = cz + dz;
                     if (z < 0 || z >= T.dim[2]) continue;
+                    const float gz = axis_gap(T, 2, r.z, z);
+                    if (beyond(gz)) continue;
                     for (int dy = -q; dy <= q; ++dy) {
                         const int y = cy + dy;
                         if (y < 0 || y >= T.dim[1]) continue;
+                        const float gy = axis_gap(T, 1, r.y, y);
+                        const float gyz = sqrtf(gy * gy + gz * gz);
+                        if (beyond(gyz)) continue;
                         const bool full = q == 0 || dz == -q || dz == q || dy == -q || dy == q;
                         const int step = full ? 1 : 2 * q;
                         for (int x = cx - q; x <= cx + q; x += step) {
                             if (x < 0 || x >= T.dim[0]) continue;
-                            const float g = cell_gap(T, r.x, r.y, r.z, x, y, z) - skip;
-                            if (g > 0.0f && (double)g * (double)g >= best2) continue;
+                            const float gx = axis_gap(T, 0, r.x, x);
+                            if (beyond(sqrtf(gx * gx + gyz * gyz))) continue;
                             const uint32_t cell = ((uint32_t)z * (uint32_t)T.dim[1] + (uint32_t)y) *
                                                       (uint32_t)T.dim[0] + (uint32_t)x;
                             const uint32_t k1 = a.tstart[cell + 1];
