@@ -572,6 +572,8 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     pa.bpos = w.bpos;
     pa.cell_start = w.cell_start;
     pa.self_possible = q.target == APT_ANY || q.neighbor == APT_ANY || q.target == q.neighbor;
+    pa.lab = cl->lab;
+    pa.nbr_species = q.neighbor;
     int n_bins = 1;
     bool in_lds = false;
     if (do_rdf) {
@@ -625,8 +627,10 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
         const bool self = pa.self_possible != 0;
         const size_t nl = nbr_lds_bytes(n_bins, in_lds);
         auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(resident_grid(kern, nl)), dim3(kBlock), nl, st, pa); };
-        if (in_lds) self ? go(k_rdf_nbr<kRdfLds | kSelf>) : go(k_rdf_nbr<kRdfLds>);
-        else self ? go(k_rdf_nbr<kRdfGlobal | kSelf>) : go(k_rdf_nbr<kRdfGlobal>);
+        if (self)
+            hipLaunchKernelGGL(k_nbr_self, dim3(std::max(1, device_info().cus * 2)), dim3(kBlock), 0, st, pa);
+        if (in_lds) go(k_rdf_nbr<kRdfLds>);
+        else go(k_rdf_nbr<kRdfGlobal>);
         if (tu.rdf_kernel == 2) {
             // (the tuning asks for the one-target-per-wavefront RDF in mode 3)
             const size_t tl = pair_lds_bytes(true, false, n_bins, in_lds);

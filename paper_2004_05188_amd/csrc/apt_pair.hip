@@ -396,7 +396,6 @@ template <int FLAGS>
 __global__ __launch_bounds__(kBlock, 8) void k_rdf_nbr(PairArgs a) {
     constexpr bool COUNT = (FLAGS & kCountEvals) != 0;
     constexpr bool LDS_HIST = !COUNT && (FLAGS & kRdfLds) != 0;
-    constexpr bool SELF = (FLAGS & kSelf) != 0;
     const GridPlan P = *a.plan;
     if (P.tile_mode != 3 || !P.rdf_nbr) return;
     unsigned long long evals = 0;   // COUNT: pair evaluations (records x staged targets)
@@ -433,7 +432,6 @@ __global__ __launch_bounds__(kBlock, 8) void k_rdf_nbr(PairArgs a) {
         const bool valid = j < nB;
         const float4 rec = a.bpos[valid ? j : nB - 1];
         const bool fin0 = valid && isfinite(rec.x) && isfinite(rec.y) && isfinite(rec.z);
-        const uint32_t rid = __builtin_bit_cast(uint32_t, rec.w);
         // a run of 64 records may end one cell row and start the next, far
         // apart in x: each row's part is evaluated with its own bounding box
         const uint32_t crow = fin0 ? (uint32_t)cell_axis(P, 2, rec.z) * (uint32_t)P.dim[1] +
@@ -464,16 +462,14 @@ __global__ __launch_bounds__(kBlock, 8) void k_rdf_nbr(PairArgs a) {
                     return;
                 }
                 wave_sync();
-                float4 Tn = list[0];
+#pragma unroll 4
                 for (int t = 0; t < cnt; ++t) {
-                    // the next target's LDS read is in flight during this one
-                    const float4 T = Tn;
-                    if (t + 1 < cnt) Tn = list[t + 1];
+                    const float4 T = list[t];
                     const float dx = rec.x - T.x, dy = rec.y - T.y, dz = rec.z - T.z;
                     const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    bool ok = fin && d2 < thr2;
-                    if (SELF) ok = ok && rid != __builtin_bit_cast(uint32_t, T.w);
-                    if (ok) {
+                    // (a target's pair with its own record lands in bin 0
+                    // here and is taken off by k_nbr_self)
+                    if (fin && d2 < thr2) {
                         const float tt = __builtin_amdgcn_sqrtf(d2) * inv_w;
                         int b = (int)tt;
                         if (LDS_HIST) {
@@ -561,9 +557,21 @@ __global__ __launch_bounds__(kBlock, 8) void k_rdf_nbr(PairArgs a) {
 }
 
 template __global__ void k_rdf_nbr<kRdfLds>(PairArgs);
-template __global__ void k_rdf_nbr<kRdfLds | kSelf>(PairArgs);
 template __global__ void k_rdf_nbr<kRdfGlobal>(PairArgs);
-template __global__ void k_rdf_nbr<kRdfGlobal | kSelf>(PairArgs);
+
+__global__ __launch_bounds__(kBlock) void k_nbr_self(PairArgs a) {
+    const GridPlan P = *a.plan;
+    if (P.tile_mode != 3 || !P.rdf_nbr) return;
+    uint32_t cnt = 0;
+    for (uint32_t q = blockIdx.x * kBlock + threadIdx.x; q < P.nT; q += gridDim.x * kBlock) {
+        if (!(isfinite(a.tx[q]) && isfinite(a.ty[q]) && isfinite(a.tz[q]))) continue;
+        if (a.nbr_species == APT_ANY || (int)a.lab[a.t_id[q]] == a.nbr_species) ++cnt;
+    }
+    cnt = wave_sum(cnt);
+    // (u64 arithmetic modulo 2^64: the order of this and the kernel's adds
+    // does not matter)
+    if (lane_id() == 0 && cnt) atomicAdd((unsigned long long*)a.hist, 0ull - (unsigned long long)cnt);
+}
 template __global__ void k_rdf_nbr<kRdfGlobal | kCountEvals>(PairArgs);
 
 #define APT_TILE_INST(F, K) template __global__ void k_pair_tile<F, K>(PairArgs);

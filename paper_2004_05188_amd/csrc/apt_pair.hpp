@@ -17,6 +17,8 @@ struct PairArgs {
     const float4* bpos;          // [nB] neighbours in cell order: x, y, z, ion index (bits)
     const uint32_t* cell_start;  // [n_cells + 1]
     int32_t self_possible;       // a target may also be a neighbour
+    const uint8_t* lab;          // [n] species labels
+    int32_t nbr_species;         // species of the neighbours (or APT_ANY)
     // RDF
     int32_t n_bins;
     float r_enum;                // enumeration radius covering every counted pair
@@ -74,6 +76,12 @@ size_t tile_lds_bytes(bool rdf, int n_bins);
 // chose mode 3.
 template <int FLAGS>
 __global__ void k_rdf_nbr(PairArgs a);
+// With targets that may be neighbours the neighbour-major kernel also counts
+// each such target against its own record (distance 0, bin 0) instead of
+// testing identities per pair: this kernel takes those counts off bin 0
+// (every target with a finite position whose species is a neighbour's).
+// Exits unless the plan chose mode 3 with the neighbour-major RDF.
+__global__ void k_nbr_self(PairArgs a);
 // Mode 3 with the RDF one target per wavefront (tuning rdf_kernel 2): RDF
 // of every target, eight wavefronts per SIMD; exits otherwise.
 template <int FLAGS>
