@@ -517,6 +517,7 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
                 knn_hist ? kb->n_bins + 1 : 0, n_targets, w.strag_count,
                 do_rdf ? w.E2 : nullptr, do_rdf ? rb->r_max : 0.0f, do_rdf ? rb->n_bins : 0,
                 knn_hist ? w.KE2 : nullptr, knn_hist ? kb->r_max : 0.0f, knn_hist ? kb->n_bins : 0};
+    ia.work_q = w.strag_count + 8;
     // (zeroed and filled by the binning's first kernel)
 
     const apt_tuning tu = tuning();
@@ -551,6 +552,7 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
             ca.t_id = w.t_id;
             ca.bpos = w.bpos;
             ca.t_cell_start = w.t_cell_start;
+            ca.work_q = w.strag_count + 8;
             ca.r_enum = (float)((double)rb->r_max * (1.0 + 4e-5));
             ca.hist = cand;
             ca.n_bins = 1;
@@ -616,6 +618,7 @@ static apt_status run_plain(const apt_cloud* cl, apt_query q, const apt_bins* rb
     pa.strag = w.strag;
     pa.strag_count = w.strag_count;
     pa.t_cell_start = w.t_cell_start;
+    pa.work_q = w.strag_count + 8;
     // the kNN radii from the occupied cells that the binning counted
     pa.occ = do_knn ? w.strag_count + 1 : nullptr;
     pa.n_targets = do_knn ? n_targets : nullptr;

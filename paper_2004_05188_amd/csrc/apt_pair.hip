@@ -412,14 +412,15 @@ __global__ __launch_bounds__(kBlock, 8) void k_rdf_nbr(PairArgs a) {
 
     const uint32_t nB = P.nB;
     const uint32_t n_chunks = (nB + kWave - 1) / kWave;
-    // XCD-aware deal over chunks (cell order): each XCD's L2 serves one
-    // region of space (the grid is a multiple of kXcd workgroups)
+    // XCD-aware work queue over chunks (cell order): each XCD takes one
+    // eighth of the chunks, and its wavefronts take batches of consecutive
+    // chunks from the XCD's counter, so that the chunks in flight on an XCD
+    // stay one compact region whose target rows its L2 keeps (a static deal
+    // lets the wavefronts drift apart).  (workgroup b runs on XCD b mod 8)
     const int xcd = blockIdx.x % kXcd;
-    const int per_xcd = gridDim.x / kXcd;
-    const uint32_t wx = (uint32_t)(blockIdx.x / kXcd) * kWavesPerBlock + (uint32_t)w;
-    const uint32_t wstride = (uint32_t)per_xcd * kWavesPerBlock;
     const uint32_t c0 = (uint32_t)((uint64_t)n_chunks * (uint64_t)xcd / kXcd);
     const uint32_t c1 = (uint32_t)((uint64_t)n_chunks * (uint64_t)(xcd + 1) / kXcd);
+    constexpr uint32_t kBatch = 16;
     const float Re = a.r_enum + P.eps;
     const float R2 = Re * Re;
     const float thr2 = a.thr2, inv_w = a.inv_w, lo_b = a.delta_b, hi_b = 1.0f - a.delta_b;
@@ -427,7 +428,13 @@ __global__ __launch_bounds__(kBlock, 8) void k_rdf_nbr(PairArgs a) {
     uint32_t since_flush = 0;
     const uint32_t flush_at = 0xFFFFFFFFu - (uint32_t)(kWave * kNbrList);
 
-    for (uint32_t c = c0 + wx; c < c1; c += wstride) {
+    for (;;) {
+    uint32_t cb = 0;
+    if (l == 0) cb = atomicAdd(a.work_q + xcd, kBatch);
+    cb = c0 + (uint32_t)__shfl((int)cb, 0, kWave);
+    if (cb >= c1) break;
+    const uint32_t ce = cb + kBatch < c1 ? cb + kBatch : c1;
+    for (uint32_t c = cb; c < ce; ++c) {
         const uint32_t j = c * (uint32_t)kWave + (uint32_t)l;
         const bool valid = j < nB;
         const float4 rec = a.bpos[valid ? j : nB - 1];
@@ -526,13 +533,11 @@ __global__ __launch_bounds__(kBlock, 8) void k_rdf_nbr(PairArgs a) {
                     const uint32_t base = (uint32_t)__shfl((int)(st - offr), row, kWave);
                     bool keep = v < tot;
                     float tx = 0.0f, ty = 0.0f, tz = 0.0f;
-                    uint32_t ti = 0;
                     if (keep) {
                         const uint32_t q = base + v;
                         tx = a.tx[q];
                         ty = a.ty[q];
                         tz = a.tz[q];
-                        ti = a.t_id[q];
                         // exact cull against the records' box (a pair within
                         // r_max lies within r_max of the box)
                         const float ex = fmaxf(0.0f, fmaxf(x0 - tx, tx - x1));
@@ -541,7 +546,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_rdf_nbr(PairArgs a) {
                         keep = isfinite(tx) && isfinite(ty) && isfinite(tz) && ex * ex + ey * ey + ez * ez <= R2;
                     }
                     const uint64_t m = __ballot(keep);
-                    if (keep) list[cnt + __popcll(m & lanemask_lt())] = make_float4(tx, ty, tz, __builtin_bit_cast(float, ti));
+                    if (keep) list[cnt + __popcll(m & lanemask_lt())] = make_float4(tx, ty, tz, 0.0f);
                     cnt += __popcll(m);
                     if (cnt > kNbrList - kWave) {
                         run(cnt);
@@ -551,6 +556,7 @@ __global__ __launch_bounds__(kBlock, 8) void k_rdf_nbr(PairArgs a) {
             }
             if (cnt > 0) run(cnt);
         }
+    }
     }
     if (LDS_HIST) flush_hist(hist_l, a.hist, a.n_bins);
     if (COUNT && l == 0 && evals) atomicAdd((unsigned long long*)a.hist, evals);
