@@ -21,7 +21,7 @@ struct InitArgs {
     double* ke2;
     float ke2_rmax;
     int32_t ke2_nbins;
-    uint32_t* work_q = nullptr;   // [kXcd] work counters of the neighbour-major RDF, or NULL
+    uint32_t* work_q = nullptr;   // [2 kXcd] per-XCD work counters of the pair kernels, or NULL
 };
 
 __device__ inline void fill_edges(double* E2, float r_max, int n_bins, int t, int stride);
@@ -36,7 +36,7 @@ __device__ inline void init_body(const InitArgs& a, int t, int st) {
         if (a.counter)
             for (int c = 0; c < 4; ++c) a.counter[c] = 0;
         if (a.work_q)
-            for (int c = 0; c < kXcd; ++c) a.work_q[c] = 0;
+            for (int c = 0; c < 2 * kXcd; ++c) a.work_q[c] = 0;
     }
     if (a.h1)
         for (int b = t; b < a.n1; b += st) a.h1[b] = 0;

@@ -291,16 +291,23 @@ __global__ __launch_bounds__(kBlock, 4) void k_pair_tile(PairArgs a) {
     wave_sync();
     const float Rk = KMAX > 0 ? fminf(P.rk_tile, a.rknn) : 0.0f;
 
+    // XCD-aware work queue over tiles (cell order): each XCD takes one
+    // eighth of them, its wavefronts take batches of consecutive tiles from
+    // the XCD's counter, so the tiles in flight stay one compact region
     const uint32_t n_tiles = (P.nT + kWave - 1) / kWave;
     const int xcd = blockIdx.x % kXcd;
-    const int per_xcd = gridDim.x / kXcd;
-    const uint32_t wx = (uint32_t)(blockIdx.x / kXcd) * kWavesPerBlock + (uint32_t)w;
-    const uint32_t wstride = (uint32_t)per_xcd * kWavesPerBlock;
     const uint32_t g0 = (uint32_t)((uint64_t)n_tiles * (uint64_t)xcd / kXcd);
     const uint32_t g1 = (uint32_t)((uint64_t)n_tiles * (uint64_t)(xcd + 1) / kXcd);
+    constexpr uint32_t kBatch = 4;
     uint32_t since_flush = 0;
     const uint32_t flush_at = P.nB >= 0x7FFFFFFFu / kWave ? 0u : 0xFFFFFFFFu - P.nB * kWave;
-    for (uint32_t g = g0 + wx; g < g1; g += wstride) {
+    for (;;) {
+    uint32_t gb = 0;
+    if (l == 0) gb = atomicAdd(a.work_q + kXcd + xcd, kBatch);
+    gb = g0 + (uint32_t)__shfl((int)gb, 0, kWave);
+    if (gb >= g1) break;
+    const uint32_t ge = gb + kBatch < g1 ? gb + kBatch : g1;
+    for (uint32_t g = gb; g < ge; ++g) {
         const uint32_t slot = g * kWave + (uint32_t)l;
         const bool valid = slot < P.nT;
         uint32_t rank = 0, i = 0;
@@ -367,6 +374,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_pair_tile(PairArgs a) {
                 since_flush = 0;
             }
         }
+    }
     }
     if (LDS_HIST) flush_hist(T.hist_l, a.hist, a.n_bins);
 }

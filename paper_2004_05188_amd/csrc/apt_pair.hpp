@@ -46,7 +46,8 @@ struct PairArgs {
     uint32_t* strag_count;       // [1], zeroed before the tile pass
     const uint32_t* occ;         // [2] occupied-cell counts for refine_radii, or NULL
     const uint32_t* t_cell_start;  // [n_cells + 1] targets per cell (mode 3: plain cell order)
-    uint32_t* work_q;            // [kXcd] per-XCD chunk counters of k_rdf_nbr, zeroed by the call's init
+    uint32_t* work_q;            // [2 kXcd] per-XCD counters: chunks of k_rdf_nbr, then tiles of
+                                 // k_pair_tile; zeroed by the call's init
     // written once per call by k_pair (workgroup 0): the eligible target
     // count, and APT_STATUS_CAPACITY when k > 0 and it exceeds capacity
     int64_t* n_targets;
