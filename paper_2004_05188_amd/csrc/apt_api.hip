@@ -188,8 +188,8 @@ struct PlainWs {
     uint32_t* bsel;
     uint32_t* K[2];         // target sort keys and values (ping-pong)
     uint32_t* V[2];
-    uint32_t* KB[2];        // neighbour sort keys and values (ping-pong)
-    uint32_t* VB[2];
+    uint32_t* KB[2];        // neighbour sort keys (ping-pong)
+    float4* brec2;          // the neighbour records' second buffer (the first is bpos)
     uint32_t* t_rank;
     uint32_t* t_id;
     float* tx;
@@ -225,9 +225,8 @@ static PlainWs carve_plain(void* base, int64_t n) {
     w.K[1] = c.take<uint32_t>(N);
     w.V[1] = c.take<uint32_t>(N);
     w.KB[0] = c.take<uint32_t>(N);
-    w.VB[0] = c.take<uint32_t>(N);
     w.KB[1] = c.take<uint32_t>(N);
-    w.VB[1] = c.take<uint32_t>(N);
+    w.brec2 = c.take<float4>(N);
     w.t_rank = c.take<uint32_t>(N);
     w.t_id = c.take<uint32_t>(N);
     w.tx = c.take<float>(N);
@@ -443,7 +442,7 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
     // the compaction writes both key lists (the plan is known by then)
     CompactArgs cm{cl->lab, cl->d_bnd, n, chunk, q.target, q.neighbor, q.d_srf, w.part_off, w.tid,
                    all_b ? nullptr : w.bsel, sel_union, w.plan, cl->xyz, zscale, w.K[0], w.V[0], w.KB[0],
-                   w.VB[0]};
+                   {w.bpos, w.brec2}};
     hipLaunchKernelGGL(k_compact, dim3(G), dim3(kBlock), 0, st, cm);
 
     // both sorts share each pass's launches; target keys never need more
@@ -458,8 +457,10 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
     for (int p = 0; p < passes; ++p) {
         SortSet ss{};
         ss.s[0] = SortArgs{w.plan, 1, p, GsT, {w.K[0], w.K[1]}, {w.V[0], w.V[1]}, w.rs_counts, w.rs_totals};
-        ss.s[1] = SortArgs{w.plan, 0, p, Gs, {w.KB[0], w.KB[1]}, {w.VB[0], w.VB[1]},
-                           w.rs_counts + (size_t)256 * kSortBlocks, w.rs_totals + 256};
+        // the neighbours' 16-byte records travel with their keys: no random
+        // position reads after the sort
+        ss.s[1] = SortArgs{w.plan, 0, p, Gs, {w.KB[0], w.KB[1]}, {nullptr, nullptr},
+                           w.rs_counts + (size_t)256 * kSortBlocks, w.rs_totals + 256, {w.bpos, w.brec2}};
         ss.n = 2;
         const int grid = GsT + Gs;
         hipLaunchKernelGGL(k_rs_upsweep, dim3(grid), dim3(kBlock), 0, st, ss);
@@ -471,7 +472,7 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
     const bool occ = pp.k > 0 && !zscale;
     OrderArgs oa{w.plan, cl->xyz, w.tid, {w.V[0], w.V[1]}, w.t_rank, w.t_id, w.tx, w.ty, w.tz,
                  {w.K[0], w.K[1]}, occ ? w.strag_count + 1 : nullptr, w.t_cell_start};
-    GatherArgs ga{w.plan, cl->xyz, zscale, {w.KB[0], w.KB[1]}, {w.VB[0], w.VB[1]}, w.bpos, w.cell_start,
+    GatherArgs ga{w.plan, nullptr, zscale, {w.KB[0], w.KB[1]}, {nullptr, nullptr}, w.bpos, w.cell_start,
                   occ ? w.strag_count + 2 : nullptr};
     // (up to 2^25 ions half the usual grid per half: more records per thread
     // beat more workgroups, −2 % on 7.5e6 records; beyond, the full grid:

@@ -361,9 +361,10 @@ __device__ __forceinline__ void compact_keys(const CompactArgs& a, uint32_t t0, 
         a.tkeys[j] = target_key(P, x, y, z);
         a.tvals[j] = j;
     });
+    float4* __restrict__ brec = rec_after(a.brec[0], a.brec[1], (int)P.passes, -1);
     auto bkey = [&](uint32_t j, uint32_t id, float x, float y, float z) {
         a.bkeys[j] = cell_id(P, x, y, z);
-        a.bvals[j] = id;
+        brec[j] = make_float4(x, y, z, __builtin_bit_cast(float, id));
     };
     if (a.bsel) run(a.bsel, b0, b1, bkey);
     else run(nullptr, i0, i1, bkey);   // neighbours = every ion, in index order
@@ -452,8 +453,8 @@ __global__ __launch_bounds__(kBlock) void k_keys(KeyArgs a) {
 //    inside each wavefront with ballots, then placed through LDS so that
 //    the global writes of one digit are contiguous.
 // ------------------------------------------------------------------------
-constexpr int kRsItems = 16;
-constexpr int kRsTile = kBlock * kRsItems;   // 4096
+constexpr int kRsItems = 8;
+constexpr int kRsTile = kBlock * kRsItems;   // 2048
 constexpr int kRadix = 256;
 constexpr int kRsUp = 8;                     // keys per thread in flight in the upsweep
 constexpr int kGatherItems = 4;              // random position reads per thread in flight
@@ -481,6 +482,8 @@ __device__ __forceinline__ SortArgs sort_of(const SortSet& set, int q) {
     a.vals[1] = q ? s1.vals[1] : s0.vals[1];
     a.counts = q ? s1.counts : s0.counts;
     a.totals = q ? s1.totals : s0.totals;
+    a.rec[0] = q ? s1.rec[0] : s0.rec[0];
+    a.rec[1] = q ? s1.rec[1] : s0.rec[1];
     return a;
 }
 
@@ -570,71 +573,51 @@ __global__ __launch_bounds__(kBlock) void k_rs_scan(SortSet set) {
     if (t == kBlock - 1) a.totals[d] = run;
 }
 
-__global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortSet set) {
-    // sort 0 takes the first s[0].G workgroups, sort 1 the next s[1].G
-    const uint32_t g0 = (uint32_t)set.s[0].G;
-    const int q = blockIdx.x < g0 ? 0 : 1;
-    if (q >= set.n) return;
-    const SortArgs a = sort_of(set, q);
-    const uint32_t bid = blockIdx.x - (q ? g0 : 0u);
-    if (bid >= (uint32_t)a.G) return;
-    const GridPlan P = *a.plan;
-    if (!rs_active(P, a)) return;
-    const uint32_t n = a.count_is_T ? P.nT : P.nB;
-    const uint32_t* __restrict__ kin = pick2(a.keys[0], a.keys[1], (uint32_t)a.pass);
-    const uint32_t* __restrict__ vin = pick2(a.vals[0], a.vals[1], (uint32_t)a.pass);
-    uint32_t* __restrict__ kout = pick2(a.keys[0], a.keys[1], (uint32_t)a.pass + 1u);
-    uint32_t* __restrict__ vout = pick2(a.vals[0], a.vals[1], (uint32_t)a.pass + 1u);
-    const uint32_t shift = 8u * (uint32_t)a.pass;
+// LDS of one downsweep workgroup
+struct DownLds {
+    uint32_t key[kRsTile];
+    float4 pay[kRsTile];                 // values (as u32) or records
+    uint32_t wcnt[kWavesPerBlock][kRadix];
+    uint32_t lstart[kRadix];
+    uint32_t tot[kRadix];
+    uint32_t run[kRadix];
+    uint32_t tmp[16];
+};
 
-    __shared__ uint32_t s_key[kRsTile];
-    __shared__ uint32_t s_val[kRsTile];
-    __shared__ uint32_t s_wcnt[kWavesPerBlock][kRadix];
-    __shared__ uint32_t s_lstart[kRadix];
-    __shared__ uint32_t s_tot[kRadix];
-    __shared__ uint32_t s_run[kRadix];
-    __shared__ uint32_t s_tmp[16];
-
-    uint32_t chunk;
-    rs_chunk(n, a.G, &chunk);
-    const uint64_t beg = (uint64_t)bid * chunk;
-    uint64_t end = beg + chunk;
-    if (end > n) end = n;
+// One workgroup's tiles: keys ranked by digit with ballots per wavefront,
+// placed through LDS with their payload (a 4-byte value, or a 16-byte
+// record) so that each digit's run leaves as one contiguous write.  The
+// next tile's keys and payloads are loaded while this one is ranked and
+// written (register double buffer: two wavefronts per SIMD with records;
+// reading the payload with its own tile instead, at three, was 3 % slower).
+template <class PAY>
+__device__ __forceinline__ void downsweep_tiles(uint64_t beg, uint64_t end, uint32_t shift,
+                                                const uint32_t* __restrict__ kin, uint32_t* __restrict__ kout,
+                                                const PAY* __restrict__ pin, PAY* __restrict__ pout, DownLds& S) {
     const int t = threadIdx.x, w = t / kWave, l = lane_id();
-    {
-        // digit base = sum of the totals of the smaller digits (kBlock == kRadix)
-        const uint32_t tot_d = a.totals[t];
-        const uint32_t inc = wave_incl_scan(tot_d);
-        if (l == kWave - 1) s_tmp[w] = inc;
-        __syncthreads();
-        uint32_t base = inc - tot_d;
-        for (int v = 0; v < w; ++v) base += s_tmp[v];
-        s_run[t] = base + a.counts[(size_t)t * a.G + bid];
-    }
-    __syncthreads();
-
-    // the next tile's keys and values are loaded while this one is ranked
-    // and written (register double buffer)
-    uint32_t nkey[kRsItems], nval[kRsItems];
-    auto load_tile = [&](uint64_t tile) {
+    PAY* s_pay = reinterpret_cast<PAY*>(S.pay);
+    uint32_t nkey[kRsItems];
+    PAY npay[kRsItems];
+    auto load_keys = [&](uint64_t tile) {
 #pragma unroll
         for (int j = 0; j < kRsItems; ++j) {
             const uint64_t i = tile + (uint64_t)w * (kRsItems * kWave) + (uint64_t)j * kWave + l;
             nkey[j] = i < end ? kin[i] : 0u;
-            nval[j] = i < end ? vin[i] : 0u;
+            npay[j] = i < end ? pin[i] : PAY{};
         }
     };
-    if (beg < end) load_tile(beg);
+    if (beg < end) load_keys(beg);
     for (uint64_t tile = beg; tile < end; tile += kRsTile) {
-        uint32_t key[kRsItems], val[kRsItems], pos[kRsItems];
+        uint32_t key[kRsItems], pos[kRsItems];
+        PAY pay[kRsItems];
         bool ok[kRsItems];
 #pragma unroll
         for (int j = 0; j < kRsItems; ++j) {
             key[j] = nkey[j];
-            val[j] = nval[j];
+            pay[j] = npay[j];
         }
-        if (tile + kRsTile < end) load_tile(tile + kRsTile);
-        for (int i = t; i < kWavesPerBlock * kRadix; i += kBlock) (&s_wcnt[0][0])[i] = 0;
+        if (tile + kRsTile < end) load_keys(tile + kRsTile);
+        for (int i = t; i < kWavesPerBlock * kRadix; i += kBlock) (&S.wcnt[0][0])[i] = 0;
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kRsItems; ++j) {
@@ -647,10 +630,10 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortSet set) {
                 const uint64_t b = __ballot((d >> bit) & 1u);
                 peers &= ((d >> bit) & 1u) ? b : ~b;
             }
-            const uint32_t before = s_wcnt[w][d];
+            const uint32_t before = S.wcnt[w][d];
             wave_sync();
             pos[j] = before + (uint32_t)__popcll(peers & lanemask_lt());
-            if (ok[j] && (peers & lanemask_lt()) == 0) s_wcnt[w][d] = before + (uint32_t)__popcll(peers);
+            if (ok[j] && (peers & lanemask_lt()) == 0) S.wcnt[w][d] = before + (uint32_t)__popcll(peers);
             wave_sync();
         }
         __syncthreads();
@@ -659,30 +642,31 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortSet set) {
         for (int d = t; d < kRadix; d += kBlock) {
             uint32_t acc = 0;
             for (int v = 0; v < kWavesPerBlock; ++v) {
-                const uint32_t c = s_wcnt[v][d];
-                s_wcnt[v][d] = acc;
+                const uint32_t c = S.wcnt[v][d];
+                S.wcnt[v][d] = acc;
                 acc += c;
             }
-            s_tot[d] = acc;
+            S.tot[d] = acc;
             tot = acc;
         }
         // exclusive scan of the 256 digit totals (kBlock == kRadix)
         {
             uint32_t inc = wave_incl_scan(tot);
-            if (l == kWave - 1) s_tmp[w] = inc;
+            if (l == kWave - 1) S.tmp[w] = inc;
             __syncthreads();
             uint32_t add = 0;
-            for (int v = 0; v < w; ++v) add += s_tmp[v];
-            s_lstart[t] = inc - tot + add;
+            for (int v = 0; v < w; ++v) add += S.tmp[v];
+            S.lstart[t] = inc - tot + add;
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kRsItems; ++j) {
-            if (!ok[j]) continue;
-            const uint32_t d = (key[j] >> shift) & 0xFFu;
-            const uint32_t lp = s_lstart[d] + s_wcnt[w][d] + pos[j];
-            s_key[lp] = key[j];
-            s_val[lp] = val[j];
+            if (ok[j]) {
+                const uint32_t d = (key[j] >> shift) & 0xFFu;
+                const uint32_t lp = S.lstart[d] + S.wcnt[w][d] + pos[j];
+                S.key[lp] = key[j];
+                s_pay[lp] = pay[j];
+            }
         }
         __syncthreads();
         const uint32_t cnt = (uint32_t)((end - tile) < (uint64_t)kRsTile ? (end - tile) : kRsTile);
@@ -690,16 +674,60 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortSet set) {
         for (int j = 0; j < kRsItems; ++j) {
             const uint32_t idx = (uint32_t)(j * kBlock + t);
             if (idx < cnt) {
-                const uint32_t k = s_key[idx];
+                const uint32_t k = S.key[idx];
                 const uint32_t d = (k >> shift) & 0xFFu;
-                const uint32_t g = s_run[d] + (idx - s_lstart[d]);
+                const uint32_t g = S.run[d] + (idx - S.lstart[d]);
                 kout[g] = k;
-                vout[g] = s_val[idx];
+                pout[g] = s_pay[idx];
             }
         }
         __syncthreads();
-        for (int d = t; d < kRadix; d += kBlock) s_run[d] += s_tot[d];
+        for (int d = t; d < kRadix; d += kBlock) S.run[d] += S.tot[d];
         __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortSet set) {
+    // sort 0 takes the first s[0].G workgroups, sort 1 the next s[1].G
+    const uint32_t g0 = (uint32_t)set.s[0].G;
+    const int q = blockIdx.x < g0 ? 0 : 1;
+    if (q >= set.n) return;
+    const SortArgs a = sort_of(set, q);
+    const uint32_t bid = blockIdx.x - (q ? g0 : 0u);
+    if (bid >= (uint32_t)a.G) return;
+    const GridPlan P = *a.plan;
+    if (!rs_active(P, a)) return;
+    const uint32_t n = a.count_is_T ? P.nT : P.nB;
+    const uint32_t* __restrict__ kin = pick2(a.keys[0], a.keys[1], (uint32_t)a.pass);
+    uint32_t* __restrict__ kout = pick2(a.keys[0], a.keys[1], (uint32_t)a.pass + 1u);
+    const uint32_t shift = 8u * (uint32_t)a.pass;
+
+    __shared__ DownLds S;
+
+    uint32_t chunk;
+    rs_chunk(n, a.G, &chunk);
+    const uint64_t beg = (uint64_t)bid * chunk;
+    uint64_t end = beg + chunk;
+    if (end > n) end = n;
+    const int t = threadIdx.x, w = t / kWave, l = lane_id();
+    {
+        // digit base = sum of the totals of the smaller digits (kBlock == kRadix)
+        const uint32_t tot_d = a.totals[t];
+        const uint32_t inc = wave_incl_scan(tot_d);
+        if (l == kWave - 1) S.tmp[w] = inc;
+        __syncthreads();
+        uint32_t base = inc - tot_d;
+        for (int v = 0; v < w; ++v) base += S.tmp[v];
+        S.run[t] = base + a.counts[(size_t)t * a.G + bid];
+    }
+    __syncthreads();
+    if (a.rec[0]) {
+        const int passes = a.count_is_T ? (int)P.passes_T : (int)P.passes;
+        downsweep_tiles<float4>(beg, end, shift, kin, kout, rec_after(a.rec[0], a.rec[1], passes, a.pass - 1),
+                                rec_after(a.rec[0], a.rec[1], passes, a.pass), S);
+    } else {
+        downsweep_tiles<uint32_t>(beg, end, shift, kin, kout, pick2(a.vals[0], a.vals[1], (uint32_t)a.pass),
+                                  pick2(a.vals[0], a.vals[1], (uint32_t)a.pass + 1u), S);
     }
 }
 
@@ -806,10 +834,22 @@ __device__ __forceinline__ void gather(const GatherArgs& a, uint32_t bid, uint32
         for (uint32_t c = bid * kBlock + threadIdx.x; c <= nc; c += stride) a.cell_start[c] = 0;
         return;
     }
-    // kGatherItems ions per thread in flight: the position reads are random
     const uint64_t st64 = stride;
     uint32_t distinct = 0;
-    for (uint64_t p0 = (uint64_t)bid * kBlock + threadIdx.x; p0 < nB; p0 += st64 * kGatherItems) {
+    if (!a.xyz) {
+        // the records are in place: cell offsets from the sorted keys only
+        for (uint64_t pp = (uint64_t)bid * kBlock + threadIdx.x; pp < nB; pp += st64) {
+            const uint32_t p = (uint32_t)pp;
+            const uint32_t c = key[p];
+            const uint32_t cprev = p == 0 ? 0u : key[p - 1] + 1u;
+            for (uint32_t q = cprev; q <= c; ++q) a.cell_start[q] = p;
+            distinct += cprev <= c ? 1u : 0u;   // the first record of its cell
+            if (p == nB - 1)
+                for (uint32_t q = c + 1; q <= nc; ++q) a.cell_start[q] = nB;
+        }
+    }
+    // kGatherItems ions per thread in flight: the position reads are random
+    for (uint64_t p0 = (uint64_t)bid * kBlock + threadIdx.x; a.xyz && p0 < nB; p0 += st64 * kGatherItems) {
         uint32_t id[kGatherItems];
         float x[kGatherItems], y[kGatherItems], z[kGatherItems];
 #pragma unroll

@@ -86,14 +86,16 @@ struct CompactArgs {
     uint32_t* bsel;         // [nB] or NULL (neighbours = all ions)
     int32_t sel_union;      // as CountArgs::sel_union
     // sort keys written with the lists (plan from k_plan; NULL keys: none):
-    // targets (block-raster key, list position), neighbours (cell id, ion index)
+    // targets (block-raster key, list position), neighbours (cell id and
+    // their 16-byte record (x, y, z, ion index) into the record buffer that
+    // the sort's passes start from, see SortArgs::rec)
     const GridPlan* plan;
     const float* xyz;
     const double* zscale;   // NULL: unscaled
     uint32_t* tkeys;
     uint32_t* tvals;
     uint32_t* bkeys;
-    uint32_t* bvals;
+    float4* brec[2];
 };
 
 struct KeyArgs {
@@ -116,7 +118,17 @@ struct SortArgs {
     uint32_t* vals[2];
     uint32_t* counts;       // [256][G]
     uint32_t* totals;       // [256]
+    // records instead of values (rec[0] non-NULL): the 16-byte neighbour
+    // records travel with their keys; the buffers alternate so that the
+    // last active pass writes rec[0] (rec_after)
+    float4* rec[2] = {nullptr, nullptr};
 };
+
+// the record buffer that holds the data after pass p of `passes` (p = -1:
+// what the passes start from), so that the last pass ends in rec0
+__host__ __device__ inline float4* rec_after(float4* rec0, float4* rec1, int passes, int p) {
+    return ((passes - 1 - p) & 1) ? rec1 : rec0;
+}
 
 // One radix pass of up to two independent sorts in the same launches: sort
 // 0 takes the first s[0].G workgroups, sort 1 the next s[1].G (the scan: 256
@@ -143,6 +155,8 @@ struct OrderArgs {
     uint32_t* t_cell_start;
 };
 
+// (xyz NULL: the records are already in bpos, sorted with their keys; only
+// the cell offsets and the occupied-cell count are written)
 struct GatherArgs {
     const GridPlan* plan;
     const float* xyz;
