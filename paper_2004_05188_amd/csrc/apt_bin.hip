@@ -837,15 +837,35 @@ __device__ __forceinline__ void gather(const GatherArgs& a, uint32_t bid, uint32
     const uint64_t st64 = stride;
     uint32_t distinct = 0;
     if (!a.xyz) {
-        // the records are in place: cell offsets from the sorted keys only
-        for (uint64_t pp = (uint64_t)bid * kBlock + threadIdx.x; pp < nB; pp += st64) {
-            const uint32_t p = (uint32_t)pp;
-            const uint32_t c = key[p];
-            const uint32_t cprev = p == 0 ? 0u : key[p - 1] + 1u;
-            for (uint32_t q = cprev; q <= c; ++q) a.cell_start[q] = p;
-            distinct += cprev <= c ? 1u : 0u;   // the first record of its cell
-            if (p == nB - 1)
-                for (uint32_t q = c + 1; q <= nc; ++q) a.cell_start[q] = nB;
+        // the records are in place: cell offsets from the sorted keys only,
+        // eight consecutive keys per thread (two 16-byte loads and the key
+        // before them)
+        constexpr uint32_t kRun = 8;
+        const uint64_t n_runs = ((uint64_t)nB + kRun - 1) / kRun;
+        for (uint64_t r = (uint64_t)bid * kBlock + threadIdx.x; r < n_runs; r += st64) {
+            const uint32_t p0 = (uint32_t)(r * kRun);
+            uint32_t k[kRun];
+            if (p0 + kRun <= nB) {
+                const uint4 v0 = *reinterpret_cast<const uint4*>(key + p0);
+                const uint4 v1 = *reinterpret_cast<const uint4*>(key + p0 + 4);
+                k[0] = v0.x; k[1] = v0.y; k[2] = v0.z; k[3] = v0.w;
+                k[4] = v1.x; k[5] = v1.y; k[6] = v1.z; k[7] = v1.w;
+            } else {
+#pragma unroll
+                for (uint32_t u = 0; u < kRun; ++u) k[u] = p0 + u < nB ? key[p0 + u] : 0u;
+            }
+            uint32_t prev = p0 == 0 ? 0u : key[p0 - 1] + 1u;   // first cell this run may open
+#pragma unroll
+            for (uint32_t u = 0; u < kRun; ++u) {
+                const uint32_t p = p0 + u;
+                if (p >= nB) break;
+                const uint32_t c = k[u];
+                for (uint32_t q = prev; q <= c; ++q) a.cell_start[q] = p;
+                distinct += prev <= c ? 1u : 0u;   // the first record of its cell
+                if (p == nB - 1)
+                    for (uint32_t q = c + 1; q <= nc; ++q) a.cell_start[q] = nB;
+                prev = c + 1u;
+            }
         }
     }
     // kGatherItems ions per thread in flight: the position reads are random
