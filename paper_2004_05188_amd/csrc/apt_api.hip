@@ -165,9 +165,7 @@ static uint32_t cell_cap_for(int64_t n) {
     return (uint32_t)c;
 }
 static int sort_passes_max(uint32_t cap) {
-    int p = 1;
-    while (p < 4 && ((cap - 1u) >> (8 * p)) != 0u) ++p;
-    return p;
+    return sort_passes_for(cap - 1u);
 }
 constexpr int kSortBlocks = 1024;   // most workgroups of a radix pass (the counts matrix is sized for it)
 // Workgroups of a radix pass over at most n keys: fewer, fuller ones for
@@ -464,7 +462,7 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
         ss.n = 2;
         const int grid = GsT + Gs;
         hipLaunchKernelGGL(k_rs_upsweep, dim3(grid), dim3(kBlock), 0, st, ss);
-        hipLaunchKernelGGL(k_rs_scan, dim3(256 * ss.n), dim3(kBlock), 0, st, ss);
+        hipLaunchKernelGGL(k_rs_scan, dim3(kRadix * ss.n), dim3(kBlock), 0, st, ss);
         hipLaunchKernelGGL(k_rs_downsweep, dim3(grid), dim3(kBlock), 0, st, ss);
     }
     // targets in cell order and the neighbour records, in one launch;
@@ -801,7 +799,7 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
                                pw.rs_totals};
             ss.n = 1;
             hipLaunchKernelGGL(k_rs_upsweep, dim3(Gs), dim3(kBlock), 0, st, ss);
-            hipLaunchKernelGGL(k_rs_scan, dim3(256), dim3(kBlock), 0, st, ss);
+            hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kBlock), 0, st, ss);
             hipLaunchKernelGGL(k_rs_downsweep, dim3(Gs), dim3(kBlock), 0, st, ss);
         }
         GatherArgs ga{pw.plan, cl->xyz, nullptr, {pw.K[0], pw.K[1]}, {pw.V[0], pw.V[1]}, pw.bpos, pw.cell_start,

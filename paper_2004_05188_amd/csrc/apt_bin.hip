@@ -241,9 +241,12 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
     // needle the pair kernel took 10 % less time at 0.7x the edge); take it
     // for large neighbour sets (below 2^25 neighbours the finer grid's
     // binning cost more than it saved: +2 % on the 7.7e6-ion needle) when
-    // its cell ids fit the same number of bytes, so that the binning runs
-    // no extra radix pass (at 2e8 ions the extra pass cost more)
-    if (pp.h_shrink > 0.0f && !tiles && totB >= (1u << 25) && h < 3.0e38) {
+    // its cell ids need no more radix passes (at 2e8 ions the extra pass
+    // cost more).  Not in mode 3: there the neighbour-major RDF and the
+    // binning of fewer cells gain more at the larger edge than the per-lane
+    // kNN loses (2e9-ion needle, Sc -> any: 189 ms per step at 1.0 nm, 196
+    // ms at 0.7 nm)
+    if (pp.h_shrink > 0.0f && !tiles && P.tile_mode != 3 && totB >= (1u << 25) && h < 3.0e38) {
         const double h2 = fmax((double)pp.h_min * (double)pp.h_shrink, cbrt(occ / rho));
         if (h2 < h && h2 >= 1e-6 * (emax + 1.0)) {
             auto cells_of = [&](double hh) {
@@ -252,13 +255,11 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
                 for (int ax = 0; ax < 3; ++ax) c *= floor(ext[ax] / hf) + 1.0;
                 return c;
             };
-            auto bytes_of = [](double c) {   // bytes of the largest cell id, c - 1
-                int b = 1;
-                while (b < 4 && c - 1.0 >= ldexp(1.0, 8 * b)) ++b;
-                return b;
-            };
+            // (both counts are at most cell_cap here: exact in u64)
             const double c1 = cells_of(h), c2 = cells_of(h2);
-            if (c2 <= (double)pp.cell_cap && bytes_of(c2) == bytes_of(c1)) h = h2;
+            if (c2 <= (double)pp.cell_cap &&
+                sort_passes_for((uint64_t)c2 - 1u) == sort_passes_for((uint64_t)c1 - 1u))
+                h = h2;
         }
     }
     P.h = (float)h;
@@ -271,30 +272,29 @@ __global__ __launch_bounds__(1024) void k_plan(PlanArgs a) {
     P.n_cells = (uint32_t)ncell;
     P.nT = totT;
     P.nB = totB;
-    uint32_t passes = 1;
-    while (passes < 4 && ((P.n_cells - 1u) >> (8u * passes)) != 0u) ++passes;
+    const uint32_t passes = (uint32_t)sort_passes_for(P.n_cells - 1u);
     P.passes = passes;
-    // targets in block-raster order when its keys need no more bytes than
-    // the largest cell id the workspace allows (the radix passes launched
-    // for both sorts), else in cell order
+    P.bits = key_bits(P.n_cells - 1u);
+    // targets in block-raster order when its keys fit 32 bits and need no
+    // more passes than the largest cell id the workspace allows (the radix
+    // passes launched for both sorts), else in cell order
     {
         const uint64_t nbx = ((uint64_t)P.dim[0] + 7) / 8, nby = ((uint64_t)P.dim[1] + 7) / 8,
                        nbz = ((uint64_t)P.dim[2] + 7) / 8;
         const uint64_t kmax = nbx * nby * nbz * 512u - 1u;
-        uint32_t cap_bytes = 1;
-        while (cap_bytes < 4 && ((pp.cell_cap - 1u) >> (8u * cap_bytes)) != 0u) ++cap_bytes;
+        const int cap_passes = sort_passes_for(pp.cell_cap - 1u);
         // (mode 3 looks targets up by cell: plain cell order)
-        if (P.tile_mode != 3 && kmax < (1ull << (8u * cap_bytes))) {
+        if (P.tile_mode != 3 && kmax <= 0xFFFFFFFFull && sort_passes_for(kmax) <= cap_passes) {
             P.tblock = 8;
             P.nbx = (int32_t)nbx;
             P.nby = (int32_t)nby;
-            uint32_t pt = 1;
-            while (pt < 4 && (kmax >> (8u * pt)) != 0u) ++pt;
-            P.passes_T = pt;
+            P.passes_T = (uint32_t)sort_passes_for(kmax);
+            P.bits_T = key_bits(kmax);
         } else {
             P.tblock = 1;
             P.nbx = P.nby = 0;
             P.passes_T = passes;
+            P.bits_T = P.bits;
         }
     }
     // (x - lo) * inv_h in FP32 misplaces a point by at most ~3 ulps of the
@@ -448,14 +448,16 @@ __global__ __launch_bounds__(kBlock) void k_keys(KeyArgs a) {
 }
 
 // ------------------------------------------------------------------------
-// 5. LSD radix sort of (cell id, value) pairs, 8-bit digits, stable.
+// 5. LSD radix sort of (cell id, value) pairs, kDigitBits per pass, stable.
 //    Block b sorts its chunk tile by tile; digits of a tile are ranked
 //    inside each wavefront with ballots, then placed through LDS so that
 //    the global writes of one digit are contiguous.
 // ------------------------------------------------------------------------
-constexpr int kRsItems = 8;
-constexpr int kRsTile = kBlock * kRsItems;   // 2048
-constexpr int kRadix = 256;
+// 11 keys per thread: the most whose double buffer (below) stays within 256
+// VGPRs, two wavefronts per SIMD; longer digit runs than at 8 (2e9 ions:
+// binning 132 -> 128 ms)
+constexpr int kRsItems = 11;
+constexpr int kRsTile = kBlock * kRsItems;   // 2816
 constexpr int kRsUp = 8;                     // keys per thread in flight in the upsweep
 constexpr int kGatherItems = 4;              // random position reads per thread in flight
 constexpr int kOrderItems = 2;               // the same for the (fewer) targets
@@ -516,7 +518,9 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortSet set) {
     uint64_t end = beg + chunk;
     if (end > n) end = n;
     const int w = threadIdx.x / kWave;
-    const uint32_t shift = 8u * (uint32_t)a.pass;
+    uint32_t shift, mask;
+    pass_digit(a.count_is_T ? P.bits_T : P.bits, a.count_is_T ? P.passes_T : P.passes, (uint32_t)a.pass, &shift,
+               &mask);
     // kRsUp independent coalesced loads in flight per thread before the
     // LDS counts (one load at a time leaves the pass latency-bound)
     for (uint64_t i0 = beg + threadIdx.x; i0 < end; i0 += (uint64_t)kBlock * kRsUp) {
@@ -528,7 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortSet set) {
         }
 #pragma unroll
         for (int u = 0; u < kRsUp; ++u)
-            if (i0 + (uint64_t)u * kBlock < end) atomicAdd(&s_h[w][(k[u] >> shift) & 0xFFu], 1u);
+            if (i0 + (uint64_t)u * kBlock < end) atomicAdd(&s_h[w][(k[u] >> shift) & mask], 1u);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < kRadix; d += kBlock) {
@@ -540,7 +544,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortSet set) {
 
 // Row scan of the digit counts: workgroup d turns counts[d][0..G) into
 // exclusive prefixes within the row and writes the row total to totals[d].
-// The downsweep adds the digit bases (a scan of the 256 totals).
+// The downsweep adds the digit bases (a scan of the kRadix totals).
 __global__ __launch_bounds__(kBlock) void k_rs_scan(SortSet set) {
     const int q = blockIdx.x / kRadix;
     if (q >= set.n) return;
@@ -591,7 +595,7 @@ struct DownLds {
 // written (register double buffer: two wavefronts per SIMD with records;
 // reading the payload with its own tile instead, at three, was 3 % slower).
 template <class PAY>
-__device__ __forceinline__ void downsweep_tiles(uint64_t beg, uint64_t end, uint32_t shift,
+__device__ __forceinline__ void downsweep_tiles(uint64_t beg, uint64_t end, uint32_t shift, uint32_t mask,
                                                 const uint32_t* __restrict__ kin, uint32_t* __restrict__ kout,
                                                 const PAY* __restrict__ pin, PAY* __restrict__ pout, DownLds& S) {
     const int t = threadIdx.x, w = t / kWave, l = lane_id();
@@ -623,10 +627,10 @@ __device__ __forceinline__ void downsweep_tiles(uint64_t beg, uint64_t end, uint
         for (int j = 0; j < kRsItems; ++j) {
             const uint64_t i = tile + (uint64_t)w * (kRsItems * kWave) + (uint64_t)j * kWave + l;
             ok[j] = i < end;
-            const uint32_t d = (key[j] >> shift) & 0xFFu;
+            const uint32_t d = (key[j] >> shift) & mask;
             uint64_t peers = __ballot(ok[j]);
 #pragma unroll
-            for (int bit = 0; bit < 8; ++bit) {
+            for (int bit = 0; bit < kDigitBits; ++bit) {
                 const uint64_t b = __ballot((d >> bit) & 1u);
                 peers &= ((d >> bit) & 1u) ? b : ~b;
             }
@@ -649,20 +653,20 @@ __device__ __forceinline__ void downsweep_tiles(uint64_t beg, uint64_t end, uint
             S.tot[d] = acc;
             tot = acc;
         }
-        // exclusive scan of the 256 digit totals (kBlock == kRadix)
+        // exclusive scan of the digit totals (thread t < kRadix: digit t)
         {
             uint32_t inc = wave_incl_scan(tot);
             if (l == kWave - 1) S.tmp[w] = inc;
             __syncthreads();
             uint32_t add = 0;
             for (int v = 0; v < w; ++v) add += S.tmp[v];
-            S.lstart[t] = inc - tot + add;
+            if (t < kRadix) S.lstart[t] = inc - tot + add;
         }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kRsItems; ++j) {
             if (ok[j]) {
-                const uint32_t d = (key[j] >> shift) & 0xFFu;
+                const uint32_t d = (key[j] >> shift) & mask;
                 const uint32_t lp = S.lstart[d] + S.wcnt[w][d] + pos[j];
                 S.key[lp] = key[j];
                 s_pay[lp] = pay[j];
@@ -675,7 +679,7 @@ __device__ __forceinline__ void downsweep_tiles(uint64_t beg, uint64_t end, uint
             const uint32_t idx = (uint32_t)(j * kBlock + t);
             if (idx < cnt) {
                 const uint32_t k = S.key[idx];
-                const uint32_t d = (k >> shift) & 0xFFu;
+                const uint32_t d = (k >> shift) & mask;
                 const uint32_t g = S.run[d] + (idx - S.lstart[d]);
                 kout[g] = k;
                 pout[g] = s_pay[idx];
@@ -700,7 +704,9 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortSet set) {
     const uint32_t n = a.count_is_T ? P.nT : P.nB;
     const uint32_t* __restrict__ kin = pick2(a.keys[0], a.keys[1], (uint32_t)a.pass);
     uint32_t* __restrict__ kout = pick2(a.keys[0], a.keys[1], (uint32_t)a.pass + 1u);
-    const uint32_t shift = 8u * (uint32_t)a.pass;
+    uint32_t shift, mask;
+    pass_digit(a.count_is_T ? P.bits_T : P.bits, a.count_is_T ? P.passes_T : P.passes, (uint32_t)a.pass, &shift,
+               &mask);
 
     __shared__ DownLds S;
 
@@ -711,22 +717,22 @@ __global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortSet set) {
     if (end > n) end = n;
     const int t = threadIdx.x, w = t / kWave, l = lane_id();
     {
-        // digit base = sum of the totals of the smaller digits (kBlock == kRadix)
-        const uint32_t tot_d = a.totals[t];
+        // digit base = sum of the totals of the smaller digits (thread t < kRadix: digit t)
+        const uint32_t tot_d = t < kRadix ? a.totals[t] : 0u;
         const uint32_t inc = wave_incl_scan(tot_d);
         if (l == kWave - 1) S.tmp[w] = inc;
         __syncthreads();
         uint32_t base = inc - tot_d;
         for (int v = 0; v < w; ++v) base += S.tmp[v];
-        S.run[t] = base + a.counts[(size_t)t * a.G + bid];
+        if (t < kRadix) S.run[t] = base + a.counts[(size_t)t * a.G + bid];
     }
     __syncthreads();
     if (a.rec[0]) {
         const int passes = a.count_is_T ? (int)P.passes_T : (int)P.passes;
-        downsweep_tiles<float4>(beg, end, shift, kin, kout, rec_after(a.rec[0], a.rec[1], passes, a.pass - 1),
+        downsweep_tiles<float4>(beg, end, shift, mask, kin, kout, rec_after(a.rec[0], a.rec[1], passes, a.pass - 1),
                                 rec_after(a.rec[0], a.rec[1], passes, a.pass), S);
     } else {
-        downsweep_tiles<uint32_t>(beg, end, shift, kin, kout, pick2(a.vals[0], a.vals[1], (uint32_t)a.pass),
+        downsweep_tiles<uint32_t>(beg, end, shift, mask, kin, kout, pick2(a.vals[0], a.vals[1], (uint32_t)a.pass),
                                   pick2(a.vals[0], a.vals[1], (uint32_t)a.pass + 1u), S);
     }
 }

@@ -4,6 +4,38 @@
 
 namespace apt {
 
+// LSD radix sort of cell ids and target keys: the fewest passes of at most
+// kDigitBits each, the key's bits split evenly over them.  A narrower digit
+// has fewer values, so each tile's run of one digit is longer and leaves as
+// a longer contiguous write (on 2e9 ions, 28-bit cell ids: four passes of 7
+// bits bin in 121 ms, of 8, 8, 8 and 4 bits in 132 ms).
+constexpr int kDigitBits = 8;
+constexpr int kRadix = 1 << kDigitBits;
+static_assert(kRadix <= kBlock, "one thread per digit in the sort's scans");
+
+// bits of max_key (0 for 0)
+__host__ __device__ inline uint32_t key_bits(uint64_t max_key) {
+    uint32_t b = 0;
+    while (b < 64 && (max_key >> b) != 0u) ++b;
+    return b;
+}
+
+// passes that sort keys in [0, max_key]
+__host__ __device__ inline int sort_passes_for(uint64_t max_key) {
+    const uint32_t b = key_bits(max_key);
+    return b == 0 ? 1 : (int)((b + kDigitBits - 1) / kDigitBits);
+}
+
+// the digit of pass `pass` over keys of `bits` bits sorted in `passes`
+// passes: (key >> shift) & mask; the lower passes take the odd bits
+__host__ __device__ inline void pass_digit(uint32_t bits, uint32_t passes, uint32_t pass, uint32_t* shift,
+                                           uint32_t* mask) {
+    const uint32_t base = bits / passes, extra = bits % passes;
+    *shift = pass * base + (pass < extra ? pass : extra);
+    const uint32_t width = base + (pass < extra ? 1u : 0u);
+    *mask = (1u << width) - 1u;
+}
+
 // What a call zeroes or fills before its work: status word, output
 // histograms, target count, counters, squared bin edges (any may be NULL).
 struct InitArgs {

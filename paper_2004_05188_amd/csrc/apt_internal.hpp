@@ -28,6 +28,8 @@ struct GridPlan {
     uint32_t nB;        // neighbour ions
     uint32_t passes;    // active radix passes over the cell ids (neighbours)
     uint32_t passes_T;  // active radix passes over the target keys
+    uint32_t bits;      // bits of the largest cell id (the radix digits split them)
+    uint32_t bits_T;    // bits of the largest target key
     int32_t tblock;     // targets are ordered by blocks of tblock^3 cells (8), or by cell (1)
     int32_t nbx, nby;   // blocks per axis (x, y)
     float eps;          // culling margin covering FP32 cell-assignment error (nm)
