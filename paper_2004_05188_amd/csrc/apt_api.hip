@@ -463,7 +463,7 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
         const int grid = GsT + Gs;
         hipLaunchKernelGGL(k_rs_upsweep, dim3(grid), dim3(kBlock), 0, st, ss);
         hipLaunchKernelGGL(k_rs_scan, dim3(kRadix * ss.n), dim3(kBlock), 0, st, ss);
-        hipLaunchKernelGGL(k_rs_downsweep, dim3(grid), dim3(kBlock), 0, st, ss);
+        hipLaunchKernelGGL(k_rs_downsweep, dim3(grid), dim3(kDsBlock), 0, st, ss);
     }
     // targets in cell order and the neighbour records, in one launch;
     // occupied cells (distinct sorted keys) feed the kNN radii
@@ -800,7 +800,7 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
             ss.n = 1;
             hipLaunchKernelGGL(k_rs_upsweep, dim3(Gs), dim3(kBlock), 0, st, ss);
             hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kBlock), 0, st, ss);
-            hipLaunchKernelGGL(k_rs_downsweep, dim3(Gs), dim3(kBlock), 0, st, ss);
+            hipLaunchKernelGGL(k_rs_downsweep, dim3(Gs), dim3(kDsBlock), 0, st, ss);
         }
         GatherArgs ga{pw.plan, cl->xyz, nullptr, {pw.K[0], pw.K[1]}, {pw.V[0], pw.V[1]}, pw.bpos, pw.cell_start,
                       nullptr};

@@ -453,11 +453,14 @@ __global__ __launch_bounds__(kBlock) void k_keys(KeyArgs a) {
 //    inside each wavefront with ballots, then placed through LDS so that
 //    the global writes of one digit are contiguous.
 // ------------------------------------------------------------------------
-// 11 keys per thread: the most whose double buffer (below) stays within 256
-// VGPRs, two wavefronts per SIMD; longer digit runs than at 8 (2e9 ions:
-// binning 132 -> 128 ms)
-constexpr int kRsItems = 11;
-constexpr int kRsTile = kBlock * kRsItems;   // 2816
+// Tiles of 512 x 14 keys (with 16-byte records, 151 KB of LDS: one
+// workgroup per CU): the longer a tile, the longer each digit's run in it
+// and the write that carries the run (2e9 ions, 28-bit cell ids in four
+// 7-bit passes: binning 117 ms with tiles of 256 x 11 keys, 105 ms with
+// 512 x 11, 103 ms with 512 x 14).
+constexpr int kRsItems = 14;
+constexpr int kDsWaves = kDsBlock / kWave;
+constexpr int kRsTile = kDsBlock * kRsItems;
 constexpr int kRsUp = 8;                     // keys per thread in flight in the upsweep
 constexpr int kGatherItems = 4;              // random position reads per thread in flight
 constexpr int kOrderItems = 2;               // the same for the (fewer) targets
@@ -581,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scan(SortSet set) {
 struct DownLds {
     uint32_t key[kRsTile];
     float4 pay[kRsTile];                 // values (as u32) or records
-    uint32_t wcnt[kWavesPerBlock][kRadix];
+    uint32_t wcnt[kDsWaves][kRadix];
     uint32_t lstart[kRadix];
     uint32_t tot[kRadix];
     uint32_t run[kRadix];
@@ -591,9 +594,10 @@ struct DownLds {
 // One workgroup's tiles: keys ranked by digit with ballots per wavefront,
 // placed through LDS with their payload (a 4-byte value, or a 16-byte
 // record) so that each digit's run leaves as one contiguous write.  The
-// next tile's keys and payloads are loaded while this one is ranked and
-// written (register double buffer: two wavefronts per SIMD with records;
-// reading the payload with its own tile instead, at three, was 3 % slower).
+// next tile's keys are loaded while this one is ranked and written; the
+// payloads are loaded at the start of their own tile and wait in registers
+// through the ranking (loading them a tile ahead too took the registers of
+// three more keys per thread and was no faster).
 template <class PAY>
 __device__ __forceinline__ void downsweep_tiles(uint64_t beg, uint64_t end, uint32_t shift, uint32_t mask,
                                                 const uint32_t* __restrict__ kin, uint32_t* __restrict__ kout,
@@ -601,13 +605,11 @@ __device__ __forceinline__ void downsweep_tiles(uint64_t beg, uint64_t end, uint
     const int t = threadIdx.x, w = t / kWave, l = lane_id();
     PAY* s_pay = reinterpret_cast<PAY*>(S.pay);
     uint32_t nkey[kRsItems];
-    PAY npay[kRsItems];
     auto load_keys = [&](uint64_t tile) {
 #pragma unroll
         for (int j = 0; j < kRsItems; ++j) {
             const uint64_t i = tile + (uint64_t)w * (kRsItems * kWave) + (uint64_t)j * kWave + l;
             nkey[j] = i < end ? kin[i] : 0u;
-            npay[j] = i < end ? pin[i] : PAY{};
         }
     };
     if (beg < end) load_keys(beg);
@@ -618,10 +620,11 @@ __device__ __forceinline__ void downsweep_tiles(uint64_t beg, uint64_t end, uint
 #pragma unroll
         for (int j = 0; j < kRsItems; ++j) {
             key[j] = nkey[j];
-            pay[j] = npay[j];
+            const uint64_t i = tile + (uint64_t)w * (kRsItems * kWave) + (uint64_t)j * kWave + l;
+            pay[j] = i < end ? pin[i] : PAY{};
         }
         if (tile + kRsTile < end) load_keys(tile + kRsTile);
-        for (int i = t; i < kWavesPerBlock * kRadix; i += kBlock) (&S.wcnt[0][0])[i] = 0;
+        for (int i = t; i < kDsWaves * kRadix; i += kDsBlock) (&S.wcnt[0][0])[i] = 0;
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kRsItems; ++j) {
@@ -643,9 +646,9 @@ __device__ __forceinline__ void downsweep_tiles(uint64_t beg, uint64_t end, uint
         __syncthreads();
         // per-digit totals of the tile and wave prefixes
         uint32_t tot = 0;
-        for (int d = t; d < kRadix; d += kBlock) {
+        for (int d = t; d < kRadix; d += kDsBlock) {
             uint32_t acc = 0;
-            for (int v = 0; v < kWavesPerBlock; ++v) {
+            for (int v = 0; v < kDsWaves; ++v) {
                 const uint32_t c = S.wcnt[v][d];
                 S.wcnt[v][d] = acc;
                 acc += c;
@@ -676,7 +679,7 @@ __device__ __forceinline__ void downsweep_tiles(uint64_t beg, uint64_t end, uint
         const uint32_t cnt = (uint32_t)((end - tile) < (uint64_t)kRsTile ? (end - tile) : kRsTile);
 #pragma unroll
         for (int j = 0; j < kRsItems; ++j) {
-            const uint32_t idx = (uint32_t)(j * kBlock + t);
+            const uint32_t idx = (uint32_t)(j * kDsBlock + t);
             if (idx < cnt) {
                 const uint32_t k = S.key[idx];
                 const uint32_t d = (k >> shift) & mask;
@@ -686,12 +689,12 @@ __device__ __forceinline__ void downsweep_tiles(uint64_t beg, uint64_t end, uint
             }
         }
         __syncthreads();
-        for (int d = t; d < kRadix; d += kBlock) S.run[d] += S.tot[d];
+        for (int d = t; d < kRadix; d += kDsBlock) S.run[d] += S.tot[d];
         __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_rs_downsweep(SortSet set) {
+__global__ __launch_bounds__(kDsBlock) void k_rs_downsweep(SortSet set) {
     // sort 0 takes the first s[0].G workgroups, sort 1 the next s[1].G
     const uint32_t g0 = (uint32_t)set.s[0].G;
     const int q = blockIdx.x < g0 ? 0 : 1;

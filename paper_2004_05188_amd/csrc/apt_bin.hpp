@@ -12,6 +12,7 @@ namespace apt {
 constexpr int kDigitBits = 8;
 constexpr int kRadix = 1 << kDigitBits;
 static_assert(kRadix <= kBlock, "one thread per digit in the sort's scans");
+constexpr int kDsBlock = 512;   // threads of a downsweep workgroup (kRadix <= kDsBlock)
 
 // bits of max_key (0 for 0)
 __host__ __device__ inline uint32_t key_bits(uint64_t max_key) {
