@@ -173,6 +173,17 @@ constexpr int kSortBlocks = 1024;   // most workgroups of a radix pass (the coun
 // 7.7 M-ion needle 512 bin 2 % faster than 1024, on 2e8 ions 1024 win).
 static int sort_blocks(int64_t n) { return n <= ((int64_t)1 << 25) ? 512 : kSortBlocks; }
 
+// One radix pass of the sorts in `ss` (grid: their workgroups) over a cloud
+// of n ions: upsweep, scan, and the downsweep whose tile suits the size.
+static void launch_sort_pass(SortSet& ss, int grid, int64_t n, hipStream_t st) {
+    const bool large = n > ((int64_t)1 << 25);
+    ss.tile = large ? kDsLargeBlock * kDsLargeItems : kDsSmallBlock * kDsSmallItems;
+    hipLaunchKernelGGL(k_rs_upsweep, dim3(grid), dim3(kBlock), 0, st, ss);
+    hipLaunchKernelGGL(k_rs_scan, dim3(kRadix * ss.n), dim3(kBlock), 0, st, ss);
+    if (large) hipLaunchKernelGGL(k_rs_downsweep_large, dim3(grid), dim3(kDsLargeBlock), 0, st, ss);
+    else hipLaunchKernelGGL(k_rs_downsweep_small, dim3(grid), dim3(kDsSmallBlock), 0, st, ss);
+}
+
 // Workspace of the plain path (rdf / knn / knn_rdf).
 struct PlainWs {
     GridPlan* plan;
@@ -460,10 +471,7 @@ static apt_status run_binning(const apt_cloud* cl, apt_query q, const PlanParams
         ss.s[1] = SortArgs{w.plan, 0, p, Gs, {w.KB[0], w.KB[1]}, {nullptr, nullptr},
                            w.rs_counts + (size_t)256 * kSortBlocks, w.rs_totals + 256, {w.bpos, w.brec2}};
         ss.n = 2;
-        const int grid = GsT + Gs;
-        hipLaunchKernelGGL(k_rs_upsweep, dim3(grid), dim3(kBlock), 0, st, ss);
-        hipLaunchKernelGGL(k_rs_scan, dim3(kRadix * ss.n), dim3(kBlock), 0, st, ss);
-        hipLaunchKernelGGL(k_rs_downsweep, dim3(grid), dim3(kDsBlock), 0, st, ss);
+        launch_sort_pass(ss, GsT + Gs, n, st);
     }
     // targets in cell order and the neighbour records, in one launch;
     // occupied cells (distinct sorted keys) feed the kNN radii
@@ -798,9 +806,7 @@ static apt_status run_batched(const apt_cloud* cl, const apt_query* pairs, int32
             ss.s[0] = SortArgs{pw.plan, 0, p, Gs, {pw.K[0], pw.K[1]}, {pw.V[0], pw.V[1]}, pw.rs_counts,
                                pw.rs_totals};
             ss.n = 1;
-            hipLaunchKernelGGL(k_rs_upsweep, dim3(Gs), dim3(kBlock), 0, st, ss);
-            hipLaunchKernelGGL(k_rs_scan, dim3(kRadix), dim3(kBlock), 0, st, ss);
-            hipLaunchKernelGGL(k_rs_downsweep, dim3(Gs), dim3(kDsBlock), 0, st, ss);
+            launch_sort_pass(ss, Gs, n, st);
         }
         GatherArgs ga{pw.plan, cl->xyz, nullptr, {pw.K[0], pw.K[1]}, {pw.V[0], pw.V[1]}, pw.bpos, pw.cell_start,
                       nullptr};

@@ -453,14 +453,6 @@ __global__ __launch_bounds__(kBlock) void k_keys(KeyArgs a) {
 //    inside each wavefront with ballots, then placed through LDS so that
 //    the global writes of one digit are contiguous.
 // ------------------------------------------------------------------------
-// Tiles of 512 x 14 keys (with 16-byte records, 151 KB of LDS: one
-// workgroup per CU): the longer a tile, the longer each digit's run in it
-// and the write that carries the run (2e9 ions, 28-bit cell ids in four
-// 7-bit passes: binning 117 ms with tiles of 256 x 11 keys, 105 ms with
-// 512 x 11, 103 ms with 512 x 14).
-constexpr int kRsItems = 14;
-constexpr int kDsWaves = kDsBlock / kWave;
-constexpr int kRsTile = kDsBlock * kRsItems;
 constexpr int kRsUp = 8;                     // keys per thread in flight in the upsweep
 constexpr int kGatherItems = 4;              // random position reads per thread in flight
 constexpr int kOrderItems = 2;               // the same for the (fewer) targets
@@ -495,9 +487,10 @@ __device__ __forceinline__ SortArgs sort_of(const SortSet& set, int q) {
 template <typename T>
 __device__ __forceinline__ T pick2(T p0, T p1, uint32_t bit) { return (bit & 1u) ? p1 : p0; }
 
-__device__ __forceinline__ void rs_chunk(uint32_t n, int G, uint32_t* chunk) {
+// workgroup b of G sorts keys [b chunk, (b + 1) chunk): whole tiles
+__device__ __forceinline__ void rs_chunk(uint32_t n, int G, uint32_t tile, uint32_t* chunk) {
     uint32_t c = (n + (uint32_t)G - 1u) / (uint32_t)G;
-    *chunk = (c + kRsTile - 1u) / kRsTile * kRsTile;
+    *chunk = (c + tile - 1u) / tile * tile;
 }
 
 __global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortSet set) {
@@ -516,7 +509,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_upsweep(SortSet set) {
     for (int i = threadIdx.x; i < kWavesPerBlock * kRadix; i += kBlock) (&s_h[0][0])[i] = 0;
     __syncthreads();
     uint32_t chunk;
-    rs_chunk(n, a.G, &chunk);
+    rs_chunk(n, a.G, (uint32_t)set.tile, &chunk);
     const uint64_t beg = (uint64_t)bid * chunk;
     uint64_t end = beg + chunk;
     if (end > n) end = n;
@@ -580,11 +573,12 @@ __global__ __launch_bounds__(kBlock) void k_rs_scan(SortSet set) {
     if (t == kBlock - 1) a.totals[d] = run;
 }
 
-// LDS of one downsweep workgroup
+// LDS of one downsweep workgroup of BLOCK threads, ITEMS keys each
+template <int BLOCK, int ITEMS>
 struct DownLds {
-    uint32_t key[kRsTile];
-    float4 pay[kRsTile];                 // values (as u32) or records
-    uint32_t wcnt[kDsWaves][kRadix];
+    uint32_t key[BLOCK * ITEMS];
+    float4 pay[BLOCK * ITEMS];           // values (as u32) or records
+    uint32_t wcnt[BLOCK / kWave][kRadix];
     uint32_t lstart[kRadix];
     uint32_t tot[kRadix];
     uint32_t run[kRadix];
@@ -598,10 +592,12 @@ struct DownLds {
 // payloads are loaded at the start of their own tile and wait in registers
 // through the ranking (loading them a tile ahead too took the registers of
 // three more keys per thread and was no faster).
-template <class PAY>
+template <class PAY, int BLOCK, int ITEMS>
 __device__ __forceinline__ void downsweep_tiles(uint64_t beg, uint64_t end, uint32_t shift, uint32_t mask,
                                                 const uint32_t* __restrict__ kin, uint32_t* __restrict__ kout,
-                                                const PAY* __restrict__ pin, PAY* __restrict__ pout, DownLds& S) {
+                                                const PAY* __restrict__ pin, PAY* __restrict__ pout,
+                                                DownLds<BLOCK, ITEMS>& S) {
+    constexpr int kRsItems = ITEMS, kDsBlock = BLOCK, kDsWaves = BLOCK / kWave, kRsTile = BLOCK * ITEMS;
     const int t = threadIdx.x, w = t / kWave, l = lane_id();
     PAY* s_pay = reinterpret_cast<PAY*>(S.pay);
     uint32_t nkey[kRsItems];
@@ -694,7 +690,8 @@ __device__ __forceinline__ void downsweep_tiles(uint64_t beg, uint64_t end, uint
     }
 }
 
-__global__ __launch_bounds__(kDsBlock) void k_rs_downsweep(SortSet set) {
+template <int BLOCK, int ITEMS>
+__device__ __forceinline__ void downsweep_body(const SortSet& set) {
     // sort 0 takes the first s[0].G workgroups, sort 1 the next s[1].G
     const uint32_t g0 = (uint32_t)set.s[0].G;
     const int q = blockIdx.x < g0 ? 0 : 1;
@@ -711,10 +708,10 @@ __global__ __launch_bounds__(kDsBlock) void k_rs_downsweep(SortSet set) {
     pass_digit(a.count_is_T ? P.bits_T : P.bits, a.count_is_T ? P.passes_T : P.passes, (uint32_t)a.pass, &shift,
                &mask);
 
-    __shared__ DownLds S;
+    __shared__ DownLds<BLOCK, ITEMS> S;
 
     uint32_t chunk;
-    rs_chunk(n, a.G, &chunk);
+    rs_chunk(n, a.G, (uint32_t)(BLOCK * ITEMS), &chunk);
     const uint64_t beg = (uint64_t)bid * chunk;
     uint64_t end = beg + chunk;
     if (end > n) end = n;
@@ -738,6 +735,17 @@ __global__ __launch_bounds__(kDsBlock) void k_rs_downsweep(SortSet set) {
         downsweep_tiles<uint32_t>(beg, end, shift, mask, kin, kout, pick2(a.vals[0], a.vals[1], (uint32_t)a.pass),
                                   pick2(a.vals[0], a.vals[1], (uint32_t)a.pass + 1u), S);
     }
+}
+
+// (each kernel runs only with the tile its upsweep cut the chunks for)
+__global__ __launch_bounds__(kDsLargeBlock) void k_rs_downsweep_large(SortSet set) {
+    if (set.tile != kDsLargeBlock * kDsLargeItems) return;
+    downsweep_body<kDsLargeBlock, kDsLargeItems>(set);
+}
+
+__global__ __launch_bounds__(kDsSmallBlock) void k_rs_downsweep_small(SortSet set) {
+    if (set.tile != kDsSmallBlock * kDsSmallItems) return;
+    downsweep_body<kDsSmallBlock, kDsSmallItems>(set);
 }
 
 // ------------------------------------------------------------------------

@@ -12,7 +12,17 @@ namespace apt {
 constexpr int kDigitBits = 8;
 constexpr int kRadix = 1 << kDigitBits;
 static_assert(kRadix <= kBlock, "one thread per digit in the sort's scans");
-constexpr int kDsBlock = 512;   // threads of a downsweep workgroup (kRadix <= kDsBlock)
+
+// Downsweep tiles: 512 threads x 14 keys for large sorts (with 16-byte
+// records, 151 KB of LDS: one workgroup per CU), 256 x 8 for small ones,
+// whose few tiles per workgroup then still fill two workgroups per CU.  The
+// longer a tile, the longer each digit's run in it and the write that
+// carries the run (2e9 ions, 28-bit cell ids in four 7-bit passes: binning
+// 117 ms with tiles of 256 x 11 keys, 105 ms with 512 x 11, 103 ms with
+// 512 x 14; the 7.7e6-ion needle bins 0.85 ms per step with 512 x 14 and
+// 0.75 ms with 256 x 8).
+constexpr int kDsLargeBlock = 512, kDsLargeItems = 14;
+constexpr int kDsSmallBlock = 256, kDsSmallItems = 8;
 
 // bits of max_key (0 for 0)
 __host__ __device__ inline uint32_t key_bits(uint64_t max_key) {
@@ -169,6 +179,7 @@ __host__ __device__ inline float4* rec_after(float4* rec0, float4* rec1, int pas
 struct SortSet {
     SortArgs s[2];
     int32_t n;
+    int32_t tile;   // keys per downsweep tile (the passes' chunks are whole tiles)
 };
 
 struct OrderArgs {
@@ -256,7 +267,8 @@ __global__ void k_compact(CompactArgs a);
 __global__ void k_keys(KeyArgs a);
 __global__ void k_rs_upsweep(SortSet a);
 __global__ void k_rs_scan(SortSet a);
-__global__ void k_rs_downsweep(SortSet a);
+__global__ void k_rs_downsweep_large(SortSet a);   // kDsLargeBlock threads
+__global__ void k_rs_downsweep_small(SortSet a);   // kDsSmallBlock threads
 __global__ void k_gather(GatherArgs a);
 // the target order (first g_order workgroups) and the neighbour gather (the
 // rest) in one launch: they read and write disjoint arrays
