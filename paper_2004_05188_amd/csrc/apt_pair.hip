@@ -399,9 +399,10 @@ size_t nbr_lds_bytes(int n_bins, bool hist_in_lds) {
     return b + (size_t)kWavesPerBlock * kNbrList * sizeof(float4);
 }
 
-// (at most 64 VGPRs: eight wavefronts per SIMD)
+// (at most 72 VGPRs: seven wavefronts per SIMD; at eight, 64 VGPRs with
+// three spilled, the 2e9-ion needle's launch took 3 % longer)
 template <int FLAGS>
-__global__ __launch_bounds__(kBlock, 8) void k_rdf_nbr(PairArgs a) {
+__global__ __launch_bounds__(kBlock, 7) void k_rdf_nbr(PairArgs a) {
     constexpr bool COUNT = (FLAGS & kCountEvals) != 0;
     constexpr bool LDS_HIST = !COUNT && (FLAGS & kRdfLds) != 0;
     const GridPlan P = *a.plan;

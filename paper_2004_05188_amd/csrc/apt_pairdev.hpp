@@ -388,8 +388,10 @@ __device__ __forceinline__ void run_tile(const GridPlan& P, const PairTask& T, b
 // no staging, and no lane waits on a shared candidate list.  Same results as
 // run_tile (same candidate set, order-free updates).  With rdf_on false only
 // the kNN keys within Rk are taken (a small radius when the neighbours are
-// dense: a few dozen records per lane).
-constexpr int kLaneU = 4;
+// dense: a few dozen records per lane).  Eight records in flight per lane
+// (2e9-ion needle, 1.0 nm cells: 23.4 ms with four, 22.4 with eight, 34
+// with two; sixteen spill).
+constexpr int kLaneU = 8;
 
 template <int FLAGS, int KMAX>
 __device__ __forceinline__ void run_lane(const GridPlan& P, const PairTask& T, bool valid, float px, float py,
