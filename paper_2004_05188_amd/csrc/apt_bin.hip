@@ -859,8 +859,12 @@ __device__ __forceinline__ void gather(const GatherArgs& a, uint32_t bid, uint32
         // before them)
         constexpr uint32_t kRun = 8;
         const uint64_t n_runs = ((uint64_t)nB + kRun - 1) / kRun;
-        for (uint64_t r = (uint64_t)bid * kBlock + threadIdx.x; r < n_runs; r += st64) {
-            const uint32_t p0 = (uint32_t)(r * kRun);
+        // (every lane of a wavefront takes the same iterations: the long
+        // runs of cells below are written by all of its lanes together)
+        const uint64_t r_wave = (uint64_t)bid * kBlock + (threadIdx.x & ~(uint32_t)(kWave - 1));
+        for (uint64_t rb = r_wave; rb < n_runs; rb += st64) {
+            const uint64_t r = rb + (uint64_t)lane_id();
+            const uint32_t p0 = r < n_runs ? (uint32_t)(r * kRun) : nB;
             uint32_t k[kRun];
             if (p0 + kRun <= nB) {
                 const uint4 v0 = *reinterpret_cast<const uint4*>(key + p0);
@@ -871,17 +875,49 @@ __device__ __forceinline__ void gather(const GatherArgs& a, uint32_t bid, uint32
 #pragma unroll
                 for (uint32_t u = 0; u < kRun; ++u) k[u] = p0 + u < nB ? key[p0 + u] : 0u;
             }
-            uint32_t prev = p0 == 0 ? 0u : key[p0 - 1] + 1u;   // first cell this run may open
+            uint32_t prev = (p0 == 0 || p0 >= nB) ? 0u : key[p0 - 1] + 1u;   // first cell this run may open
 #pragma unroll
             for (uint32_t u = 0; u < kRun; ++u) {
                 const uint32_t p = p0 + u;
-                if (p >= nB) break;
-                const uint32_t c = k[u];
-                for (uint32_t q = prev; q <= c; ++q) a.cell_start[q] = p;
-                distinct += prev <= c ? 1u : 0u;   // the first record of its cell
-                if (p == nB - 1)
+                const bool in = p < nB;
+                const uint32_t c = in ? k[u] : 0u;
+                // cells [prev, c] start at record p; the last record also
+                // closes cells (c, nc] at nB.  Runs of up to kShort cells are
+                // written by their lane, longer ones (empty cells around the
+                // specimen) by the whole wavefront, 64 consecutive cells per
+                // store
+                uint32_t q0 = prev, q1 = c, v = p;
+                bool open = in && prev <= c;
+                distinct += open ? 1u : 0u;   // the first record of its cell
+                constexpr uint32_t kShort = 4;
+                bool tail = in && p == nB - 1 && c < nc;
+                if (open && c - prev < kShort) {
+                    for (uint32_t q = prev; q <= c; ++q) a.cell_start[q] = p;
+                    open = false;
+                }
+                if (tail && nc - c <= kShort) {
                     for (uint32_t q = c + 1; q <= nc; ++q) a.cell_start[q] = nB;
-                prev = c + 1u;
+                    tail = false;
+                }
+                for (int pass = 0; pass < 2; ++pass) {
+                    const bool mine = pass == 0 ? open : tail;
+                    if (pass == 1) {
+                        q0 = c + 1u;
+                        q1 = nc;
+                        v = nB;
+                    }
+                    uint64_t m = __ballot(mine);
+                    while (m) {
+                        const int s = __builtin_ctzll(m);
+                        m &= m - 1;
+                        const uint32_t s0 = (uint32_t)__shfl((int)q0, s, kWave);
+                        const uint32_t s1 = (uint32_t)__shfl((int)q1, s, kWave);
+                        const uint32_t sv = (uint32_t)__shfl((int)v, s, kWave);
+                        for (uint32_t q = s0 + (uint32_t)lane_id(); q <= s1 && q >= s0; q += kWave)
+                            a.cell_start[q] = sv;
+                    }
+                }
+                if (in) prev = c + 1u;
             }
         }
     }
