@@ -399,10 +399,9 @@ size_t nbr_lds_bytes(int n_bins, bool hist_in_lds) {
     return b + (size_t)kWavesPerBlock * kNbrList * sizeof(float4);
 }
 
-// (at most 72 VGPRs: seven wavefronts per SIMD; at eight, 64 VGPRs with
-// three spilled, the 2e9-ion needle's launch took 3 % longer)
+// (at most 64 VGPRs: eight wavefronts per SIMD)
 template <int FLAGS>
-__global__ __launch_bounds__(kBlock, 7) void k_rdf_nbr(PairArgs a) {
+__global__ __launch_bounds__(kBlock, 8) void k_rdf_nbr(PairArgs a) {
     constexpr bool COUNT = (FLAGS & kCountEvals) != 0;
     constexpr bool LDS_HIST = !COUNT && (FLAGS & kRdfLds) != 0;
     const GridPlan P = *a.plan;
@@ -458,19 +457,21 @@ __global__ __launch_bounds__(kBlock, 7) void k_rdf_nbr(PairArgs a) {
             const uint32_t row_sel = readlane(crow, __builtin_ctzll(todo));
             const bool fin = fin0 && crow == row_sel;
             todo &= ~__ballot(fin);
-            // bounding box of the part's records
-            float x0 = fin ? rec.x : INFINITY, y0 = fin ? rec.y : INFINITY, z0 = fin ? rec.z : INFINITY;
-            float x1 = fin ? rec.x : -INFINITY, y1 = fin ? rec.y : -INFINITY, z1 = fin ? rec.z : -INFINITY;
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) {
-                x0 = fminf(x0, __shfl_xor(x0, d, kWave));
-                y0 = fminf(y0, __shfl_xor(y0, d, kWave));
-                z0 = fminf(z0, __shfl_xor(z0, d, kWave));
-                x1 = fmaxf(x1, __shfl_xor(x1, d, kWave));
-                y1 = fmaxf(y1, __shfl_xor(y1, d, kWave));
-                z1 = fmaxf(z1, __shfl_xor(z1, d, kWave));
-            }
-            const uint32_t n_rec = (uint32_t)__popcll(__ballot(fin));
+            // a box holding the part's records: its cells (one cell row; the
+            // records are in cell order, so its first and last lanes hold its
+            // lowest and highest x cell), widened by the FP32 margin of the
+            // cells' assignment and bounds.  (Six lane reductions for the
+            // exact box cost more VALU than the slightly larger box's extra
+            // candidates.)
+            const uint64_t pm = __ballot(fin);
+            const int cxv = fin ? cell_axis(P, 0, rec.x) : 0;
+            const int cxa = readlane(cxv, __builtin_ctzll(pm));
+            const int cxb = readlane(cxv, 63 - __builtin_clzll(pm));
+            const int cyr = (int)(row_sel % (uint32_t)P.dim[1]), czr = (int)(row_sel / (uint32_t)P.dim[1]);
+            const float x0 = P.lo[0] + (float)cxa * P.h - P.eps, x1 = P.lo[0] + (float)(cxb + 1) * P.h + P.eps;
+            const float y0 = P.lo[1] + (float)cyr * P.h - P.eps, y1 = P.lo[1] + (float)(cyr + 1) * P.h + P.eps;
+            const float z0 = P.lo[2] + (float)czr * P.h - P.eps, z1 = P.lo[2] + (float)(czr + 1) * P.h + P.eps;
+            const uint32_t n_rec = (uint32_t)__popcll(pm);
             // every staged target against the 64 records
             auto run = [&](int cnt) {
                 if (COUNT) {
