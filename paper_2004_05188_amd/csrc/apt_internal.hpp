@@ -80,14 +80,20 @@ __device__ __forceinline__ T readlane(T v, int lane) {
     return __builtin_bit_cast(T, r);
 }
 
+// Inclusive prefix sum over the wavefront with DPP moves (no LDS): shifts
+// by 1, 2, 4 and 8 lanes within each row of 16 (lanes shifted in from
+// outside the row add 0), then the last lane of rows 0 and 2 added to rows 1
+// and 3 (row_bcast:15) and the last lane of row 1 to rows 2 and 3
+// (row_bcast:31).
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const int l = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t o = __shfl_up(v, d, kWave);
-        if (l >= d) v += o;
-    }
-    return v;
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15, rows 1 and 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31, rows 2 and 3
+    return (uint32_t)x;
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
