@@ -44,9 +44,9 @@ K, R_MAX, N_BINS, KB_RMAX, KB_NBINS = 10, 2.0, 200, 5.0, 5000
 # plain-copy calibration; valid only for the kernel sources they were taken
 # on (the summaries under profiles/)
 PAIR_TRAFFIC = {
-    # profiles/counters_frustum2g.md: FETCH_SIZE 16 327 460.5 KiB x 2.0 +
+    # profiles/counters_frustum2g.md: FETCH_SIZE 16 314 537.1 KiB x 2.0 +
     # WRITE_SIZE 74 091.3 KiB per k_rdf_nbr<1> launch
-    ("frustum2g", "k_rdf_nbr"): (33_513_663_428, "9628ab48e6092295"),
+    ("frustum2g", "k_rdf_nbr"): (33_487_197_757, "3dec29db6eee67cd"),
 }
 PAIR_SOURCES = ("apt_pair.hip", "apt_pair.hpp", "apt_pairdev.hpp", "apt_internal.hpp", "apt_bin.hpp")
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X: 256 CU x 2.4 GHz x 256 FLOP/clk (packed FMA)
