@@ -1,9 +1,12 @@
 """Full-scale parity: the 2e9-ion needle (Sc -> any species, kNN k = 10 and
-RDF to 2 nm, d_srf = 2 nm) on one GPU, checked on sampled outputs.
+RDF to 2 nm, d_srf = 2 nm) on one GPU, checked on sampled outputs; the same
+check first on the needle scaled to 2e8 ions (the same density and
+chemistry: the large-cloud radix tiles and the dense-neighbour mode at a
+tenth of the cost).
 
 The oracle cannot take the whole cloud, so three z-slabs of 4 nm and 200
-randomly placed 12 nm cubes (about 1e5 targets, checked by brute force)
-serve as samples.  Their ions are collected while the cloud is generated
+randomly placed 12 nm cubes (about 1e5 targets, checked by brute force;
+40 cubes of 8 nm at 2e8 ions) serve as samples.  Their ions are collected while the cloud is generated
 chunk by chunk into HBM; each sample with a 3 nm halo on every side is a
 sub-cloud whose only eligible targets are the sample's own (the halo covers
 r_max and every k-th neighbour distance, which is asserted).
@@ -44,39 +47,49 @@ def _say(msg):
         pass
 
 
+def test_midscale_needle_2e8(orc, synth):
+    _check_needle(orc, synth, synth.frustum200m(), n_cubes=40, free_gib=40, min_targets=1_000_000,
+                  min_cube_targets=4_000, cube=8.0)
+
+
 def test_fullscale_needle_2e9(orc, synth):
+    _check_needle(orc, synth, synth.frustum2g(), n_cubes=N_CUBES, free_gib=200, min_targets=10_000_000,
+                  min_cube_targets=90_000)
+
+
+def _check_needle(orc, synth, spec, n_cubes, free_gib, min_targets, min_cube_targets, cube=CUBE):
     import torch
 
     import paper_2004_05188_amd as aptstat
 
     assert torch.cuda.is_available()
     free, total = torch.cuda.mem_get_info()
-    if free < 200 * 2**30:
-        pytest.skip(f"needs about 200 GiB of free HBM, {free / 2**30:.0f} GiB free")
-    spec = synth.frustum2g()
+    if free < free_gib * 2**30:
+        pytest.skip(f"needs about {free_gib} GiB of free HBM, {free / 2**30:.0f} GiB free")
     H = spec.H
     z0s = [0.06 * H, 0.5 * H, 0.93 * H]
     cores = [(np.float32(z), np.float32(z + SLAB)) for z in z0s]
     picks = [[] for _ in z0s]
-    # random cubes: cells of a lattice of (CUBE + 2 HALO) nm whose cube lies
+    # random cubes: cells of a lattice of (cube + 2 HALO) nm whose cube lies
     # inside the needle at least 2 nm from its surface and clear of the slabs
     # with their halos
-    L = CUBE + 2 * HALO
+    L = cube + 2 * HALO
     rng = np.random.default_rng(2004)
     R0, R1 = spec.R0, spec.R1
     cand = []
     for kz in range(int(H // L)):
         zlo = kz * L + HALO
-        if any(zlo + CUBE > a - 2 * HALO and zlo < b + 2 * HALO for a, b in cores):
+        if any(zlo + cube > a - 2 * HALO and zlo < b + 2 * HALO for a, b in cores):
             continue
-        r_top = R0 + (R1 - R0) * (zlo + CUBE) / H - 2.0 - CUBE * 1.75
+        r_top = R0 + (R1 - R0) * (zlo + cube) / H - 2.0 - cube * 1.75
         n_xy = int(r_top // L)
         for kx in range(-n_xy, n_xy):
             for ky in range(-n_xy, n_xy):
                 c = np.array([(kx + 0.5) * L, (ky + 0.5) * L])
-                if np.hypot(*c) + CUBE < r_top:
+                if np.hypot(*c) + cube < r_top:
                     cand.append((kx, ky, kz))
-    chosen = [cand[i] for i in rng.choice(len(cand), size=N_CUBES, replace=False)]
+    assert len(cand) >= n_cubes
+    chosen = [cand[i] for i in rng.choice(len(cand), size=n_cubes, replace=False)]
     # lattice cells -> cube number (-1: not a sample), looked up by the
     # ions' cell indices (a cube lies HALO inside its cell, so FP32 floors
     # near cell faces never matter for it)
@@ -116,7 +129,7 @@ def test_fullscale_needle_2e9(orc, synth):
         q = table_d[k[:, 2].clamp(0, table.shape[0] - 1), (k[:, 1] + OFF).clamp(0, 2 * OFF - 1),
                     (k[:, 0] + OFF).clamp(0, 2 * OFF - 1)]
         lo = (k * int(L) + int(HALO)).to(torch.float32)
-        core = ((v >= lo) & (v < lo + CUBE)).all(dim=1)
+        core = ((v >= lo) & (v < lo + cube)).all(dim=1)
         return q, core
 
     cube_picks = [[] for _ in chosen]
@@ -140,7 +153,7 @@ def test_fullscale_needle_2e9(orc, synth):
     torch.cuda.synchronize()
     assert int(r.status.item()) == 0
     nt = int(r.n_targets.item())
-    assert nt > 10_000_000
+    assert nt > min_targets
     gtid = r.target_id[:nt].cpu().numpy()
     assert np.all(np.diff(gtid) > 0)
 
@@ -202,7 +215,7 @@ def test_fullscale_needle_2e9(orc, synth):
         lo = cube_lo(c).astype(np.float32)
         core = np.ones(len(gid), bool)
         for ax in range(3):
-            core &= (xyz[:, ax] >= lo[ax]) & (xyz[:, ax] < np.float32(np.float64(lo[ax]) + CUBE))
+            core &= (xyz[:, ax] >= lo[ax]) & (xyz[:, ax] < np.float32(np.float64(lo[ax]) + cube))
         d_o = np.where(core, d, np.float32(-np.inf)).astype(np.float32)
         o_rdf += orc.rdf(xyz, lab, d_o, SC, ANY, D_SRF, R_MAX, N_BINS)
         tid, dist, nid, kh = orc.knn(xyz, lab, d_o, SC, ANY, D_SRF, K, np.inf, KB_RMAX, KB_NBINS, method="brute")
@@ -219,7 +232,7 @@ def test_fullscale_needle_2e9(orc, synth):
         assert np.all(np.abs(g_dist - dist) <= 1e-6 * dist), f"kNN distances differ in cube {q}"
         cube_checked += len(tid)
     _say(f"fullscale: {checked} slab targets and {cube_checked} cube targets' kNN rows checked")
-    assert cube_checked >= 90_000
+    assert cube_checked >= min_cube_targets
     checked += cube_checked
     assert int(rs.n_targets.item()) == checked
     assert np.array_equal(g_rdf, o_rdf), f"RDF differs in {np.count_nonzero(g_rdf != o_rdf)} bins"
