@@ -191,6 +191,28 @@ def sdm_timing(aptstat, torch, cloud, ws, reps=5):
             "pairs_per_s_kernel": pairs / (k_ms / 1e3) if k_ms > 0 else None}
 
 
+def knn100_timing(aptstat, torch, cloud, ws, reps=5):
+    """kNN with k = 100 (and the RDF to 2 nm, the k-th distance histogram at
+    0.001 nm) of the 7.7e6-ion needle's queries Sc -> Sc and Sc -> Al
+    (d_srf = 1 nm): ms per call and target ions per second."""
+    out = {"workload": "frustum7m", "k": 100, "d_srf_nm": 1.0, "r_max_nm": R_MAX, "queries": {}}
+    for name, (A, B) in (("Sc->Sc", (SC, SC)), ("Sc->Al", (SC, AL))):
+        r = aptstat.knn_rdf(cloud, A, B, 1.0, 100, r_max=R_MAX, n_bins=N_BINS, kb_rmax=KB_RMAX,
+                            kb_nbins=KB_NBINS, ws=ws)
+        torch.cuda.synchronize()
+        assert int(r.status.item()) == 0
+        nt = int(r.n_targets.item())
+        outs = (r.target_id, r.dist, r.nbr_id, r.knn_hist, r.n_targets, r.status, r.rdf_hist)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            aptstat.knn_rdf(cloud, A, B, 1.0, 100, r_max=R_MAX, n_bins=N_BINS, capacity=r.target_id.shape[0],
+                            kb_rmax=KB_RMAX, kb_nbins=KB_NBINS, ws=ws, outputs=outs)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out["queries"][name] = {"targets": nt, "ms_per_call": 1e3 * dt, "target_ions_per_s": nt / dt}
+    return out
+
+
 def cluster_timing(aptstat, torch, cloud, ws, reps=3):
     """Maximum-separation clustering of the Sc ions of the 7.7e6-ion needle
     over the d_max sweep of the paper's benchmark task (0.10 to 0.70 nm in
@@ -556,6 +578,8 @@ def main():
                                                 min(args.looped_reps, args.batched_reps))
             log("[bench] two-point statistic on frustum7m")
             line["sdm"] = sdm_timing(aptstat, torch, cloud, ws)
+            log("[bench] kNN k = 100 on frustum7m")
+            line["knn100"] = knn100_timing(aptstat, torch, cloud, ws)
             log("[bench] maximum-separation clustering sweep on frustum7m")
             line["cluster"] = cluster_timing(aptstat, torch, cloud, ws)
             log("[bench] ion-to-edge distancing on frustum7m")
